@@ -1,0 +1,195 @@
+/*
+ * inpaint.h - C ABI of the MI355X (gfx950) homogeneous diffusion inpainting solver.
+ *
+ * Operation (Kaemper, Chizhov, Weickert, "Efficient Parallel Algorithms for
+ * Inpainting-Based Representations of 4K Images - Part I", Section 2.2,
+ * Eq. 2.6):  for each channel solve  A u = b  with  A = C + (I - C) L  and
+ * b = C f, where C = diag(mask) and L is the 5-point negated Laplacian with
+ * reflecting image boundaries (diagonal |N(i)|, -1 per direct neighbour).
+ * Known pixels are Dirichlet data, every other pixel is filled by the discrete
+ * Laplace equation.  The solver is the paper's reduced full multigrid
+ * (Section 4.2) with an optimized restricted additive Schwarz smoother
+ * (Section 3, Algorithm 2) on overlapping blocks, iterated with V-cycles until
+ * the relative residual drops to the requested tolerance.
+ *
+ * Conventions shared by every entry point:
+ *   - Images f and out are planar float32 [channels][H][W], row-major and
+ *     contiguous.  mask is uint8 [H][W] (non-zero = known pixel) and is shared
+ *     by all channels (Section 2.2, "Practical Considerations").
+ *   - A pointer may be device memory (hipMalloc, a torch CUDA tensor) or host
+ *     memory; host buffers are staged through the library's own device
+ *     buffers.  The caller owns f, mask and out; the library never frees them.
+ *   - out == f (the same address) is allowed; any other overlap is rejected.
+ *     Values of f at unknown pixels are never read and may be NaN.
+ *   - Relative residual (Section 5.2, "Stopping Criterion"; the start of the
+ *     decay is not named in the paper, this library uses the zero-filled start
+ *     C f):  rel_res(u) = ||b - A u||_2 / ||b - A C f||_2, in float64 on the
+ *     finest grid, per channel.
+ *   - Guarantees on success: out equals f bit for bit at known pixels, and each
+ *     channel is solved on its own (its result does not depend on the others).
+ *   - Return value: an inpaint_status.  Negative values are errors and leave
+ *     out unspecified; INPAINT_NOT_CONVERGED still writes the last iterate.
+ *     inpaint_last_error() gives a message for the calling thread.
+ *   - All entry points are thread-safe.  Calls that overlap in time on the same
+ *     device use separate workspaces.
+ */
+#ifndef INPAINT_H
+#define INPAINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum inpaint_status {
+  INPAINT_OK = 0,
+  INPAINT_NOT_CONVERGED = 1, /* cycle cap reached; out holds the last iterate */
+  INPAINT_E_INVALID = -1,    /* bad argument, overlapping buffers, non-finite f at a known pixel */
+  INPAINT_E_EMPTY_MASK = -2, /* no known pixel: the system is singular (any constant solves it) */
+  INPAINT_E_NOMEM = -3,      /* device or pinned host allocation failed */
+  INPAINT_E_DEVICE = -4,     /* a HIP runtime call failed */
+  INPAINT_E_DIVERGED = -5    /* the residual became non-finite */
+} inpaint_status;
+
+/* Cycle schedules (Section 4.2).  RFMG is the paper's choice. */
+typedef enum inpaint_schedule {
+  INPAINT_SCHED_RFMG = 0,       /* reduced FMG: coarse-to-fine cascade with one ORAS
+                                   iteration per coarse level, then V-cycles on the finest */
+  INPAINT_SCHED_FMG = 1,        /* full FMG: one V-cycle on every level of the cascade */
+  INPAINT_SCHED_MULTILEVEL = 2, /* cascade, then plain ORAS iterations on the finest */
+  INPAINT_SCHED_SINGLE = 3      /* ORAS iterations on the finest grid only, from C f */
+} inpaint_schedule;
+
+typedef enum inpaint_rhs_restriction {
+  INPAINT_RHS_MODIFIED = 0, /* known children weighted by their free neighbours (Section 4.3) */
+  INPAINT_RHS_NAIVE = 1     /* plain mean of the known children (Section 4.3) */
+} inpaint_rhs_restriction;
+
+/*
+ * Solver options.  Zero-initialise and set struct_size = sizeof(inpaint_opts);
+ * every zero field takes its default.  A NULL opts pointer means all defaults.
+ */
+typedef struct inpaint_opts {
+  int struct_size;     /* sizeof(inpaint_opts) */
+  int block;           /* ORAS block side B: 16 or 32 (default 32, Section 3.1) */
+  int overlap;         /* overlap o in pixels between neighbouring blocks, 2 <= o <= B/2 (default 6) */
+  float gamma;         /* Robin term added per cut block edge, 0 < gamma <= 1 (gamma = 1 is
+                          Dirichlet RAS); the paper leaves alpha open (default 0.5) */
+  float tau;           /* local CG stop: ||rho_i||^2 <= tau * ||r||^2 * |block| / N (default 0.02) */
+  int max_local_iters; /* cap on local CG iterations per block (default 64) */
+  int schedule;        /* inpaint_schedule (default INPAINT_SCHED_RFMG) */
+  int max_cycles;      /* cap on V-cycles (or finest ORAS iterations for MULTILEVEL and
+                          SINGLE); default 30 for RFMG/FMG, 2000 otherwise */
+  int pre_smooth;      /* ORAS iterations before the coarse correction (default 1) */
+  int post_smooth;     /* ORAS iterations after it (default 1) */
+  int rhs_restriction; /* inpaint_rhs_restriction (default MODIFIED) */
+  float coarse_tau;    /* relative stop of the CG solve on the coarsest grid, on squared
+                          norms (default 1e-8) */
+  int coarse_max_iters;/* cap on that solve (default 256) */
+} inpaint_opts;
+
+/* Per-solve statistics (all channels of one problem). */
+typedef struct inpaint_stats {
+  double rel_res;        /* largest relative residual over the channels (float64) */
+  int cycles;            /* V-cycles run (finest ORAS iterations for MULTILEVEL/SINGLE) */
+  int levels;            /* grid levels used */
+  int oras_iters;        /* ORAS iterations over all levels and channels */
+  double local_cg_mean;  /* mean local CG iterations per block solve */
+  int local_cg_max;      /* largest local CG iteration count of any block */
+  float gpu_ms;          /* device time of the solve, from HIP events */
+} inpaint_stats;
+
+/*
+ * Solve one image, synchronously, with default options.
+ *   f     [channels][H][W] float32, host or device
+ *   mask  [H][W] uint8, host or device
+ *   W, H  >= 1;  channels in [1, 4];  tol in (0, 1): target relative residual
+ *   out   [channels][H][W] float32, host or device
+ */
+int inpaint_solve(const float* f, const uint8_t* mask, int W, int H, int channels,
+                  double tol, float* out);
+
+/*
+ * As inpaint_solve, with options, a stream (a hipStream_t passed as void*;
+ * NULL = the null stream) and optional statistics.  Work is issued on that
+ * stream; the call returns after the result is in out (it waits on the stream
+ * once per V-cycle to read the convergence flags).
+ */
+int inpaint_solve_ex(const float* f, const uint8_t* mask, int W, int H, int channels,
+                     double tol, float* out, const inpaint_opts* opts, void* stream,
+                     inpaint_stats* stats);
+
+/*
+ * Relative residual (float64, per channel, see above) of u for the problem
+ * (f, mask).  u, f: [channels][H][W] float32; rel_res_out: channels doubles
+ * (host memory).  Computed on the device.
+ */
+int inpaint_rel_res(const float* u, const float* f, const uint8_t* mask, int W, int H,
+                    int channels, double* rel_res_out);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* inpaint_last_error(void);
+
+/* Library version string. */
+const char* inpaint_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Step-level entry points.  Each runs one step of the method on the device and
+ * returns its result to host buffers, synchronously, so that the step can be
+ * checked on its own.  All pointers are host memory.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Grid hierarchy of the coarse problems (Section 4.3; level rule of Section
+ * 4.4: halve with ceil until both sides are at most `block`).
+ *   levels_out      number of levels L (host int)
+ *   sizes_out       2*L ints: (W_l, H_l) finest first (capacity 2*16 ints)
+ *   masks_out       concatenation over levels of uint8 [H_l][W_l] coarse masks
+ *                   (max pooling of the children), or NULL
+ *   rhs_out         concatenation over levels of float32 [channels][H_l][W_l]
+ *                   known values b_l (0 at unknown pixels), or NULL
+ *   rhs_restriction inpaint_rhs_restriction
+ * Buffers must hold sum_l H_l*W_l (masks) and channels * sum_l H_l*W_l (rhs)
+ * elements; inpaint_hierarchy_size() gives both counts.
+ */
+int inpaint_hierarchy_size(int W, int H, int block, int* levels_out, size_t* pixels_out);
+int inpaint_debug_pyramid(const float* f, const uint8_t* mask, int W, int H, int channels,
+                          int block, int rhs_restriction, int* levels_out, int* sizes_out,
+                          uint8_t* masks_out, float* rhs_out);
+
+/*
+ * One ORAS iteration (Section 3, Algorithm 2) on the finest grid:
+ * r = b - A u_in;  solve A_i v_i = R_i r on every block by local CG;
+ * u_out = u_in + sum_i R_i^T D_i v_i.  u_in must equal f at known pixels.
+ * Block side, overlap, gamma, tau and the CG cap come from opts.
+ * u_in, u_out: [channels][H][W] float32.
+ */
+int inpaint_debug_oras_step(const float* u_in, const float* f, const uint8_t* mask, int W,
+                            int H, int channels, const inpaint_opts* opts, float* u_out);
+
+/*
+ * Residual restriction (Sections 4.1 and 4.4): for each coarse pixel X of a
+ * [ceil(Hf/2)][ceil(Wf/2)] grid, r_c(X) = 4 * mean of the existing fine
+ * children of r_f where mask_c(X) == 0, and 0 where mask_c(X) != 0 (the factor
+ * 4 = (H/h)^2 keeps the integer 5-point stencil on every level).
+ *   r_f [Hf][Wf] float32, mask_c [Hc][Wc] uint8, r_c [Hc][Wc] float32.
+ */
+int inpaint_debug_restrict(const float* r_f, const uint8_t* mask_c, int Wf, int Hf, float* r_c);
+
+/*
+ * Bilinear, cell-centred prolongation (Section 4.4) from a [Hc][Wc] grid with
+ * Hc = ceil(Hf/2), Wc = ceil(Wf/2) to [Hf][Wf]:
+ *   mode 0 (cascade):    u_out = mask_f ? b_f : P u_c
+ *   mode 1 (correction): u_out = u_in + (mask_f ? 0 : P u_c)
+ * u_in may be NULL for mode 0.
+ */
+int inpaint_debug_prolong(const float* u_c, int Wf, int Hf, const uint8_t* mask_f,
+                          const float* b_f, const float* u_in, int mode, float* u_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INPAINT_H */

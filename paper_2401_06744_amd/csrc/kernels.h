@@ -1,0 +1,106 @@
+// Internal declarations shared by the gfx950 kernels and the host driver.
+// Not part of the public ABI (see include/inpaint.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace inpaint {
+
+constexpr int kMaxChannels = 4;
+constexpr int kMaxLevels = 24;
+
+// Tile of the grid passes: 64 columns x 16 rows, 256 threads (4 rows each).
+constexpr int kTileW = 64;
+constexpr int kTileH = 16;
+
+// One grid level as the kernels see it.  Fields are planar per channel with a
+// padded row pitch P (elements); one plane holds H*P elements.
+struct LevelView {
+  int W, H, P;
+  size_t plane;
+  int nbx, nby;  // ORAS blocks along x and y
+  int B, o;      // block side and overlap (stride B - o)
+};
+
+// Per-channel norm reduction target of a grid pass.
+struct NormOut {
+  double* partials;   // [C][ntiles]
+  unsigned* counter;  // [C], left at 0 after every pass
+  double* out;        // [C] squared norm of the residual written by the pass
+  // Optional convergence test on the finest grid (check != 0):
+  const double* den;  // [C] squared norm of the reference residual
+  double* relres;     // [C] sqrt(out / den)
+  int* active;        // [C] set to 0 once relres <= tol
+  double tol;
+  int check;
+};
+
+enum PassMode : int {
+  PASS_RES = 0,    // u_new = u_in (residual only; u_out unused)
+  PASS_UPD = 1,    // u_new = u_in + sum of weighted block corrections
+  PASS_PSOL = 2,   // u_new = mask ? b : P u_c   (cascade prolongation)
+  PASS_PCORR = 3,  // u_new = u_in + (mask ? 0 : P u_c)   (coarse-grid correction)
+};
+
+struct PassArgs {
+  LevelView lv;
+  const uint8_t* c;
+  const float* b;
+  const float* u_in;
+  float* u_out;
+  float* r;
+  const float* contrib;  // PASS_UPD: [C][nby*nbx][B][B]
+  const float* uc;       // PASS_PSOL/PCORR: coarse field [C][Hc][Pc]
+  int Wc, Hc, Pc;
+  size_t planec;
+  NormOut norm;
+  const int* active;     // [C] or nullptr: skip channels already converged
+};
+
+struct BlockArgs {
+  LevelView lv;
+  const uint8_t* c;
+  const float* r;         // residual [C][H][P]
+  const double* snorm;    // [C] squared global residual norm
+  float* contrib;         // [C][nby*nbx][B][B] weighted corrections D_i v_i
+  float gamma, tau;
+  int maxit;
+  const int* active;
+  unsigned long long* cgstat;  // [2]: total local iterations, max, or nullptr
+};
+
+struct CoarseArgs {
+  LevelView lv;  // a single block covers the level
+  const uint8_t* c;
+  const float* b;
+  float* u;      // in/out
+  int init;      // 1: start from u = C b;  0: continue from u
+  float rel_tol; // stop when ||rho||^2 <= rel_tol * ||rho_0||^2
+  int maxit;
+  const int* active;
+  unsigned long long* cgstat;
+};
+
+// Launchers (all enqueue on `s`, return hipError_t of the launch).
+hipError_t launch_stage(const float* f, const uint8_t* mask, int W, int H, int C, int Pf,
+                        LevelView lv, uint8_t* c, float* b, float* u, int* status, hipStream_t s);
+hipError_t launch_mask_down(LevelView fine, const uint8_t* cf, LevelView coarse, uint8_t* cc,
+                            hipStream_t s);
+hipError_t launch_rhs_down(LevelView fine, const uint8_t* cf, const float* bf, LevelView coarse,
+                           const uint8_t* cc, float* bc, int C, int naive, hipStream_t s);
+hipError_t launch_pass(int mode, const PassArgs& a, int C, hipStream_t s);
+hipError_t launch_restrict(LevelView fine, const float* rf, LevelView coarse, const uint8_t* cc,
+                           float* bc, float* uc, float* rc, NormOut norm, const int* active,
+                           int C, hipStream_t s);
+hipError_t launch_block_solve(const BlockArgs& a, int C, hipStream_t s);
+hipError_t launch_coarse_solve(const CoarseArgs& a, int C, hipStream_t s);
+hipError_t launch_output(LevelView lv, const uint8_t* c, const float* b,
+                         const float* const* u_sel, float* out, int Pout, int C, hipStream_t s);
+hipError_t launch_copy_in(const float* src, int W, int H, int C, int Psrc, float* dst, LevelView lv,
+                          hipStream_t s);
+
+size_t pass_tiles(const LevelView& lv);
+
+}  // namespace inpaint

@@ -1,0 +1,682 @@
+// gfx950 kernels of the homogeneous diffusion inpainting solver.
+//
+// Every field is float32, planar per channel with a padded row pitch; the
+// mask is uint8 (1 = known).  Level l uses the integer 5-point stencil
+// h_l^2 L (diagonal = number of in-image neighbours, -1 per neighbour), so the
+// operator of every level is  A_l = C_l + (I - C_l) h_l^2 L_l  and coarse
+// right-hand sides carry the factor (H/h)^2 = 4 (Sections 2.2 and 4.1).
+//
+// Kernels:
+//   stage        b_0 = C f, mask normalised to 0/1, u_0 = C f, input checks
+//   mask_down    coarse mask by max pooling (Section 4.3)
+//   rhs_down     coarse known values, naive or modified (Section 4.3)
+//   pass<MODE>   one fused grid pass: form the new iterate on a 64x16 tile plus
+//                a 1-pixel halo in LDS (ORAS update, cascade prolongation or
+//                coarse-grid correction), write it, write the float64-evaluated
+//                residual and reduce its squared norm per channel
+//   block_solve  the ORAS local problems (Section 3, Algorithm 2, step 2): one
+//                wavefront per block, the block held in registers, plain CG
+//   restrict     coarse right-hand side of the correction problem (Section 4.1)
+//   coarse_solve CG on the single block of the coarsest grid
+//   output       out = mask ? f : u
+#include "kernels.h"
+
+#include <math.h>
+
+namespace inpaint {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kPassThreads = 256;
+
+// ---------------------------------------------------------------------------
+// cross-lane helpers
+// ---------------------------------------------------------------------------
+
+// DPP wave_shr:1 -- lane i receives lane i-1; lane 0 receives 0.
+__device__ __forceinline__ float lane_from_left(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x138, 0xf, 0xf, false));
+}
+// DPP wave_shl:1 -- lane i receives lane i+1; lane 63 receives 0.
+__device__ __forceinline__ float lane_from_right(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x130, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// Sum over the 64 lanes of a fully active wavefront, in a fixed order; the
+// result is uniform.  quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror and
+// row_mirror build 16-lane sums, then the four row sums are added.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_f<0xB1>(v);
+  v += dpp_f<0x4E>(v);
+  v += dpp_f<0x141>(v);
+  v += dpp_f<0x140>(v);
+  return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+// Workgroups are handed to the 8 XCDs round robin; remap so that each XCD
+// works on one contiguous range of tiles and shares halo reads in its L2.
+__device__ __forceinline__ unsigned xcd_remap(unsigned wg, unsigned n) {
+  const unsigned nper = n >> 3, rem = n & 7u;
+  const unsigned xcd = wg & 7u, idx = wg >> 3;
+  return xcd < rem ? xcd * (nper + 1) + idx : rem * (nper + 1) + (xcd - rem) * nper + idx;
+}
+
+// ---------------------------------------------------------------------------
+// staging and output
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_stage(const float* __restrict__ f,
+                                               const uint8_t* __restrict__ mask, int W, int H,
+                                               int C, int Pf, LevelView lv, uint8_t* __restrict__ c,
+                                               float* __restrict__ b, float* __restrict__ u,
+                                               int* __restrict__ status) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  bool bad = false, known = false;
+  if (x < W && y < H) {
+    known = mask[(size_t)y * W + x] != 0;
+    c[(size_t)y * lv.P + x] = known ? 1 : 0;
+    for (int ch = 0; ch < C; ++ch) {
+      float v = known ? f[(size_t)ch * Pf * H + (size_t)y * Pf + x] : 0.0f;
+      bad |= known && !isfinite(v);
+      const size_t o = (size_t)ch * lv.plane + (size_t)y * lv.P + x;
+      b[o] = v;
+      u[o] = v;
+    }
+  }
+  const unsigned long long anybad = __ballot(bad);
+  const unsigned long long anyknown = __ballot(known);
+  if ((threadIdx.x & 63) == 0 && (anybad || anyknown))
+    atomicOr(status, (anybad ? 1 : 0) | (anyknown ? 2 : 0));
+}
+
+__global__ void __launch_bounds__(256) k_output(LevelView lv, const uint8_t* __restrict__ c,
+                                                const float* __restrict__ b, const float* u0,
+                                                const float* u1, const float* u2, const float* u3,
+                                                float* __restrict__ out, int Pout) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int ch = blockIdx.z;
+  if (x >= lv.W || y >= lv.H) return;
+  const float* u = ch == 0 ? u0 : ch == 1 ? u1 : ch == 2 ? u2 : u3;
+  const size_t o = (size_t)y * lv.P + x;
+  const size_t src = (size_t)ch * lv.plane + o;
+  out[(size_t)ch * Pout * lv.H + (size_t)y * Pout + x] = c[o] ? b[src] : u[src];
+}
+
+// ---------------------------------------------------------------------------
+// coarse problems (Section 4.3)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_mask_down(LevelView fl, const uint8_t* __restrict__ cf,
+                                                   LevelView cl, uint8_t* __restrict__ cc) {
+  const int X = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int Y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (X >= cl.W || Y >= cl.H) return;
+  uint8_t m = 0;
+  for (int dy = 0; dy < 2; ++dy)
+    for (int dx = 0; dx < 2; ++dx) {
+      const int y = 2 * Y + dy, x = 2 * X + dx;
+      if (y < fl.H && x < fl.W) m |= cf[(size_t)y * fl.P + x];
+    }
+  cc[(size_t)Y * cl.P + X] = m ? 1 : 0;
+}
+
+// Coarse known value of cell (X, Y).  Modified form: a known child j is
+// weighted by its number of direct neighbours that are not known, judging a
+// neighbour in the same cell by the fine mask and one in an adjacent cell by
+// that cell's coarse mask; neighbours outside the image are not counted.  If
+// every weight is 0 the plain mean of the known children is used.
+__global__ void __launch_bounds__(256) k_rhs_down(LevelView fl, const uint8_t* __restrict__ cf,
+                                                  const float* __restrict__ bf, LevelView cl,
+                                                  const uint8_t* __restrict__ cc,
+                                                  float* __restrict__ bc, int C, int naive) {
+  const int X = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int Y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (X >= cl.W || Y >= cl.H) return;
+  const size_t oc = (size_t)Y * cl.P + X;
+  if (!cc[oc]) {
+    for (int ch = 0; ch < C; ++ch) bc[(size_t)ch * cl.plane + oc] = 0.0f;
+    return;
+  }
+  int wts[4];
+  size_t offs[4];
+  int nk = 0;
+  for (int dy = 0; dy < 2; ++dy)
+    for (int dx = 0; dx < 2; ++dx) {
+      const int y = 2 * Y + dy, x = 2 * X + dx;
+      if (y >= fl.H || x >= fl.W) continue;
+      const size_t of = (size_t)y * fl.P + x;
+      if (!cf[of]) continue;
+      int w = 0;
+      const int ny[4] = {y, y, y - 1, y + 1};
+      const int nx[4] = {x - 1, x + 1, x, x};
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const int yy = ny[d], xx = nx[d];
+        if (yy < 0 || yy >= fl.H || xx < 0 || xx >= fl.W) continue;
+        const bool same = (yy >> 1) == Y && (xx >> 1) == X;
+        const uint8_t k = same ? cf[(size_t)yy * fl.P + xx] : cc[(size_t)(yy >> 1) * cl.P + (xx >> 1)];
+        w += k ? 0 : 1;
+      }
+      wts[nk] = w;
+      offs[nk] = of;
+      ++nk;
+    }
+  int wsum = 0;
+  for (int k = 0; k < nk; ++k) wsum += wts[k];
+  for (int ch = 0; ch < C; ++ch) {
+    const float* bp = bf + (size_t)ch * fl.plane;
+    double num = 0.0, plain = 0.0;
+    for (int k = 0; k < nk; ++k) {
+      const double v = (double)bp[offs[k]];
+      num += (double)wts[k] * v;
+      plain += v;
+    }
+    double val;
+    if (!naive && wsum > 0)
+      val = num / (double)wsum;
+    else
+      val = plain / (double)(nk > 0 ? nk : 1);
+    bc[(size_t)ch * cl.plane + oc] = (float)val;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// norm reduction with a last-workgroup finish (deterministic order)
+// ---------------------------------------------------------------------------
+
+__device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, const NormOut& no) {
+  __shared__ double red[kPassThreads / kWave];
+  __shared__ int last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  acc = wave_sum_d(acc);
+  if (lane == 0) red[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double s = (red[0] + red[1]) + (red[2] + red[3]);
+    no.partials[(size_t)ch * ntiles + tile] = s;
+    __threadfence();
+    const unsigned prev = atomicAdd(&no.counter[ch], 1u);
+    last = prev == ntiles - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double s = 0.0;
+  const double* part = no.partials + (size_t)ch * ntiles;
+  for (unsigned i = threadIdx.x; i < ntiles; i += kPassThreads)
+    s += __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  s = wave_sum_d(s);
+  __syncthreads();
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double tot = (red[0] + red[1]) + (red[2] + red[3]);
+    no.out[ch] = tot;
+    atomicExch(&no.counter[ch], 0u);
+    if (no.check) {
+      const double den = no.den[ch];
+      const double rel = den > 0.0 ? sqrt(tot / den) : (tot > 0.0 ? INFINITY : 0.0);
+      no.relres[ch] = rel;
+      if (rel <= no.tol) no.active[ch] = 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// fused grid pass
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double prolong_at(const float* __restrict__ uc, int Wc, int Hc, int Pc,
+                                             int gx, int gy) {
+  const int X = gx >> 1, Y = gy >> 1;
+  const int Xf = (gx & 1) ? min(X + 1, Wc - 1) : max(X - 1, 0);
+  const int Yf = (gy & 1) ? min(Y + 1, Hc - 1) : max(Y - 1, 0);
+  const double a = uc[(size_t)Y * Pc + X], b = uc[(size_t)Y * Pc + Xf];
+  const double c = uc[(size_t)Yf * Pc + X], d = uc[(size_t)Yf * Pc + Xf];
+  // ((9/16 a + 3/16 b) + 3/16 c) + 1/16 d, each product and sum rounded once
+  double s = __dadd_rn(__dmul_rn(0.5625, a), __dmul_rn(0.1875, b));
+  s = __dadd_rn(s, __dmul_rn(0.1875, c));
+  return __dadd_rn(s, __dmul_rn(0.0625, d));
+}
+
+template <int MODE>
+__device__ __forceinline__ float new_iterate(const PassArgs& a, int ch, int gx, int gy) {
+  const LevelView& lv = a.lv;
+  const size_t o = (size_t)ch * lv.plane + (size_t)gy * lv.P + gx;
+  if constexpr (MODE == PASS_RES) {
+    return a.u_in[o];
+  } else if constexpr (MODE == PASS_UPD) {
+    const int B = lv.B, S = lv.B - lv.o;
+    const int bx1 = min(gx / S, lv.nbx - 1), lx1 = gx - bx1 * S;
+    const int by1 = min(gy / S, lv.nby - 1), ly1 = gy - by1 * S;
+    const bool hx0 = bx1 > 0 && lx1 < lv.o, hy0 = by1 > 0 && ly1 < lv.o;
+    const float* cb = a.contrib + (size_t)ch * ((size_t)lv.nbx * lv.nby * B * B);
+    auto at = [&](int by, int bx, int ly, int lx) {
+      return cb[(((size_t)by * lv.nbx + bx) * B + ly) * B + lx];
+    };
+    float d = 0.0f;
+    if (hy0) {
+      if (hx0) d += at(by1 - 1, bx1 - 1, ly1 + S, lx1 + S);
+      d += at(by1 - 1, bx1, ly1 + S, lx1);
+    }
+    if (hx0) d += at(by1, bx1 - 1, ly1, lx1 + S);
+    d += at(by1, bx1, ly1, lx1);
+    return a.u_in[o] + d;
+  } else {
+    const size_t oc = (size_t)gy * lv.P + gx;
+    const bool known = a.c[oc] != 0;
+    if constexpr (MODE == PASS_PSOL) {
+      if (known) return a.b[o];
+      return (float)prolong_at(a.uc + (size_t)ch * a.planec, a.Wc, a.Hc, a.Pc, gx, gy);
+    } else {
+      const float u = a.u_in[o];
+      if (known) return u;
+      return (float)((double)u + prolong_at(a.uc + (size_t)ch * a.planec, a.Wc, a.Hc, a.Pc, gx, gy));
+    }
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tiles_x,
+                                                      unsigned ntiles) {
+  const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int ch = lin / ntiles;
+  const unsigned tile = lin - (unsigned)ch * ntiles;
+  if (a.active && !a.active[ch]) return;
+  const LevelView& lv = a.lv;
+  const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
+  __shared__ float t[kTileH + 2][kTileW + 2];
+  for (int i = threadIdx.x; i < (kTileH + 2) * (kTileW + 2); i += kPassThreads) {
+    const int ty = i / (kTileW + 2), tx = i - ty * (kTileW + 2);
+    const int gx = x0 + tx - 1, gy = y0 + ty - 1;
+    float v = 0.0f;
+    if (gx >= 0 && gx < lv.W && gy >= 0 && gy < lv.H) v = new_iterate<MODE>(a, ch, gx, gy);
+    t[ty][tx] = v;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, tyg = threadIdx.x >> 6;
+  const int gx = x0 + tx;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < kTileH / 4; ++k) {
+    const int ty = tyg * (kTileH / 4) + k;
+    const int gy = y0 + ty;
+    if (gx < lv.W && gy < lv.H) {
+      const size_t oc = (size_t)gy * lv.P + gx;
+      const size_t o = (size_t)ch * lv.plane + oc;
+      const float u = t[ty + 1][tx + 1];
+      if constexpr (MODE != PASS_RES) a.u_out[o] = u;
+      const double bb = a.b[o];
+      double r;
+      if (a.c[oc]) {
+        r = bb - (double)u;
+      } else {
+        double nsum = 0.0;
+        int n = 0;
+        if (gx > 0) { nsum += (double)t[ty + 1][tx]; ++n; }
+        if (gx < lv.W - 1) { nsum += (double)t[ty + 1][tx + 2]; ++n; }
+        if (gy > 0) { nsum += (double)t[ty][tx + 1]; ++n; }
+        if (gy < lv.H - 1) { nsum += (double)t[ty + 2][tx + 1]; ++n; }
+        r = bb - ((double)n * (double)u - nsum);
+      }
+      const float rf = (float)r;
+      a.r[o] = rf;
+      acc += r * r;
+    }
+  }
+  reduce_norm(acc, ch, tile, ntiles, a.norm);
+}
+
+// ---------------------------------------------------------------------------
+// residual restriction (Sections 4.1, 4.4)
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kPassThreads) k_restrict(LevelView fl, const float* __restrict__ rf,
+                                                          LevelView cl, const uint8_t* __restrict__ cc,
+                                                          float* __restrict__ bc, float* __restrict__ uc,
+                                                          float* __restrict__ rc, NormOut no,
+                                                          const int* __restrict__ active,
+                                                          unsigned tiles_x, unsigned ntiles) {
+  const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int ch = lin / ntiles;
+  const unsigned tile = lin - (unsigned)ch * ntiles;
+  if (active && !active[ch]) return;
+  const int X = (int)(tile % tiles_x) * kTileW + (threadIdx.x & 63);
+  const int Yb = (int)(tile / tiles_x) * kTileH + (threadIdx.x >> 6) * (kTileH / 4);
+  double acc = 0.0;
+  const float* r = rf + (size_t)ch * fl.plane;
+#pragma unroll
+  for (int k = 0; k < kTileH / 4; ++k) {
+    const int Y = Yb + k;
+    if (X < cl.W && Y < cl.H) {
+      const size_t oc = (size_t)Y * cl.P + X;
+      double v = 0.0;
+      if (!cc[oc]) {
+        double s = 0.0;
+        int n = 0;
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            const int y = 2 * Y + dy, x = 2 * X + dx;
+            if (y < fl.H && x < fl.W) { s += (double)r[(size_t)y * fl.P + x]; ++n; }
+          }
+        v = 4.0 * s / (double)n;
+      }
+      const float vf = (float)v;
+      const size_t o = (size_t)ch * cl.plane + oc;
+      bc[o] = vf;
+      uc[o] = 0.0f;
+      rc[o] = vf;
+      acc += (double)vf * (double)vf;
+    }
+  }
+  reduce_norm(acc, ch, tile, ntiles, no);
+}
+
+// ---------------------------------------------------------------------------
+// local CG on one block held in the registers of one wavefront
+// ---------------------------------------------------------------------------
+//
+// Lane layout for block side B (B in {16, 32}): lane = lx + B * g, where lx is
+// the column inside the block and g one of G = 64 / B row groups; each lane
+// holds the R = B / G rows g*R .. g*R + R - 1 of its column.  Horizontal
+// neighbours come from lanes +-1 through DPP wave shifts; vertical neighbours
+// are in the same lane's registers except across row groups (lanes +-B).
+template <int B>
+struct BlockCG {
+  static constexpr int G = kWave / B;
+  static constexpr int R = B / G;
+  int lane, lx, g;
+  float hasL, hasR;  // the lane to the left / right belongs to the same row group
+  float dg[R];       // diagonal of A_i, 0 at known and outside pixels
+  float nm[R];       // 1 at unknown pixels of the block, else 0
+
+  __device__ void apply(const float (&x)[R], float (&q)[R]) const {
+    float fa = __shfl(x[R - 1], (lane - B) & 63);
+    float fb = __shfl(x[0], (lane + B) & 63);
+    fa = g > 0 ? fa : 0.0f;
+    fb = g < G - 1 ? fb : 0.0f;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const float l = lane_from_left(x[k]) * hasL;
+      const float r = lane_from_right(x[k]) * hasR;
+      const float up = k > 0 ? x[k - 1] : fa;
+      const float dn = k < R - 1 ? x[k + 1] : fb;
+      q[k] = dg[k] * x[k] - nm[k] * ((l + r) + (up + dn));
+    }
+  }
+
+  // Set up the lane geometry and the diagonal for a block at (x0, y0) of size
+  // bw x bh on a W x H level.  A neighbour outside the block but inside the
+  // image is a cut edge and adds gamma (Robin); one outside the image adds 0.
+  __device__ void setup(int x0, int y0, int bw, int bh, int W, int H, float gamma,
+                        const uint8_t* __restrict__ c, int P) {
+    lane = threadIdx.x & 63;
+    lx = lane % B;
+    g = lane / B;
+    hasL = lx > 0 ? 1.0f : 0.0f;
+    hasR = lx < B - 1 ? 1.0f : 0.0f;
+    const bool colok = lx < bw;
+    const float dl = lx > 0 ? 1.0f : (x0 > 0 ? gamma : 0.0f);
+    const float dr = lx < bw - 1 ? 1.0f : (x0 + bw < W ? gamma : 0.0f);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int ly = g * R + k;
+      const bool ok = colok && ly < bh;
+      const bool unknown = ok && c[(size_t)(y0 + ly) * P + x0 + lx] == 0;
+      const float du = ly > 0 ? 1.0f : (y0 > 0 ? gamma : 0.0f);
+      const float dd = ly < bh - 1 ? 1.0f : (y0 + bh < H ? gamma : 0.0f);
+      nm[k] = unknown ? 1.0f : 0.0f;
+      dg[k] = unknown ? (dl + dr) + (du + dd) : 0.0f;
+    }
+  }
+
+  // Plain CG from v = 0 on A_i v = rho (rho is overwritten by the final
+  // residual).  Stops when ||rho||^2 <= thr or after maxit iterations.
+  __device__ int solve(float (&rho)[R], float (&v)[R], float thr, int maxit) const {
+    float p[R], q[R];
+    float rr = 0.0f;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      rho[k] *= nm[k];
+      v[k] = 0.0f;
+      p[k] = rho[k];
+      rr += rho[k] * rho[k];
+    }
+    rr = wave_sum(rr);
+    int it = 0;
+    while (it < maxit && rr > thr) {
+      apply(p, q);
+      float pq = 0.0f;
+#pragma unroll
+      for (int k = 0; k < R; ++k) pq += p[k] * q[k];
+      pq = wave_sum(pq);
+      if (!(pq > 0.0f)) break;
+      const float alpha = rr / pq;
+      float rn = 0.0f;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        v[k] += alpha * p[k];
+        rho[k] -= alpha * q[k];
+        rn += rho[k] * rho[k];
+      }
+      rn = wave_sum(rn);
+      const float beta = rn / rr;
+      rr = rn;
+#pragma unroll
+      for (int k = 0; k < R; ++k) p[k] = rho[k] + beta * p[k];
+      ++it;
+    }
+    return it;
+  }
+};
+
+__device__ __forceinline__ float pou_weight(int l, int nb, int k, int B, int o) {
+  // 1-D partition of unity (Section 3.1): 0 at the outermost overlap pixel,
+  // 1 at the innermost, linear in between; 1 away from overlaps.
+  if (k > 0 && l < o) return (float)l / (float)(o - 1);
+  if (k < nb - 1 && l >= B - o) return (float)(B - 1 - l) / (float)(o - 1);
+  return 1.0f;
+}
+
+template <int B>
+__global__ void __launch_bounds__(kWave) k_block_solve(BlockArgs a, unsigned nblk) {
+  const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int ch = lin / nblk;
+  const unsigned bi = lin - (unsigned)ch * nblk;
+  if (a.active && !a.active[ch]) return;
+  const LevelView& lv = a.lv;
+  const int S = B - lv.o;
+  const int bx = bi % lv.nbx, by = bi / lv.nbx;
+  const int x0 = bx * S, y0 = by * S;
+  const int bw = min(B, lv.W - x0), bh = min(B, lv.H - y0);
+  BlockCG<B> cg;
+  cg.setup(x0, y0, bw, bh, lv.W, lv.H, a.gamma, a.c, lv.P);
+  constexpr int R = BlockCG<B>::R;
+  float rho[R], v[R];
+  const float* r = a.r + (size_t)ch * lv.plane;
+  const bool colok = cg.lx < bw;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int ly = cg.g * R + k;
+    rho[k] = (colok && ly < bh) ? r[(size_t)(y0 + ly) * lv.P + x0 + cg.lx] : 0.0f;
+  }
+  const double frac = (double)bw * (double)bh / ((double)lv.W * (double)lv.H);
+  const float thr = (float)((double)a.tau * a.snorm[ch] * frac);
+  const int it = cg.solve(rho, v, thr, a.maxit);
+  float* out = a.contrib + (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B;
+  const float wx = pou_weight(cg.lx, lv.nbx, bx, B, lv.o);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int ly = cg.g * R + k;
+    if (colok && ly < bh) out[ly * B + cg.lx] = wx * pou_weight(ly, lv.nby, by, B, lv.o) * v[k];
+  }
+  if (a.cgstat && cg.lane == 0) {
+    atomicAdd(&a.cgstat[0], (unsigned long long)it);
+    atomicMax(&a.cgstat[1], (unsigned long long)it);
+  }
+}
+
+// The coarsest grid is a single block.  Residual in float64 from u, then CG,
+// then u += v.  One wavefront per channel.
+template <int B>
+__global__ void __launch_bounds__(kWave) k_coarse_solve(CoarseArgs a) {
+  const int ch = blockIdx.x;
+  if (a.active && !a.active[ch]) return;
+  const LevelView& lv = a.lv;
+  BlockCG<B> cg;
+  cg.setup(0, 0, lv.W, lv.H, lv.W, lv.H, 0.0f, a.c, lv.P);
+  constexpr int R = BlockCG<B>::R;
+  const bool colok = cg.lx < lv.W;
+  float u[R], bb[R], known[R];
+  const float* bp = a.b + (size_t)ch * lv.plane;
+  float* up = a.u + (size_t)ch * lv.plane;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int ly = cg.g * R + k;
+    const bool ok = colok && ly < lv.H;
+    const size_t o = (size_t)ly * lv.P + cg.lx;
+    const bool kn = ok && a.c[o] != 0;
+    known[k] = kn ? 1.0f : 0.0f;
+    bb[k] = ok ? bp[o] : 0.0f;
+    u[k] = ok ? (a.init ? (kn ? bb[k] : 0.0f) : up[o]) : 0.0f;
+  }
+  // residual r = b - A u (float64 arithmetic), 0 at known pixels
+  float rho[R];
+  {
+    float fa = __shfl(u[R - 1], (cg.lane - B) & 63);
+    float fb = __shfl(u[0], (cg.lane + B) & 63);
+    fa = cg.g > 0 ? fa : 0.0f;
+    fb = cg.g < BlockCG<B>::G - 1 ? fb : 0.0f;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const double l = (double)(lane_from_left(u[k]) * cg.hasL);
+      const double r = (double)(lane_from_right(u[k]) * cg.hasR);
+      const double upv = k > 0 ? u[k - 1] : fa;
+      const double dn = k < R - 1 ? u[k + 1] : fb;
+      const double res = (double)bb[k] - ((double)cg.dg[k] * (double)u[k] - ((l + r) + (upv + dn)));
+      rho[k] = (float)(res * (double)cg.nm[k]);
+    }
+  }
+  float rr0 = 0.0f;
+#pragma unroll
+  for (int k = 0; k < R; ++k) rr0 += rho[k] * rho[k];
+  rr0 = wave_sum(rr0);
+  float v[R];
+  const int it = cg.solve(rho, v, a.rel_tol * rr0, a.maxit);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int ly = cg.g * R + k;
+    if (colok && ly < lv.H) {
+      const size_t o = (size_t)ly * lv.P + cg.lx;
+      up[o] = known[k] != 0.0f ? bb[k] : u[k] + v[k];
+    }
+  }
+  if (a.cgstat && cg.lane == 0) {
+    atomicAdd(&a.cgstat[0], (unsigned long long)it);
+    atomicMax(&a.cgstat[1], (unsigned long long)it);
+  }
+}
+
+dim3 px_grid(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
+
+}  // namespace
+
+size_t pass_tiles(const LevelView& lv) {
+  return (size_t)((lv.W + kTileW - 1) / kTileW) * (size_t)((lv.H + kTileH - 1) / kTileH);
+}
+
+hipError_t launch_stage(const float* f, const uint8_t* mask, int W, int H, int C, int Pf,
+                        LevelView lv, uint8_t* c, float* b, float* u, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_stage, px_grid(W, H), dim3(256), 0, s, f, mask, W, H, C, Pf, lv, c, b, u,
+                     status);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_down(LevelView fine, const uint8_t* cf, LevelView coarse, uint8_t* cc,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_down, px_grid(coarse.W, coarse.H), dim3(256), 0, s, fine, cf, coarse, cc);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_down(LevelView fine, const uint8_t* cf, const float* bf, LevelView coarse,
+                           const uint8_t* cc, float* bc, int C, int naive, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs_down, px_grid(coarse.W, coarse.H), dim3(256), 0, s, fine, cf, bf, coarse,
+                     cc, bc, C, naive);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass(int mode, const PassArgs& a, int C, hipStream_t s) {
+  const unsigned tx = (a.lv.W + kTileW - 1) / kTileW;
+  const unsigned nt = (unsigned)pass_tiles(a.lv);
+  const dim3 grid(nt * (unsigned)C);
+  switch (mode) {
+    case PASS_RES: hipLaunchKernelGGL(k_pass<PASS_RES>, grid, dim3(kPassThreads), 0, s, a, tx, nt); break;
+    case PASS_UPD: hipLaunchKernelGGL(k_pass<PASS_UPD>, grid, dim3(kPassThreads), 0, s, a, tx, nt); break;
+    case PASS_PSOL: hipLaunchKernelGGL(k_pass<PASS_PSOL>, grid, dim3(kPassThreads), 0, s, a, tx, nt); break;
+    case PASS_PCORR: hipLaunchKernelGGL(k_pass<PASS_PCORR>, grid, dim3(kPassThreads), 0, s, a, tx, nt); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict(LevelView fine, const float* rf, LevelView coarse, const uint8_t* cc,
+                           float* bc, float* uc, float* rc, NormOut norm, const int* active,
+                           int C, hipStream_t s) {
+  const unsigned tx = (coarse.W + kTileW - 1) / kTileW;
+  const unsigned nt = (unsigned)pass_tiles(coarse);
+  hipLaunchKernelGGL(k_restrict, dim3(nt * (unsigned)C), dim3(kPassThreads), 0, s, fine, rf, coarse,
+                     cc, bc, uc, rc, norm, active, tx, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_solve(const BlockArgs& a, int C, hipStream_t s) {
+  const unsigned nblk = (unsigned)a.lv.nbx * (unsigned)a.lv.nby;
+  const dim3 grid(nblk * (unsigned)C);
+  if (a.lv.B == 32)
+    hipLaunchKernelGGL(k_block_solve<32>, grid, dim3(kWave), 0, s, a, nblk);
+  else if (a.lv.B == 16)
+    hipLaunchKernelGGL(k_block_solve<16>, grid, dim3(kWave), 0, s, a, nblk);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_solve(const CoarseArgs& a, int C, hipStream_t s) {
+  if (a.lv.W > a.lv.B || a.lv.H > a.lv.B) return hipErrorInvalidValue;
+  if (a.lv.B == 32)
+    hipLaunchKernelGGL(k_coarse_solve<32>, dim3(C), dim3(kWave), 0, s, a);
+  else if (a.lv.B == 16)
+    hipLaunchKernelGGL(k_coarse_solve<16>, dim3(C), dim3(kWave), 0, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_output(LevelView lv, const uint8_t* c, const float* b, const float* const* u_sel,
+                         float* out, int Pout, int C, hipStream_t s) {
+  dim3 g = px_grid(lv.W, lv.H);
+  g.z = C;
+  hipLaunchKernelGGL(k_output, g, dim3(256), 0, s, lv, c, b, u_sel[0], C > 1 ? u_sel[1] : u_sel[0],
+                     C > 2 ? u_sel[2] : u_sel[0], C > 3 ? u_sel[3] : u_sel[0], out, Pout);
+  return hipGetLastError();
+}
+
+}  // namespace inpaint

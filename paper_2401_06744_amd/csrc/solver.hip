@@ -1,0 +1,844 @@
+// Host side of the inpainting library: workspaces (grid hierarchy in HBM),
+// the cycle driver of Section 4.2 and the C ABI of include/inpaint.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "inpaint.h"
+#include "kernels.h"
+
+namespace inpaint {
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+  int code;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) {
+  g_err = msg;
+  throw Fail{code};
+}
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      fail(e_ == hipErrorOutOfMemory ? INPAINT_E_NOMEM : INPAINT_E_DEVICE,        \
+           std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int num_blocks_axis(int n, int B, int o) { return n <= B ? 1 : (n - o + (B - o) - 1) / (B - o); }
+
+// ---------------------------------------------------------------------------
+// options
+// ---------------------------------------------------------------------------
+
+struct Opts {
+  int B = 32, o = 6;
+  float gamma = 0.5f, tau = 0.02f;
+  int maxit = 64;
+  int schedule = INPAINT_SCHED_RFMG;
+  int max_cycles = 0;
+  int pre = 1, post = 1;
+  int rhs = INPAINT_RHS_MODIFIED;
+  float coarse_tau = 1e-8f;
+  int coarse_maxit = 256;
+};
+
+Opts resolve(const inpaint_opts* p) {
+  Opts o;
+  if (p) {
+    if (p->struct_size != (int)sizeof(inpaint_opts))
+      fail(INPAINT_E_INVALID, "inpaint_opts.struct_size must equal sizeof(inpaint_opts)");
+    if (p->block) o.B = p->block;
+    if (p->overlap) o.o = p->overlap;
+    if (p->gamma != 0.0f) o.gamma = p->gamma;
+    if (p->tau != 0.0f) o.tau = p->tau;
+    if (p->max_local_iters) o.maxit = p->max_local_iters;
+    o.schedule = p->schedule;
+    if (p->max_cycles) o.max_cycles = p->max_cycles;
+    if (p->pre_smooth) o.pre = p->pre_smooth;
+    if (p->post_smooth) o.post = p->post_smooth;
+    o.rhs = p->rhs_restriction;
+    if (p->coarse_tau != 0.0f) o.coarse_tau = p->coarse_tau;
+    if (p->coarse_max_iters) o.coarse_maxit = p->coarse_max_iters;
+  }
+  if (o.B != 16 && o.B != 32) fail(INPAINT_E_INVALID, "block must be 16 or 32");
+  if (o.o < 2 || 2 * o.o > o.B) fail(INPAINT_E_INVALID, "overlap must satisfy 2 <= overlap <= block/2");
+  if (!(o.gamma > 0.0f && o.gamma <= 1.0f)) fail(INPAINT_E_INVALID, "gamma must lie in (0, 1]");
+  if (!(o.tau >= 0.0f) || !std::isfinite(o.tau)) fail(INPAINT_E_INVALID, "tau must be finite and >= 0");
+  if (o.maxit < 0 || o.coarse_maxit < 0) fail(INPAINT_E_INVALID, "iteration caps must be >= 0");
+  if (o.schedule < INPAINT_SCHED_RFMG || o.schedule > INPAINT_SCHED_SINGLE)
+    fail(INPAINT_E_INVALID, "unknown schedule");
+  if (o.rhs != INPAINT_RHS_MODIFIED && o.rhs != INPAINT_RHS_NAIVE)
+    fail(INPAINT_E_INVALID, "unknown rhs_restriction");
+  if (o.pre < 0 || o.post < 0 || o.pre > 16 || o.post > 16)
+    fail(INPAINT_E_INVALID, "smoothing counts must lie in [0, 16]");
+  if (!(o.coarse_tau >= 0.0f)) fail(INPAINT_E_INVALID, "coarse_tau must be >= 0");
+  if (o.max_cycles < 0) fail(INPAINT_E_INVALID, "max_cycles must be >= 0");
+  if (o.max_cycles == 0)
+    o.max_cycles = (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG) ? 30 : 2000;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// workspaces
+// ---------------------------------------------------------------------------
+
+struct Level {
+  LevelView v;
+  uint8_t* c = nullptr;
+  float* b = nullptr;
+  float* u[2] = {nullptr, nullptr};
+  float* r = nullptr;
+  float* contrib = nullptr;
+  int cur = 0;
+};
+
+struct Key {
+  int dev, W, H, C, B, o, coarsest;
+  bool operator<(const Key& k) const {
+    return std::tie(dev, W, H, C, B, o, coarsest) < std::tie(k.dev, k.W, k.H, k.C, k.B, k.o, k.coarsest);
+  }
+};
+
+struct Workspace {
+  Key key{};
+  int L = 0;
+  Level lv[kMaxLevels];
+  void* base = nullptr;
+  size_t bytes = 0;
+  double* partials = nullptr;
+  unsigned* counters = nullptr;
+  double* snorm = nullptr;  // [L][C]
+  double* den = nullptr;    // [C]
+  double* relres = nullptr; // [C]
+  int* active = nullptr;    // [C]
+  int* status = nullptr;    // [4]
+  unsigned long long* cgstat = nullptr;  // [2]
+  // host-pointer staging (allocated on first use)
+  void* stage_base = nullptr;
+  float* f_dev = nullptr;
+  uint8_t* m_dev = nullptr;
+  float* o_dev = nullptr;
+  // pinned readback
+  void* host = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool busy = false;
+
+  ~Workspace() {
+    int old = -1;
+    (void)hipGetDevice(&old);
+    (void)hipSetDevice(key.dev);
+    if (base) (void)hipFree(base);
+    if (stage_base) (void)hipFree(stage_base);
+    if (host) (void)hipHostFree(host);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (old >= 0) (void)hipSetDevice(old);
+  }
+};
+
+std::vector<std::pair<int, int>> level_sizes(int W, int H, int coarsest) {
+  std::vector<std::pair<int, int>> s{{W, H}};
+  while (s.back().first > coarsest || s.back().second > coarsest) {
+    const auto [w, h] = s.back();
+    s.push_back({(w + 1) / 2, (h + 1) / 2});
+    if ((int)s.size() > kMaxLevels) break;
+  }
+  return s;
+}
+
+std::unique_ptr<Workspace> create_workspace(const Key& k) {
+  auto ws = std::make_unique<Workspace>();
+  ws->key = k;
+  const auto sizes = level_sizes(k.W, k.H, k.coarsest);
+  if ((int)sizes.size() > kMaxLevels) fail(INPAINT_E_INVALID, "image too large for the level table");
+  ws->L = (int)sizes.size();
+  const int C = k.C;
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    const size_t at = off;
+    off = round_up(off + n, 256);
+    return at;
+  };
+  struct Offs { size_t c, b, u0, u1, r, contrib; };
+  std::vector<Offs> lo(ws->L);
+  size_t maxtiles = 1;
+  for (int l = 0; l < ws->L; ++l) {
+    LevelView& v = ws->lv[l].v;
+    v.W = sizes[l].first;
+    v.H = sizes[l].second;
+    v.P = (int)round_up((size_t)v.W, 64);
+    v.plane = (size_t)v.H * v.P;
+    v.B = k.B;
+    v.o = k.o;
+    v.nbx = num_blocks_axis(v.W, k.B, k.o);
+    v.nby = num_blocks_axis(v.H, k.B, k.o);
+    const size_t f = (size_t)C * v.plane * sizeof(float);
+    lo[l].c = take(v.plane);
+    lo[l].b = take(f);
+    lo[l].u0 = take(f);
+    lo[l].u1 = take(f);
+    lo[l].r = take(f);
+    lo[l].contrib = take((size_t)C * v.nbx * v.nby * k.B * k.B * sizeof(float));
+    maxtiles = std::max(maxtiles, pass_tiles(v));
+  }
+  const size_t o_part = take((size_t)C * maxtiles * sizeof(double));
+  const size_t o_cnt = take((size_t)C * sizeof(unsigned));
+  const size_t o_sn = take((size_t)ws->L * C * sizeof(double));
+  const size_t o_den = take((size_t)C * sizeof(double));
+  const size_t o_rel = take((size_t)C * sizeof(double));
+  const size_t o_act = take((size_t)C * sizeof(int));
+  const size_t o_st = take(4 * sizeof(int));
+  const size_t o_cg = take(2 * sizeof(unsigned long long));
+  ws->bytes = off;
+  HIPCHK(hipMalloc(&ws->base, off));
+  char* base = (char*)ws->base;
+  for (int l = 0; l < ws->L; ++l) {
+    Level& L = ws->lv[l];
+    L.c = (uint8_t*)(base + lo[l].c);
+    L.b = (float*)(base + lo[l].b);
+    L.u[0] = (float*)(base + lo[l].u0);
+    L.u[1] = (float*)(base + lo[l].u1);
+    L.r = (float*)(base + lo[l].r);
+    L.contrib = (float*)(base + lo[l].contrib);
+  }
+  ws->partials = (double*)(base + o_part);
+  ws->counters = (unsigned*)(base + o_cnt);
+  ws->snorm = (double*)(base + o_sn);
+  ws->den = (double*)(base + o_den);
+  ws->relres = (double*)(base + o_rel);
+  ws->active = (int*)(base + o_act);
+  ws->status = (int*)(base + o_st);
+  ws->cgstat = (unsigned long long*)(base + o_cg);
+  HIPCHK(hipMemset(ws->counters, 0, (size_t)C * sizeof(unsigned)));
+  HIPCHK(hipHostMalloc(&ws->host, 4096, hipHostMallocDefault));
+  HIPCHK(hipEventCreate(&ws->ev0));
+  HIPCHK(hipEventCreate(&ws->ev1));
+  return ws;
+}
+
+std::mutex g_mu;
+std::map<Key, std::vector<std::unique_ptr<Workspace>>> g_cache;
+
+struct Lease {
+  Workspace* ws = nullptr;
+  Lease() = default;
+  Lease(const Lease&) = delete;
+  Lease& operator=(const Lease&) = delete;
+  ~Lease() {
+    if (ws) {
+      std::lock_guard<std::mutex> g(g_mu);
+      ws->busy = false;
+    }
+  }
+};
+
+void acquire(Lease& lease, int W, int H, int C, int B, int o, int coarsest) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  const Key k{dev, W, H, C, B, o, coarsest};
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    for (auto& w : g_cache[k])
+      if (!w->busy) {
+        w->busy = true;
+        lease.ws = w.get();
+        return;
+      }
+  }
+  auto ws = create_workspace(k);
+  std::lock_guard<std::mutex> g(g_mu);
+  ws->busy = true;
+  lease.ws = ws.get();
+  g_cache[k].push_back(std::move(ws));
+}
+
+void ensure_staging(Workspace* ws) {
+  if (ws->stage_base) return;
+  const size_t n = (size_t)ws->key.W * ws->key.H;
+  const size_t fb = round_up(n * ws->key.C * sizeof(float), 256);
+  HIPCHK(hipMalloc(&ws->stage_base, 2 * fb + round_up(n, 256)));
+  ws->f_dev = (float*)ws->stage_base;
+  ws->o_dev = (float*)((char*)ws->stage_base + fb);
+  ws->m_dev = (uint8_t*)((char*)ws->stage_base + 2 * fb);
+}
+
+bool is_device_ptr(const void* p) {
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// ---------------------------------------------------------------------------
+// the cycle driver
+// ---------------------------------------------------------------------------
+
+struct Run {
+  Workspace* ws;
+  Opts o;
+  hipStream_t s;
+  int C;
+  double tol;
+  long oras_iters = 0;
+  long block_solves = 0;
+
+  NormOut norm(int l, bool check) const {
+    NormOut n{};
+    n.partials = ws->partials;
+    n.counter = ws->counters;
+    n.out = ws->snorm + (size_t)l * C;
+    n.den = ws->den;
+    n.relres = ws->relres;
+    n.active = ws->active;
+    n.tol = tol;
+    n.check = check ? 1 : 0;
+    return n;
+  }
+
+  PassArgs pass_args(int l) const {
+    const Level& L = ws->lv[l];
+    PassArgs a{};
+    a.lv = L.v;
+    a.c = L.c;
+    a.b = L.b;
+    a.u_in = L.u[L.cur];
+    a.u_out = L.u[L.cur ^ 1];
+    a.r = L.r;
+    a.contrib = L.contrib;
+    a.active = ws->active;
+    return a;
+  }
+
+  void residual(int l, bool check) {
+    PassArgs a = pass_args(l);
+    a.u_out = nullptr;
+    a.norm = norm(l, check);
+    HIPCHK(launch_pass(PASS_RES, a, C, s));
+  }
+
+  void oras(int l, bool check) {
+    Level& L = ws->lv[l];
+    BlockArgs b{};
+    b.lv = L.v;
+    b.c = L.c;
+    b.r = L.r;
+    b.snorm = ws->snorm + (size_t)l * C;
+    b.contrib = L.contrib;
+    b.gamma = o.gamma;
+    b.tau = o.tau;
+    b.maxit = o.maxit;
+    b.active = ws->active;
+    b.cgstat = ws->cgstat;
+    HIPCHK(launch_block_solve(b, C, s));
+    PassArgs a = pass_args(l);
+    a.norm = norm(l, check);
+    HIPCHK(launch_pass(PASS_UPD, a, C, s));
+    L.cur ^= 1;
+    ++oras_iters;
+    block_solves += (long)L.v.nbx * L.v.nby * C;
+  }
+
+  void prolong(int l, int mode, bool check) {
+    Level& L = ws->lv[l];
+    const Level& Lc = ws->lv[l + 1];
+    PassArgs a = pass_args(l);
+    a.uc = Lc.u[Lc.cur];
+    a.Wc = Lc.v.W;
+    a.Hc = Lc.v.H;
+    a.Pc = Lc.v.P;
+    a.planec = Lc.v.plane;
+    a.norm = norm(l, check);
+    HIPCHK(launch_pass(mode, a, C, s));
+    L.cur ^= 1;
+  }
+
+  void restrict_to(int l) {
+    const Level& F = ws->lv[l];
+    Level& Cl = ws->lv[l + 1];
+    HIPCHK(launch_restrict(F.v, F.r, Cl.v, Cl.c, Cl.b, Cl.u[Cl.cur], Cl.r, norm(l + 1, false),
+                           ws->active, C, s));
+  }
+
+  void coarse(int l, bool init) {
+    Level& L = ws->lv[l];
+    CoarseArgs a{};
+    a.lv = L.v;
+    a.c = L.c;
+    a.b = L.b;
+    a.u = L.u[L.cur];
+    a.init = init ? 1 : 0;
+    a.rel_tol = o.coarse_tau;
+    a.maxit = o.coarse_maxit;
+    a.active = ws->active;
+    a.cgstat = nullptr;
+    HIPCHK(launch_coarse_solve(a, C, s));
+  }
+
+  // One V-cycle on level l for the problem held in (b_l, u_l).  On return
+  // (l > 0) u_l holds the correction; at l == 0 the residual of the finest
+  // grid and its norm are current.
+  void vcycle(int l) {
+    const int Lc = ws->L - 1;
+    if (l == Lc) {
+      coarse(l, l != 0);
+      if (l == 0) residual(0, true);
+      return;
+    }
+    for (int i = 0; i < o.pre; ++i) oras(l, false);
+    restrict_to(l);
+    vcycle(l + 1);
+    prolong(l, PASS_PCORR, l == 0 && o.post == 0);
+    for (int i = 0; i < o.post; ++i) oras(l, l == 0 && i == o.post - 1);
+  }
+
+  // Coarse-to-fine initial guess (Section 4.2): exact-ish solve on the
+  // coarsest grid, then on every finer level prolongate the solution, reset
+  // the known pixels and smooth with one ORAS iteration (reduced FMG) or a
+  // V-cycle (full FMG); the finest level is left to the V-cycles.
+  void cascade() {
+    const int Lc = ws->L - 1;
+    if (Lc == 0) {
+      residual(0, true);
+      return;
+    }
+    coarse(Lc, true);
+    for (int l = Lc - 1; l >= 0; --l) {
+      prolong(l, PASS_PSOL, l == 0);
+      if (l == 0) break;
+      if (o.schedule == INPAINT_SCHED_FMG)
+        vcycle(l);
+      else
+        oras(l, false);
+    }
+  }
+};
+
+__global__ void k_reset(int* active, int* status, unsigned long long* cgstat, int C) {
+  const int t = threadIdx.x;
+  if (t < C) active[t] = 1;
+  if (t < 4) status[t] = 0;
+  if (t < 2) cgstat[t] = 0;
+}
+
+struct SolveResult {
+  int status = INPAINT_OK;
+  double rel = 0.0;
+  int cycles = 0;
+};
+
+// Stage (f, mask) into level 0 and build the hierarchy.  Returns after the
+// input checks have been read back.
+void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy) {
+  Workspace* ws = R.ws;
+  const int C = R.C;
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, R.s, ws->active, ws->status, ws->cgstat, C);
+  HIPCHK(hipGetLastError());
+  Level& L0 = ws->lv[0];
+  L0.cur = 0;
+  HIPCHK(launch_stage(f_d, m_d, ws->key.W, ws->key.H, C, ws->key.W, L0.v, L0.c, L0.b, L0.u[0],
+                      ws->status, R.s));
+  // denominator of the relative residual: the residual of u = C f
+  {
+    PassArgs a = R.pass_args(0);
+    a.u_in = L0.b;
+    a.u_out = nullptr;
+    NormOut n = R.norm(0, false);
+    n.out = ws->den;
+    a.norm = n;
+    a.active = nullptr;
+    HIPCHK(launch_pass(PASS_RES, a, C, R.s));
+  }
+  if (hierarchy) {
+    for (int l = 0; l + 1 < ws->L; ++l) {
+      Level& F = ws->lv[l];
+      Level& Cl = ws->lv[l + 1];
+      Cl.cur = 0;
+      HIPCHK(launch_mask_down(F.v, F.c, Cl.v, Cl.c, R.s));
+      HIPCHK(launch_rhs_down(F.v, F.c, F.b, Cl.v, Cl.c, Cl.b, C,
+                             R.o.rhs == INPAINT_RHS_NAIVE ? 1 : 0, R.s));
+    }
+  }
+  int* h = (int*)ws->host;
+  HIPCHK(hipMemcpyAsync(h, ws->status, sizeof(int), hipMemcpyDeviceToHost, R.s));
+  HIPCHK(hipStreamSynchronize(R.s));
+  if (h[0] & 1) fail(INPAINT_E_INVALID, "f is not finite at a known pixel");
+  if (!(h[0] & 2)) fail(INPAINT_E_EMPTY_MASK, "mask has no known pixel: the system is singular");
+}
+
+// Read back the per-channel flags; returns true when every channel is done.
+bool poll(Run& R, std::vector<int>& final_cur, std::vector<double>& rel) {
+  Workspace* ws = R.ws;
+  const int C = R.C;
+  char* h = (char*)ws->host;
+  HIPCHK(hipMemcpyAsync(h, ws->active, C * sizeof(int), hipMemcpyDeviceToHost, R.s));
+  HIPCHK(hipMemcpyAsync(h + 64, ws->relres, C * sizeof(double), hipMemcpyDeviceToHost, R.s));
+  HIPCHK(hipStreamSynchronize(R.s));
+  const int* act = (const int*)h;
+  const double* rr = (const double*)(h + 64);
+  bool all = true;
+  for (int ch = 0; ch < C; ++ch) {
+    if (final_cur[ch] < 0) {
+      rel[ch] = rr[ch];
+      if (!act[ch] || !std::isfinite(rr[ch])) final_cur[ch] = ws->lv[0].cur;
+    }
+    all = all && final_cur[ch] >= 0;
+  }
+  return all;
+}
+
+SolveResult run_solve(Run& R, float* out_d) {
+  Workspace* ws = R.ws;
+  const int C = R.C;
+  std::vector<int> final_cur(C, -1);
+  std::vector<double> rel(C, 0.0);
+  SolveResult res;
+  const int sched = R.o.schedule;
+  if (sched == INPAINT_SCHED_SINGLE) {
+    R.residual(0, true);
+  } else {
+    R.cascade();
+  }
+  bool done = poll(R, final_cur, rel);
+  int cycles = 0;
+  while (!done && cycles < R.o.max_cycles) {
+    if (sched == INPAINT_SCHED_RFMG || sched == INPAINT_SCHED_FMG)
+      R.vcycle(0);
+    else
+      R.oras(0, true);
+    ++cycles;
+    done = poll(R, final_cur, rel);
+  }
+  bool diverged = false;
+  for (int ch = 0; ch < C; ++ch) {
+    if (final_cur[ch] < 0) final_cur[ch] = ws->lv[0].cur;
+    if (!std::isfinite(rel[ch])) diverged = true;
+  }
+  const float* sel[kMaxChannels];
+  for (int ch = 0; ch < C; ++ch) sel[ch] = ws->lv[0].u[final_cur[ch]];
+  HIPCHK(launch_output(ws->lv[0].v, ws->lv[0].c, ws->lv[0].b, sel, out_d, ws->key.W, C, R.s));
+  res.cycles = cycles;
+  res.rel = 0.0;
+  for (int ch = 0; ch < C; ++ch) res.rel = std::max(res.rel, rel[ch]);
+  if (diverged) {
+    res.status = INPAINT_E_DIVERGED;
+    res.rel = NAN;
+  } else if (!done) {
+    res.status = INPAINT_NOT_CONVERGED;
+  }
+  return res;
+}
+
+void check_dims(const void* a, const void* b, int W, int H, int C) {
+  if (!a || !b) fail(INPAINT_E_INVALID, "NULL pointer argument");
+  if (W < 1 || H < 1) fail(INPAINT_E_INVALID, "W and H must be >= 1");
+  if (C < 1 || C > kMaxChannels) fail(INPAINT_E_INVALID, "channels must lie in [1, 4]");
+  if ((long long)W * H > (1LL << 31)) fail(INPAINT_E_INVALID, "image too large");
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+int solve_impl(const float* f, const uint8_t* mask, int W, int H, int C, double tol, float* out,
+               const inpaint_opts* opts, void* stream, inpaint_stats* stats) {
+  check_dims(f, mask, W, H, C);
+  if (!out) fail(INPAINT_E_INVALID, "NULL pointer argument");
+  if (!(tol > 0.0 && tol < 1.0)) fail(INPAINT_E_INVALID, "tol must lie in (0, 1)");
+  const Opts o = resolve(opts);
+  const size_t nf = (size_t)W * H * C * sizeof(float);
+  if (out != f && overlap(out, nf, f, nf)) fail(INPAINT_E_INVALID, "out partially overlaps f");
+  if (overlap(out, nf, mask, (size_t)W * H)) fail(INPAINT_E_INVALID, "out overlaps mask");
+  hipStream_t s = (hipStream_t)stream;
+  Lease lease;
+  acquire(lease, W, H, C, o.B, o.o, o.B);
+  Workspace* ws = lease.ws;
+  const bool fd = is_device_ptr(f), md = is_device_ptr(mask), od = is_device_ptr(out);
+  if (!fd || !md || !od) ensure_staging(ws);
+  const float* f_d = f;
+  const uint8_t* m_d = mask;
+  float* o_d = out;
+  if (!fd) {
+    HIPCHK(hipMemcpyAsync(ws->f_dev, f, nf, hipMemcpyHostToDevice, s));
+    f_d = ws->f_dev;
+  }
+  if (!md) {
+    HIPCHK(hipMemcpyAsync(ws->m_dev, mask, (size_t)W * H, hipMemcpyHostToDevice, s));
+    m_d = ws->m_dev;
+  }
+  if (!od) o_d = ws->o_dev;
+  Run R{ws, o, s, C, tol};
+  HIPCHK(hipEventRecord(ws->ev0, s));
+  prepare(R, f_d, m_d, o.schedule != INPAINT_SCHED_SINGLE);
+  const SolveResult res = run_solve(R, o_d);
+  HIPCHK(hipEventRecord(ws->ev1, s));
+  if (!od) HIPCHK(hipMemcpyAsync(out, ws->o_dev, nf, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->rel_res = res.rel;
+    stats->cycles = res.cycles;
+    stats->levels = ws->L;
+    stats->oras_iters = (int)(R.oras_iters * C);
+    unsigned long long cg[2] = {0, 0};
+    HIPCHK(hipMemcpy(cg, ws->cgstat, sizeof(cg), hipMemcpyDeviceToHost));
+    stats->local_cg_mean = R.block_solves ? (double)cg[0] / (double)R.block_solves : 0.0;
+    stats->local_cg_max = (int)cg[1];
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+    stats->gpu_ms = ms;
+  }
+  if (res.status == INPAINT_E_DIVERGED) g_err = "the residual became non-finite";
+  else if (res.status == INPAINT_NOT_CONVERGED) g_err = "cycle cap reached before the tolerance";
+  return res.status;
+}
+
+// Copy a host [C][H][W] array into a pitched level field.
+void upload_field(const float* src, const Level& L, float* dst, int C, hipStream_t s) {
+  for (int ch = 0; ch < C; ++ch)
+    HIPCHK(hipMemcpy2DAsync(dst + (size_t)ch * L.v.plane, (size_t)L.v.P * sizeof(float),
+                            src + (size_t)ch * L.v.W * L.v.H, (size_t)L.v.W * sizeof(float),
+                            (size_t)L.v.W * sizeof(float), L.v.H, hipMemcpyHostToDevice, s));
+}
+void download_field(const float* src, const Level& L, float* dst, int C, hipStream_t s) {
+  for (int ch = 0; ch < C; ++ch)
+    HIPCHK(hipMemcpy2DAsync(dst + (size_t)ch * L.v.W * L.v.H, (size_t)L.v.W * sizeof(float),
+                            src + (size_t)ch * L.v.plane, (size_t)L.v.P * sizeof(float),
+                            (size_t)L.v.W * sizeof(float), L.v.H, hipMemcpyDeviceToHost, s));
+}
+
+template <class Fn>
+int guarded(Fn&& fn) {
+  g_err.clear();
+  try {
+    return fn();
+  } catch (const Fail& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return INPAINT_E_NOMEM;
+  } catch (...) {
+    g_err = "unexpected exception";
+    return INPAINT_E_DEVICE;
+  }
+}
+
+}  // namespace
+}  // namespace inpaint
+
+using namespace inpaint;
+
+#define INPAINT_EXPORT __attribute__((visibility("default")))
+
+extern "C" {
+
+INPAINT_EXPORT int inpaint_solve(const float* f, const uint8_t* mask, int W, int H, int channels, double tol,
+                  float* out) {
+  return guarded([&] { return solve_impl(f, mask, W, H, channels, tol, out, nullptr, nullptr, nullptr); });
+}
+
+INPAINT_EXPORT int inpaint_solve_ex(const float* f, const uint8_t* mask, int W, int H, int channels, double tol,
+                     float* out, const inpaint_opts* opts, void* stream, inpaint_stats* stats) {
+  return guarded([&] { return solve_impl(f, mask, W, H, channels, tol, out, opts, stream, stats); });
+}
+
+INPAINT_EXPORT const char* inpaint_last_error(void) { return g_err.c_str(); }
+
+INPAINT_EXPORT const char* inpaint_version(void) { return "inpaint-mi355x 0.1 (gfx950)"; }
+
+INPAINT_EXPORT int inpaint_rel_res(const float* u, const float* f, const uint8_t* mask, int W, int H, int channels,
+                    double* rel_res_out) {
+  return guarded([&] {
+    check_dims(f, mask, W, H, channels);
+    if (!u || !rel_res_out) fail(INPAINT_E_INVALID, "NULL pointer argument");
+    Lease lease;
+    acquire(lease, W, H, channels, 32, 6, 1 << 30);
+    Workspace* ws = lease.ws;
+    ensure_staging(ws);
+    hipStream_t s = nullptr;
+    const size_t nf = (size_t)W * H * channels * sizeof(float);
+    const float* f_d = f;
+    const uint8_t* m_d = mask;
+    if (!is_device_ptr(f)) {
+      HIPCHK(hipMemcpyAsync(ws->f_dev, f, nf, hipMemcpyHostToDevice, s));
+      f_d = ws->f_dev;
+    }
+    if (!is_device_ptr(mask)) {
+      HIPCHK(hipMemcpyAsync(ws->m_dev, mask, (size_t)W * H, hipMemcpyHostToDevice, s));
+      m_d = ws->m_dev;
+    }
+    Opts o;
+    Run R{ws, o, s, channels, 0.5};
+    prepare(R, f_d, m_d, false);
+    Level& L0 = ws->lv[0];
+    const hipMemcpyKind kind = is_device_ptr(u) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    for (int ch = 0; ch < channels; ++ch)
+      HIPCHK(hipMemcpy2DAsync(L0.u[1] + (size_t)ch * L0.v.plane, (size_t)L0.v.P * sizeof(float),
+                              u + (size_t)ch * W * H, (size_t)W * sizeof(float),
+                              (size_t)W * sizeof(float), H, kind, s));
+    L0.cur = 1;
+    R.residual(0, false);
+    std::vector<double> sn(channels), den(channels);
+    HIPCHK(hipMemcpyAsync(sn.data(), ws->snorm, channels * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(den.data(), ws->den, channels * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int ch = 0; ch < channels; ++ch)
+      rel_res_out[ch] = den[ch] > 0 ? std::sqrt(sn[ch] / den[ch]) : (sn[ch] > 0 ? INFINITY : 0.0);
+    return INPAINT_OK;
+  });
+}
+
+INPAINT_EXPORT int inpaint_hierarchy_size(int W, int H, int block, int* levels_out, size_t* pixels_out) {
+  return guarded([&] {
+    if (W < 1 || H < 1 || block < 1) fail(INPAINT_E_INVALID, "W, H and block must be >= 1");
+    const auto sz = level_sizes(W, H, block);
+    if ((int)sz.size() > kMaxLevels) fail(INPAINT_E_INVALID, "image too large for the level table");
+    size_t n = 0;
+    for (auto& p : sz) n += (size_t)p.first * p.second;
+    if (levels_out) *levels_out = (int)sz.size();
+    if (pixels_out) *pixels_out = n;
+    return INPAINT_OK;
+  });
+}
+
+INPAINT_EXPORT int inpaint_debug_pyramid(const float* f, const uint8_t* mask, int W, int H, int channels, int block,
+                          int rhs_restriction, int* levels_out, int* sizes_out, uint8_t* masks_out,
+                          float* rhs_out) {
+  return guarded([&] {
+    check_dims(f, mask, W, H, channels);
+    if (block < 1) fail(INPAINT_E_INVALID, "block must be >= 1");
+    if (rhs_restriction != INPAINT_RHS_MODIFIED && rhs_restriction != INPAINT_RHS_NAIVE)
+      fail(INPAINT_E_INVALID, "unknown rhs_restriction");
+    Lease lease;
+    acquire(lease, W, H, channels, 32, 6, block);
+    Workspace* ws = lease.ws;
+    ensure_staging(ws);
+    hipStream_t s = nullptr;
+    HIPCHK(hipMemcpyAsync(ws->f_dev, f, (size_t)W * H * channels * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws->m_dev, mask, (size_t)W * H, hipMemcpyHostToDevice, s));
+    Opts o;
+    o.rhs = rhs_restriction;
+    Run R{ws, o, s, channels, 0.5};
+    prepare(R, ws->f_dev, ws->m_dev, true);
+    if (levels_out) *levels_out = ws->L;
+    size_t mo = 0, ro = 0;
+    for (int l = 0; l < ws->L; ++l) {
+      const Level& L = ws->lv[l];
+      if (sizes_out) {
+        sizes_out[2 * l] = L.v.W;
+        sizes_out[2 * l + 1] = L.v.H;
+      }
+      if (masks_out)
+        HIPCHK(hipMemcpy2DAsync(masks_out + mo, L.v.W, L.c, L.v.P, L.v.W, L.v.H, hipMemcpyDeviceToHost, s));
+      if (rhs_out) download_field(L.b, L, rhs_out + ro, channels, s);
+      mo += (size_t)L.v.W * L.v.H;
+      ro += (size_t)L.v.W * L.v.H * channels;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return INPAINT_OK;
+  });
+}
+
+INPAINT_EXPORT int inpaint_debug_oras_step(const float* u_in, const float* f, const uint8_t* mask, int W, int H,
+                            int channels, const inpaint_opts* opts, float* u_out) {
+  return guarded([&] {
+    check_dims(f, mask, W, H, channels);
+    if (!u_in || !u_out) fail(INPAINT_E_INVALID, "NULL pointer argument");
+    const Opts o = resolve(opts);
+    Lease lease;
+    acquire(lease, W, H, channels, o.B, o.o, 1 << 30);
+    Workspace* ws = lease.ws;
+    ensure_staging(ws);
+    hipStream_t s = nullptr;
+    HIPCHK(hipMemcpyAsync(ws->f_dev, f, (size_t)W * H * channels * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ws->m_dev, mask, (size_t)W * H, hipMemcpyHostToDevice, s));
+    Run R{ws, o, s, channels, 0.5};
+    prepare(R, ws->f_dev, ws->m_dev, false);
+    Level& L0 = ws->lv[0];
+    upload_field(u_in, L0, L0.u[0], channels, s);
+    L0.cur = 0;
+    R.residual(0, false);
+    R.oras(0, false);
+    download_field(L0.u[L0.cur], L0, u_out, channels, s);
+    HIPCHK(hipStreamSynchronize(s));
+    return INPAINT_OK;
+  });
+}
+
+INPAINT_EXPORT int inpaint_debug_restrict(const float* r_f, const uint8_t* mask_c, int Wf, int Hf, float* r_c) {
+  return guarded([&] {
+    if (!r_f || !mask_c || !r_c) fail(INPAINT_E_INVALID, "NULL pointer argument");
+    if (Wf < 2 && Hf < 2) fail(INPAINT_E_INVALID, "the fine grid must have more than one pixel");
+    check_dims(r_f, mask_c, Wf, Hf, 1);
+    Lease lease;
+    acquire(lease, Wf, Hf, 1, 32, 6, 1);
+    Workspace* ws = lease.ws;
+    hipStream_t s = nullptr;
+    Level& F = ws->lv[0];
+    Level& Cl = ws->lv[1];
+    upload_field(r_f, F, F.r, 1, s);
+    HIPCHK(hipMemcpy2DAsync(Cl.c, Cl.v.P, mask_c, Cl.v.W, Cl.v.W, Cl.v.H, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, ws->active, ws->status, ws->cgstat, 1);
+    HIPCHK(hipGetLastError());
+    Opts o;
+    Run R{ws, o, s, 1, 0.5};
+    Cl.cur = 0;
+    R.restrict_to(0);
+    download_field(Cl.b, Cl, r_c, 1, s);
+    HIPCHK(hipStreamSynchronize(s));
+    return INPAINT_OK;
+  });
+}
+
+INPAINT_EXPORT int inpaint_debug_prolong(const float* u_c, int Wf, int Hf, const uint8_t* mask_f, const float* b_f,
+                          const float* u_in, int mode, float* u_out) {
+  return guarded([&] {
+    if (!u_c || !mask_f || !b_f || !u_out || (mode == 1 && !u_in))
+      fail(INPAINT_E_INVALID, "NULL pointer argument");
+    if (mode != 0 && mode != 1) fail(INPAINT_E_INVALID, "mode must be 0 or 1");
+    if (Wf < 2 && Hf < 2) fail(INPAINT_E_INVALID, "the fine grid must have more than one pixel");
+    check_dims(u_c, mask_f, Wf, Hf, 1);
+    Lease lease;
+    acquire(lease, Wf, Hf, 1, 32, 6, 1);
+    Workspace* ws = lease.ws;
+    hipStream_t s = nullptr;
+    Level& F = ws->lv[0];
+    Level& Cl = ws->lv[1];
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, ws->active, ws->status, ws->cgstat, 1);
+    HIPCHK(hipGetLastError());
+    upload_field(u_c, Cl, Cl.u[0], 1, s);
+    Cl.cur = 0;
+    HIPCHK(hipMemcpy2DAsync(F.c, F.v.P, mask_f, F.v.W, F.v.W, F.v.H, hipMemcpyHostToDevice, s));
+    upload_field(b_f, F, F.b, 1, s);
+    upload_field(mode == 1 ? u_in : b_f, F, F.u[0], 1, s);
+    F.cur = 0;
+    Opts o;
+    Run R{ws, o, s, 1, 0.5};
+    R.prolong(0, mode == 0 ? PASS_PSOL : PASS_PCORR, false);
+    download_field(F.u[F.cur], F, u_out, 1, s);
+    HIPCHK(hipStreamSynchronize(s));
+    return INPAINT_OK;
+  });
+}
+
+}  // extern "C"

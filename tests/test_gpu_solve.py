@@ -1,0 +1,191 @@
+"""GPU solve vs the CPU oracle through the C ABI (parity gate: max abs error <= 0.5
+grey levels on [0, 255], relative residual <= 1e-6, known pixels bit-exact)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_06744_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+MAX_ERR = 0.5
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check(u, f, m, ref=None, rr_tol=TOL, err_tol=MAX_ERR):
+    u = np.asarray(u, dtype=np.float32)
+    f3 = f if f.ndim == 3 else f[None]
+    u3 = u if u.ndim == 3 else u[None]
+    k = m != 0
+    for ch in range(f3.shape[0]):
+        assert np.array_equal(u3[ch][k], f3[ch][k]), "known pixels must be reproduced bit-exactly"
+    rr = oracle.rel_res(u3.astype(np.float64), f3.astype(np.float64), m)
+    assert np.all(rr <= rr_tol), rr
+    if ref is None:
+        ref = oracle.solve_pcg(f3.astype(np.float64), m)
+    err = np.abs(u3.astype(np.float64) - ref).max()
+    assert err <= err_tol, err
+    return rr, err
+
+
+def _solve(f, m, tol=TOL, **kw):
+    opts = binding.make_opts(**kw) if kw else None
+    out, st, stats = binding.inpaint_solve_ex(f, m, tol, opts=opts)
+    return out, st, stats
+
+
+def test_small_config_256():
+    f, m = synth.config_small()
+    out, st, stats = _solve(f, m)
+    assert st == binding.OK
+    assert stats["levels"] == 4
+    _check(out, f, m)
+
+
+@pytest.mark.parametrize("W,H,C,dens,seed", [
+    (77, 53, 1, 0.05, 1), (33, 33, 3, 0.04, 2), (65, 31, 2, 0.1, 3), (300, 17, 1, 0.05, 4),
+    (129, 257, 4, 0.02, 5), (1, 100, 1, 0.1, 6), (100, 1, 1, 0.1, 7), (32, 32, 1, 0.05, 8),
+    (58, 59, 1, 0.01, 9), (511, 383, 3, 0.04, 10), (1000, 3, 1, 0.05, 11), (2, 2, 1, 0.5, 12),
+])
+def test_ragged_sizes(W, H, C, dens, seed):
+    f = synth.frame_image(W, H, C, seed=seed)
+    m = synth.bernoulli_mask(W, H, dens, seed=seed + 100)
+    out, st, _ = _solve(f, m)
+    assert st == binding.OK
+    _check(out, f, m)
+
+
+def test_single_pixel_and_all_known():
+    f = synth.plain_image(40, 30, seed=3)
+    m = np.zeros((30, 40), np.uint8)
+    m[11, 7] = 1
+    out, st, _ = _solve(f, m)
+    assert st == binding.OK
+    np.testing.assert_allclose(out[0], f[0, 11, 7], atol=1e-3)
+    m1 = np.ones((30, 40), np.uint8)
+    out1, st1, _ = _solve(f, m1)
+    assert st1 == binding.OK and np.array_equal(out1, f)
+    one = np.array([[[5.0]]], np.float32)
+    o1, s1, _ = _solve(one, np.ones((1, 1), np.uint8))
+    assert s1 == binding.OK and o1[0, 0, 0] == 5.0
+
+
+def test_ramp_with_known_border():
+    H, W = 96, 130
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    f = (20.0 + 1.2 * x + 0.5 * y).astype(np.float32)[None]
+    m = synth.bernoulli_mask(W, H, 0.03, seed=4)
+    m[0, :] = m[-1, :] = m[:, 0] = m[:, -1] = 1
+    out, st, _ = _solve(f, m)
+    assert st == binding.OK
+    np.testing.assert_allclose(out[0], f[0], atol=5e-3)
+
+
+def test_row_closed_form():
+    W = 700
+    rng = np.random.default_rng(5)
+    f = rng.uniform(0, 255, (1, 1, W)).astype(np.float32)
+    m = (rng.random((1, W)) < 0.05).astype(np.uint8)
+    m[0, 3] = 1
+    out, st, _ = _solve(f, m)
+    xs = np.nonzero(m[0])[0]
+    expect = np.interp(np.arange(W), xs, f[0, 0, xs].astype(np.float64))
+    assert st == binding.OK
+    np.testing.assert_allclose(out[0, 0], expect, atol=1e-2)
+
+
+def test_errors():
+    f, m = synth.config_small(40, 40)
+    with pytest.raises(binding.InpaintError) as e:
+        _solve(f, np.zeros_like(m))
+    assert e.value.code == binding.E_EMPTY_MASK
+    g = f.copy()
+    k = np.argwhere(m)[0]
+    g[0, k[0], k[1]] = np.nan
+    with pytest.raises(binding.InpaintError) as e:
+        _solve(g, m)
+    assert e.value.code == binding.E_INVALID
+    for bad in ({"block": 24}, {"overlap": 1}, {"overlap": 17}, {"gamma": 1.5}, {"schedule": 9}):
+        with pytest.raises(binding.InpaintError) as e:
+            _solve(f, m, **bad)
+        assert e.value.code == binding.E_INVALID
+    with pytest.raises(binding.InpaintError) as e:
+        binding.inpaint_solve_ex(f, m, 0.0)
+    assert e.value.code == binding.E_INVALID
+
+
+def test_not_converged_writes_iterate():
+    f, m = synth.config_small(128, 128, 0.01)
+    out, st, stats = _solve(f, m, tol=1e-15, max_cycles=2)
+    assert st == binding.NOT_CONVERGED
+    assert stats["cycles"] == 2
+    assert np.array_equal(out[0][m != 0], f[0][m != 0])
+    assert oracle.rel_res(out.astype(np.float64), f.astype(np.float64), m)[0] < 1e-2
+
+
+def test_unknown_values_never_read_and_channels_independent():
+    f = synth.frame_image(150, 90, 3, seed=21)
+    m = synth.bernoulli_mask(150, 90, 0.04, seed=22)
+    out, _, _ = _solve(f, m)
+    g = f.copy()
+    g[:, m == 0] = np.nan
+    out2, _, _ = _solve(g, m)
+    assert np.array_equal(out, out2)
+    for ch in range(3):
+        single, _, _ = _solve(np.ascontiguousarray(f[ch:ch + 1]), m)
+        assert np.array_equal(single[0], out[ch])
+
+
+def test_repeatable_and_device_pointers_and_alias():
+    torch = _torch()
+    f = synth.frame_image(200, 120, 3, seed=31)
+    m = synth.bernoulli_mask(200, 120, 0.05, seed=32)
+    a, _, _ = _solve(f, m)
+    b, _, _ = _solve(f, m)
+    assert np.array_equal(a, b), "run-to-run results must be bitwise identical"
+    fd = torch.from_numpy(f).cuda()
+    md = torch.from_numpy(m).cuda()
+    od, st, _ = binding.inpaint_solve_ex(fd, md, TOL)
+    torch.cuda.synchronize()
+    assert st == binding.OK and np.array_equal(od.cpu().numpy(), a)
+    al = fd.clone()
+    binding.inpaint_solve_ex(al, md, TOL, out=al)
+    torch.cuda.synchronize()
+    assert np.array_equal(al.cpu().numpy(), a)
+
+
+@pytest.mark.parametrize("kw", [
+    {"schedule": binding.SCHED_FMG}, {"schedule": binding.SCHED_MULTILEVEL},
+    {"block": 16, "overlap": 4}, {"overlap": 2}, {"overlap": 16, "block": 32},
+    {"gamma": 1.0}, {"rhs_restriction": binding.RHS_NAIVE}, {"pre_smooth": 2, "post_smooth": 2},
+    {"post_smooth": 0, "pre_smooth": 2},
+])
+def test_options_reach_the_same_solution(kw):
+    f = synth.frame_image(180, 140, 1, seed=41)
+    m = synth.bernoulli_mask(180, 140, 0.05, seed=42)
+    out, st, _ = _solve(f, m, **kw)
+    assert st == binding.OK
+    _check(out, f, m)
+
+
+def test_single_level_schedule():
+    f = synth.frame_image(64, 48, 1, seed=51)
+    m = synth.bernoulli_mask(64, 48, 0.1, seed=52)
+    out, st, stats = _solve(f, m, schedule=binding.SCHED_SINGLE)
+    assert st == binding.OK
+    _check(out, f, m)
+
+
+def test_rel_res_entry_point_matches_oracle():
+    f = synth.frame_image(123, 77, 2, seed=61)
+    m = synth.bernoulli_mask(123, 77, 0.05, seed=62)
+    rng = np.random.default_rng(63)
+    u = np.where(m[None] != 0, f, rng.uniform(0, 255, f.shape)).astype(np.float32)
+    got = binding.inpaint_rel_res(u, f, m)
+    ref = oracle.rel_res(u.astype(np.float64), f.astype(np.float64), m)
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
