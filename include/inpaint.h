@@ -88,7 +88,23 @@ typedef struct inpaint_opts {
   float coarse_tau;    /* relative stop of the CG solve on the coarsest grid, on squared
                           norms (default 1e-8) */
   int coarse_max_iters;/* cap on that solve (default 256) */
+  int profile;         /* non-zero: time every finest-grid kernel launch with HIP events on the
+                          solve's stream and report it in inpaint_stats (adds event records) */
 } inpaint_opts;
+
+/* Kernel classes reported by the profile fields of inpaint_stats. */
+typedef enum inpaint_kernel {
+  INPAINT_K_STAGE = 0,       /* staging of f and mask, and the reference residual */
+  INPAINT_K_PYRAMID = 1,     /* coarse masks and known values (first coarsening step) */
+  INPAINT_K_BLOCK_SOLVE = 2, /* ORAS local problems */
+  INPAINT_K_UPDATE = 3,      /* ORAS update + residual + norm */
+  INPAINT_K_PROLONG = 4,     /* cascade prolongation or coarse-grid correction + residual + norm */
+  INPAINT_K_RESTRICT = 5,    /* residual restriction to the next level */
+  INPAINT_K_COARSE = 6,      /* coarsest-grid solve (only when the finest grid is the coarsest) */
+  INPAINT_K_RESIDUAL = 7,    /* residual + norm only */
+  INPAINT_K_OUTPUT = 8,      /* writing out */
+  INPAINT_NUM_KERNELS = 9
+} inpaint_kernel;
 
 /* Per-solve statistics (all channels of one problem). */
 typedef struct inpaint_stats {
@@ -99,6 +115,13 @@ typedef struct inpaint_stats {
   double local_cg_mean;  /* mean local CG iterations per block solve */
   int local_cg_max;      /* largest local CG iteration count of any block */
   float gpu_ms;          /* device time of the solve, from HIP events */
+  double local_cg_finest;/* local CG iterations summed over the finest-grid block solves */
+  long long finest_block_solves; /* finest-grid block solves (blocks x channels x iterations) */
+  double finest_cg_pixel_iters;  /* sum over finest-grid block solves of iterations x block pixels */
+  /* with opts.profile: summed duration (ms) and number of finest-grid launches per
+     inpaint_kernel class, from HIP events recorded around each launch */
+  float kernel_ms[INPAINT_NUM_KERNELS];
+  int kernel_calls[INPAINT_NUM_KERNELS];
 } inpaint_stats;
 
 /*

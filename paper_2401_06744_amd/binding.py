@@ -19,6 +19,8 @@ _lib = None
 _lock = threading.Lock()
 
 OK, NOT_CONVERGED, E_INVALID, E_EMPTY_MASK, E_NOMEM, E_DEVICE, E_DIVERGED = 0, 1, -1, -2, -3, -4, -5
+KERNELS = ["stage", "pyramid", "block_solve", "update", "prolong", "restrict", "coarse",
+           "residual", "output"]
 SCHED_RFMG, SCHED_FMG, SCHED_MULTILEVEL, SCHED_SINGLE = 0, 1, 2, 3
 RHS_MODIFIED, RHS_NAIVE = 0, 1
 
@@ -35,7 +37,7 @@ class InpaintOpts(ct.Structure):
         ("gamma", ct.c_float), ("tau", ct.c_float), ("max_local_iters", ct.c_int),
         ("schedule", ct.c_int), ("max_cycles", ct.c_int), ("pre_smooth", ct.c_int),
         ("post_smooth", ct.c_int), ("rhs_restriction", ct.c_int), ("coarse_tau", ct.c_float),
-        ("coarse_max_iters", ct.c_int),
+        ("coarse_max_iters", ct.c_int), ("profile", ct.c_int),
     ]
 
 
@@ -43,11 +45,17 @@ class InpaintStats(ct.Structure):
     _fields_ = [
         ("rel_res", ct.c_double), ("cycles", ct.c_int), ("levels", ct.c_int),
         ("oras_iters", ct.c_int), ("local_cg_mean", ct.c_double), ("local_cg_max", ct.c_int),
-        ("gpu_ms", ct.c_float),
+        ("gpu_ms", ct.c_float), ("local_cg_finest", ct.c_double),
+        ("finest_block_solves", ct.c_longlong), ("finest_cg_pixel_iters", ct.c_double),
+        ("kernel_ms", ct.c_float * 9), ("kernel_calls", ct.c_int * 9),
     ]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            d[k] = list(v) if k in ("kernel_ms", "kernel_calls") else v
+        return d
 
 
 class InpaintError(RuntimeError):

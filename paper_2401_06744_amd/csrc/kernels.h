@@ -24,10 +24,10 @@ struct LevelView {
   int B, o;      // block side and overlap (stride B - o)
 };
 
-// Per-channel norm reduction target of a grid pass.
+// Per-channel norm reduction of a grid pass: every workgroup stores its partial
+// sum, then a one-workgroup-per-channel finish kernel adds them in a fixed order.
 struct NormOut {
   double* partials;   // [C][ntiles]
-  unsigned* counter;  // [C], left at 0 after every pass
   double* out;        // [C] squared norm of the residual written by the pass
   // Optional convergence test on the finest grid (check != 0):
   const double* den;  // [C] squared norm of the reference residual
@@ -57,6 +57,11 @@ struct PassArgs {
   size_t planec;
   NormOut norm;
   const int* active;     // [C] or nullptr: skip channels already converged
+  // PASS_UPD only: local CG iteration counts of the block solve being applied,
+  // summed into cgstat[ch][3] (total, max, iterations x block pixels) by the
+  // finish kernel; nullptr to skip.
+  const int* iters;
+  unsigned long long* cgstat;
 };
 
 struct BlockArgs {
@@ -68,7 +73,7 @@ struct BlockArgs {
   float gamma, tau;
   int maxit;
   const int* active;
-  unsigned long long* cgstat;  // [2]: total local iterations, max, or nullptr
+  int* iters;             // [C][nby*nbx] local CG iterations per block, or nullptr
 };
 
 struct CoarseArgs {
@@ -80,7 +85,6 @@ struct CoarseArgs {
   float rel_tol; // stop when ||rho||^2 <= rel_tol * ||rho_0||^2
   int maxit;
   const int* active;
-  unsigned long long* cgstat;
 };
 
 // Launchers (all enqueue on `s`, return hipError_t of the launch).

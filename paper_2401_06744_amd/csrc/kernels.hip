@@ -100,10 +100,15 @@ __global__ void __launch_bounds__(256) k_stage(const float* __restrict__ f,
       u[o] = v;
     }
   }
+  // Report through one word shared by the whole grid: skip the atomic when the
+  // bit is already set, so that it is issued a handful of times, not per wave.
   const unsigned long long anybad = __ballot(bad);
   const unsigned long long anyknown = __ballot(known);
-  if ((threadIdx.x & 63) == 0 && (anybad || anyknown))
-    atomicOr(status, (anybad ? 1 : 0) | (anyknown ? 2 : 0));
+  if ((threadIdx.x & 63) == 0 && (anybad || anyknown)) {
+    const int want = (anybad ? 1 : 0) | (anyknown ? 2 : 0);
+    const int have = __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((have & want) != want) atomicOr(status, want);
+  }
 }
 
 __global__ void __launch_bounds__(256) k_output(LevelView lv, const uint8_t* __restrict__ c,
@@ -199,43 +204,78 @@ __global__ void __launch_bounds__(256) k_rhs_down(LevelView fl, const uint8_t* _
 }
 
 // ---------------------------------------------------------------------------
-// norm reduction with a last-workgroup finish (deterministic order)
+// norm reduction: per-workgroup partials, then a fixed-order finish kernel
 // ---------------------------------------------------------------------------
 
-__device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, const NormOut& no) {
+// Sum `acc` over the 256 threads of the workgroup and store it as the tile's
+// partial.  No fence or atomic: the finish kernel runs after this kernel ends.
+__device__ void store_partial(double acc, int ch, unsigned tile, unsigned ntiles, double* partials) {
   __shared__ double red[kPassThreads / kWave];
-  __shared__ int last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   acc = wave_sum_d(acc);
   if (lane == 0) red[wave] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const double s = (red[0] + red[1]) + (red[2] + red[3]);
-    no.partials[(size_t)ch * ntiles + tile] = s;
-    __threadfence();
-    const unsigned prev = atomicAdd(&no.counter[ch], 1u);
-    last = prev == ntiles - 1;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double s = 0.0;
+  if (threadIdx.x == 0) partials[(size_t)ch * ntiles + tile] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// One workgroup per channel: total of the partials (fixed order), optional
+// convergence test, optional local-CG iteration statistics of a block solve.
+__global__ void __launch_bounds__(kPassThreads) k_norm_finish(NormOut no, unsigned ntiles,
+                                                             const int* __restrict__ active,
+                                                             const int* __restrict__ iters,
+                                                             unsigned nblk, LevelView lv,
+                                                             unsigned long long* __restrict__ cgstat) {
+  const int ch = blockIdx.x;
+  if (active && !active[ch]) return;
+  __shared__ double red[kPassThreads / kWave];
+  __shared__ unsigned long long ired[3][kPassThreads / kWave];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double* part = no.partials + (size_t)ch * ntiles;
-  for (unsigned i = threadIdx.x; i < ntiles; i += kPassThreads)
-    s += __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double s = 0.0;
+  for (unsigned i = threadIdx.x; i < ntiles; i += kPassThreads) s += part[i];
   s = wave_sum_d(s);
-  __syncthreads();
   if (lane == 0) red[wave] = s;
+  unsigned long long isum = 0, imax = 0, ipx = 0;
+  if (iters) {
+    const int S = lv.B - lv.o;
+    for (unsigned i = threadIdx.x; i < nblk; i += kPassThreads) {
+      const unsigned long long it = (unsigned)iters[(size_t)ch * nblk + i];
+      const int bx = (int)(i % (unsigned)lv.nbx), by = (int)(i / (unsigned)lv.nbx);
+      const int bw = min(lv.B, lv.W - bx * S), bh = min(lv.B, lv.H - by * S);
+      isum += it;
+      imax = it > imax ? it : imax;
+      ipx += it * (unsigned long long)(bw * bh);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      isum += __shfl_xor(isum, m);
+      const unsigned long long om = __shfl_xor(imax, m);
+      imax = om > imax ? om : imax;
+      ipx += __shfl_xor(ipx, m);
+    }
+    if (lane == 0) {
+      ired[0][wave] = isum;
+      ired[1][wave] = imax;
+      ired[2][wave] = ipx;
+    }
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     const double tot = (red[0] + red[1]) + (red[2] + red[3]);
     no.out[ch] = tot;
-    atomicExch(&no.counter[ch], 0u);
     if (no.check) {
       const double den = no.den[ch];
       const double rel = den > 0.0 ? sqrt(tot / den) : (tot > 0.0 ? INFINITY : 0.0);
       no.relres[ch] = rel;
       if (rel <= no.tol) no.active[ch] = 0;
+    }
+    if (iters && cgstat) {
+      unsigned long long* cs = cgstat + 3 * ch;
+      unsigned long long mx = ired[1][0];
+      for (int w = 1; w < kPassThreads / kWave; ++w) mx = ired[1][w] > mx ? ired[1][w] : mx;
+      cs[0] += ired[0][0] + ired[0][1] + ired[0][2] + ired[0][3];
+      cs[1] = mx > cs[1] ? mx : cs[1];
+      cs[2] += ired[2][0] + ired[2][1] + ired[2][2] + ired[2][3];
     }
   }
 }
@@ -342,7 +382,7 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tile
       acc += r * r;
     }
   }
-  reduce_norm(acc, ch, tile, ntiles, a.norm);
+  store_partial(acc, ch, tile, ntiles, a.norm.partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -387,7 +427,7 @@ __global__ void __launch_bounds__(kPassThreads) k_restrict(LevelView fl, const f
       acc += (double)vf * (double)vf;
     }
   }
-  reduce_norm(acc, ch, tile, ntiles, no);
+  store_partial(acc, ch, tile, ntiles, no.partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -528,10 +568,7 @@ __global__ void __launch_bounds__(kWave) k_block_solve(BlockArgs a, unsigned nbl
     const int ly = cg.g * R + k;
     if (colok && ly < bh) out[ly * B + cg.lx] = wx * pou_weight(ly, lv.nby, by, B, lv.o) * v[k];
   }
-  if (a.cgstat && cg.lane == 0) {
-    atomicAdd(&a.cgstat[0], (unsigned long long)it);
-    atomicMax(&a.cgstat[1], (unsigned long long)it);
-  }
+  if (a.iters && cg.lane == 0) a.iters[(size_t)ch * nblk + bi] = it;
 }
 
 // The coarsest grid is a single block.  Residual in float64 from u, then CG,
@@ -589,10 +626,7 @@ __global__ void __launch_bounds__(kWave) k_coarse_solve(CoarseArgs a) {
       up[o] = known[k] != 0.0f ? bb[k] : u[k] + v[k];
     }
   }
-  if (a.cgstat && cg.lane == 0) {
-    atomicAdd(&a.cgstat[0], (unsigned long long)it);
-    atomicMax(&a.cgstat[1], (unsigned long long)it);
-  }
+  (void)it;
 }
 
 dim3 px_grid(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
@@ -634,6 +668,12 @@ hipError_t launch_pass(int mode, const PassArgs& a, int C, hipStream_t s) {
     case PASS_PCORR: hipLaunchKernelGGL(k_pass<PASS_PCORR>, grid, dim3(kPassThreads), 0, s, a, tx, nt); break;
     default: return hipErrorInvalidValue;
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const bool st = mode == PASS_UPD && a.iters;
+  hipLaunchKernelGGL(k_norm_finish, dim3(C), dim3(kPassThreads), 0, s, a.norm, nt, a.active,
+                     st ? a.iters : nullptr, st ? (unsigned)(a.lv.nbx * a.lv.nby) : 0u, a.lv,
+                     st ? a.cgstat : nullptr);
   return hipGetLastError();
 }
 
@@ -644,6 +684,10 @@ hipError_t launch_restrict(LevelView fine, const float* rf, LevelView coarse, co
   const unsigned nt = (unsigned)pass_tiles(coarse);
   hipLaunchKernelGGL(k_restrict, dim3(nt * (unsigned)C), dim3(kPassThreads), 0, s, fine, rf, coarse,
                      cc, bc, uc, rc, norm, active, tx, nt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_norm_finish, dim3(C), dim3(kPassThreads), 0, s, norm, nt, active, nullptr, 0u,
+                     coarse, nullptr);
   return hipGetLastError();
 }
 

@@ -56,6 +56,7 @@ struct Opts {
   int rhs = INPAINT_RHS_MODIFIED;
   float coarse_tau = 1e-8f;
   int coarse_maxit = 256;
+  int profile = 0;
 };
 
 Opts resolve(const inpaint_opts* p) {
@@ -75,6 +76,7 @@ Opts resolve(const inpaint_opts* p) {
     o.rhs = p->rhs_restriction;
     if (p->coarse_tau != 0.0f) o.coarse_tau = p->coarse_tau;
     if (p->coarse_max_iters) o.coarse_maxit = p->coarse_max_iters;
+    o.profile = p->profile;
   }
   if (o.B != 16 && o.B != 32) fail(INPAINT_E_INVALID, "block must be 16 or 32");
   if (o.o < 2 || 2 * o.o > o.B) fail(INPAINT_E_INVALID, "overlap must satisfy 2 <= overlap <= block/2");
@@ -122,13 +124,14 @@ struct Workspace {
   void* base = nullptr;
   size_t bytes = 0;
   double* partials = nullptr;
-  unsigned* counters = nullptr;
+  int* iters = nullptr;     // [C][max blocks of a level] local CG iterations per block
   double* snorm = nullptr;  // [L][C]
   double* den = nullptr;    // [C]
   double* relres = nullptr; // [C]
   int* active = nullptr;    // [C]
   int* status = nullptr;    // [4]
-  unsigned long long* cgstat = nullptr;  // [2]
+  unsigned long long* cgstat = nullptr;  // [L][C][3]: total, max, pixel-weighted local CG iterations
+  std::vector<hipEvent_t> evpool;        // events for per-launch profiling
   // host-pointer staging (allocated on first use)
   void* stage_base = nullptr;
   float* f_dev = nullptr;
@@ -148,6 +151,7 @@ struct Workspace {
     if (host) (void)hipHostFree(host);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
     if (old >= 0) (void)hipSetDevice(old);
   }
 };
@@ -177,7 +181,7 @@ std::unique_ptr<Workspace> create_workspace(const Key& k) {
   };
   struct Offs { size_t c, b, u0, u1, r, contrib; };
   std::vector<Offs> lo(ws->L);
-  size_t maxtiles = 1;
+  size_t maxtiles = 1, maxblk = 1;
   for (int l = 0; l < ws->L; ++l) {
     LevelView& v = ws->lv[l].v;
     v.W = sizes[l].first;
@@ -196,15 +200,16 @@ std::unique_ptr<Workspace> create_workspace(const Key& k) {
     lo[l].r = take(f);
     lo[l].contrib = take((size_t)C * v.nbx * v.nby * k.B * k.B * sizeof(float));
     maxtiles = std::max(maxtiles, pass_tiles(v));
+    maxblk = std::max(maxblk, (size_t)v.nbx * v.nby);
   }
   const size_t o_part = take((size_t)C * maxtiles * sizeof(double));
-  const size_t o_cnt = take((size_t)C * sizeof(unsigned));
+  const size_t o_it = take((size_t)C * maxblk * sizeof(int));
   const size_t o_sn = take((size_t)ws->L * C * sizeof(double));
   const size_t o_den = take((size_t)C * sizeof(double));
   const size_t o_rel = take((size_t)C * sizeof(double));
   const size_t o_act = take((size_t)C * sizeof(int));
   const size_t o_st = take(4 * sizeof(int));
-  const size_t o_cg = take(2 * sizeof(unsigned long long));
+  const size_t o_cg = take((size_t)kMaxLevels * C * 3 * sizeof(unsigned long long));
   ws->bytes = off;
   HIPCHK(hipMalloc(&ws->base, off));
   char* base = (char*)ws->base;
@@ -218,14 +223,13 @@ std::unique_ptr<Workspace> create_workspace(const Key& k) {
     L.contrib = (float*)(base + lo[l].contrib);
   }
   ws->partials = (double*)(base + o_part);
-  ws->counters = (unsigned*)(base + o_cnt);
+  ws->iters = (int*)(base + o_it);
   ws->snorm = (double*)(base + o_sn);
   ws->den = (double*)(base + o_den);
   ws->relres = (double*)(base + o_rel);
   ws->active = (int*)(base + o_act);
   ws->status = (int*)(base + o_st);
   ws->cgstat = (unsigned long long*)(base + o_cg);
-  HIPCHK(hipMemset(ws->counters, 0, (size_t)C * sizeof(unsigned)));
   HIPCHK(hipHostMalloc(&ws->host, 4096, hipHostMallocDefault));
   HIPCHK(hipEventCreate(&ws->ev0));
   HIPCHK(hipEventCreate(&ws->ev1));
@@ -300,11 +304,38 @@ struct Run {
   double tol;
   long oras_iters = 0;
   long block_solves = 0;
+  long long finest_block_solves = 0;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  size_t next_ev = 0;
+
+  hipEvent_t pool_event() {
+    if (next_ev == ws->evpool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      ws->evpool.push_back(e);
+    }
+    return ws->evpool[next_ev++];
+  }
+
+  // Launch through `fn`; on the finest grid with profiling on, bracket it by
+  // two events on the same stream.
+  template <class Fn>
+  void timed(int cls, int level, Fn&& fn) {
+    if (!o.profile || level != 0) {
+      HIPCHK(fn());
+      return;
+    }
+    hipEvent_t a = pool_event(), b = pool_event();
+    HIPCHK(hipEventRecord(a, s));
+    HIPCHK(fn());
+    HIPCHK(hipEventRecord(b, s));
+    recs.push_back({cls, a, b});
+  }
 
   NormOut norm(int l, bool check) const {
     NormOut n{};
     n.partials = ws->partials;
-    n.counter = ws->counters;
     n.out = ws->snorm + (size_t)l * C;
     n.den = ws->den;
     n.relres = ws->relres;
@@ -332,7 +363,7 @@ struct Run {
     PassArgs a = pass_args(l);
     a.u_out = nullptr;
     a.norm = norm(l, check);
-    HIPCHK(launch_pass(PASS_RES, a, C, s));
+    timed(INPAINT_K_RESIDUAL, l, [&] { return launch_pass(PASS_RES, a, C, s); });
   }
 
   void oras(int l, bool check) {
@@ -347,14 +378,17 @@ struct Run {
     b.tau = o.tau;
     b.maxit = o.maxit;
     b.active = ws->active;
-    b.cgstat = ws->cgstat;
-    HIPCHK(launch_block_solve(b, C, s));
+    b.iters = ws->iters;
+    timed(INPAINT_K_BLOCK_SOLVE, l, [&] { return launch_block_solve(b, C, s); });
     PassArgs a = pass_args(l);
     a.norm = norm(l, check);
-    HIPCHK(launch_pass(PASS_UPD, a, C, s));
+    a.iters = ws->iters;
+    a.cgstat = ws->cgstat + (size_t)l * C * 3;
+    timed(INPAINT_K_UPDATE, l, [&] { return launch_pass(PASS_UPD, a, C, s); });
     L.cur ^= 1;
     ++oras_iters;
     block_solves += (long)L.v.nbx * L.v.nby * C;
+    if (l == 0) finest_block_solves += (long long)L.v.nbx * L.v.nby * C;
   }
 
   void prolong(int l, int mode, bool check) {
@@ -367,15 +401,17 @@ struct Run {
     a.Pc = Lc.v.P;
     a.planec = Lc.v.plane;
     a.norm = norm(l, check);
-    HIPCHK(launch_pass(mode, a, C, s));
+    timed(INPAINT_K_PROLONG, l, [&] { return launch_pass(mode, a, C, s); });
     L.cur ^= 1;
   }
 
   void restrict_to(int l) {
     const Level& F = ws->lv[l];
     Level& Cl = ws->lv[l + 1];
-    HIPCHK(launch_restrict(F.v, F.r, Cl.v, Cl.c, Cl.b, Cl.u[Cl.cur], Cl.r, norm(l + 1, false),
-                           ws->active, C, s));
+    const NormOut n = norm(l + 1, false);
+    timed(INPAINT_K_RESTRICT, l, [&] {
+      return launch_restrict(F.v, F.r, Cl.v, Cl.c, Cl.b, Cl.u[Cl.cur], Cl.r, n, ws->active, C, s);
+    });
   }
 
   void coarse(int l, bool init) {
@@ -389,8 +425,7 @@ struct Run {
     a.rel_tol = o.coarse_tau;
     a.maxit = o.coarse_maxit;
     a.active = ws->active;
-    a.cgstat = nullptr;
-    HIPCHK(launch_coarse_solve(a, C, s));
+    timed(INPAINT_K_COARSE, l, [&] { return launch_coarse_solve(a, C, s); });
   }
 
   // One V-cycle on level l for the problem held in (b_l, u_l).  On return
@@ -436,7 +471,7 @@ __global__ void k_reset(int* active, int* status, unsigned long long* cgstat, in
   const int t = threadIdx.x;
   if (t < C) active[t] = 1;
   if (t < 4) status[t] = 0;
-  if (t < 2) cgstat[t] = 0;
+  for (int i = t; i < 3 * C * kMaxLevels; i += blockDim.x) cgstat[i] = 0;
 }
 
 struct SolveResult {
@@ -454,8 +489,10 @@ void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy) {
   HIPCHK(hipGetLastError());
   Level& L0 = ws->lv[0];
   L0.cur = 0;
-  HIPCHK(launch_stage(f_d, m_d, ws->key.W, ws->key.H, C, ws->key.W, L0.v, L0.c, L0.b, L0.u[0],
-                      ws->status, R.s));
+  R.timed(INPAINT_K_STAGE, 0, [&] {
+    return launch_stage(f_d, m_d, ws->key.W, ws->key.H, C, ws->key.W, L0.v, L0.c, L0.b, L0.u[0],
+                        ws->status, R.s);
+  });
   // denominator of the relative residual: the residual of u = C f
   {
     PassArgs a = R.pass_args(0);
@@ -465,16 +502,18 @@ void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy) {
     n.out = ws->den;
     a.norm = n;
     a.active = nullptr;
-    HIPCHK(launch_pass(PASS_RES, a, C, R.s));
+    R.timed(INPAINT_K_STAGE, 0, [&] { return launch_pass(PASS_RES, a, C, R.s); });
   }
   if (hierarchy) {
     for (int l = 0; l + 1 < ws->L; ++l) {
       Level& F = ws->lv[l];
       Level& Cl = ws->lv[l + 1];
       Cl.cur = 0;
-      HIPCHK(launch_mask_down(F.v, F.c, Cl.v, Cl.c, R.s));
-      HIPCHK(launch_rhs_down(F.v, F.c, F.b, Cl.v, Cl.c, Cl.b, C,
-                             R.o.rhs == INPAINT_RHS_NAIVE ? 1 : 0, R.s));
+      R.timed(INPAINT_K_PYRAMID, l, [&] { return launch_mask_down(F.v, F.c, Cl.v, Cl.c, R.s); });
+      R.timed(INPAINT_K_PYRAMID, l, [&] {
+        return launch_rhs_down(F.v, F.c, F.b, Cl.v, Cl.c, Cl.b, C,
+                               R.o.rhs == INPAINT_RHS_NAIVE ? 1 : 0, R.s);
+      });
     }
   }
   int* h = (int*)ws->host;
@@ -534,7 +573,9 @@ SolveResult run_solve(Run& R, float* out_d) {
   }
   const float* sel[kMaxChannels];
   for (int ch = 0; ch < C; ++ch) sel[ch] = ws->lv[0].u[final_cur[ch]];
-  HIPCHK(launch_output(ws->lv[0].v, ws->lv[0].c, ws->lv[0].b, sel, out_d, ws->key.W, C, R.s));
+  R.timed(INPAINT_K_OUTPUT, 0, [&] {
+    return launch_output(ws->lv[0].v, ws->lv[0].c, ws->lv[0].b, sel, out_d, ws->key.W, C, R.s);
+  });
   res.cycles = cycles;
   res.rel = 0.0;
   for (int ch = 0; ch < C; ++ch) res.rel = std::max(res.rel, rel[ch]);
@@ -600,10 +641,31 @@ int solve_impl(const float* f, const uint8_t* mask, int W, int H, int C, double 
     stats->cycles = res.cycles;
     stats->levels = ws->L;
     stats->oras_iters = (int)(R.oras_iters * C);
-    unsigned long long cg[2] = {0, 0};
-    HIPCHK(hipMemcpy(cg, ws->cgstat, sizeof(cg), hipMemcpyDeviceToHost));
-    stats->local_cg_mean = R.block_solves ? (double)cg[0] / (double)R.block_solves : 0.0;
-    stats->local_cg_max = (int)cg[1];
+    std::vector<unsigned long long> cg((size_t)3 * C * ws->L, 0);
+    HIPCHK(hipMemcpy(cg.data(), ws->cgstat, cg.size() * sizeof(unsigned long long),
+                     hipMemcpyDeviceToHost));
+    unsigned long long tot = 0, mx = 0, fin = 0, finpx = 0;
+    for (int l = 0; l < ws->L; ++l)
+      for (int ch = 0; ch < C; ++ch) {
+        const unsigned long long* c3 = &cg[((size_t)l * C + ch) * 3];
+        tot += c3[0];
+        mx = std::max(mx, c3[1]);
+        if (l == 0) {
+          fin += c3[0];
+          finpx += c3[2];
+        }
+      }
+    stats->local_cg_mean = R.block_solves ? (double)tot / (double)R.block_solves : 0.0;
+    stats->local_cg_max = (int)mx;
+    stats->local_cg_finest = (double)fin;
+    stats->finest_block_solves = R.finest_block_solves;
+    stats->finest_cg_pixel_iters = (double)finpx;
+    for (const auto& rc : R.recs) {
+      float kms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&kms, rc.a, rc.b));
+      stats->kernel_ms[rc.cls] += kms;
+      stats->kernel_calls[rc.cls] += 1;
+    }
     float ms = 0.0f;
     HIPCHK(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
     stats->gpu_ms = ms;
