@@ -77,8 +77,8 @@ typedef struct inpaint_opts {
   int overlap;         /* overlap o in pixels between neighbouring blocks, 2 <= o <= B/2 (default 6) */
   float gamma;         /* Robin term added per cut block edge, 0 < gamma <= 1 (gamma = 1 is
                           Dirichlet RAS); the paper leaves alpha open (default 0.5) */
-  float tau;           /* local CG stop: ||rho_i||^2 <= tau * ||r||^2 * |block| / N (default 0.02) */
-  int max_local_iters; /* cap on local CG iterations per block (default 64) */
+  float tau;           /* local CG stop: ||rho_i||^2 <= tau * ||r||^2 * |block| / N (default 0.005) */
+  int max_local_iters; /* cap on local CG iterations per block (default 16) */
   int schedule;        /* inpaint_schedule (default INPAINT_SCHED_RFMG) */
   int max_cycles;      /* cap on V-cycles (or finest ORAS iterations for MULTILEVEL and
                           SINGLE); default 30 for RFMG/FMG, 2000 otherwise */

@@ -62,6 +62,15 @@ struct PassArgs {
   // finish kernel; nullptr to skip.
   const int* iters;
   unsigned long long* cgstat;
+  // PASS_UPD with rest != 0: instead of writing the fine residual and its norm,
+  // restrict it (Sections 4.1, 4.4) to the coarse level: write bc = uc0 = rc's
+  // right-hand side, uc0 = 0, rc = bc, and reduce the coarse norm into `norm`.
+  int rest;
+  LevelView clv;
+  const uint8_t* cc;
+  float* bc;
+  float* uc0;
+  float* rc;
 };
 
 struct BlockArgs {
@@ -88,8 +97,11 @@ struct CoarseArgs {
 };
 
 // Launchers (all enqueue on `s`, return hipError_t of the launch).
+// Stage f and mask into level 0 (b = C f, c, and u = C f when u != nullptr),
+// check the input, and reduce ||b - A C f||^2 per channel into den.out.
 hipError_t launch_stage(const float* f, const uint8_t* mask, int W, int H, int C, int Pf,
-                        LevelView lv, uint8_t* c, float* b, float* u, int* status, hipStream_t s);
+                        LevelView lv, uint8_t* c, float* b, float* u, int* status, NormOut den,
+                        hipStream_t s);
 hipError_t launch_mask_down(LevelView fine, const uint8_t* cf, LevelView coarse, uint8_t* cc,
                             hipStream_t s);
 hipError_t launch_rhs_down(LevelView fine, const uint8_t* cf, const float* bf, LevelView coarse,

@@ -81,36 +81,6 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned wg, unsigned n) {
 // staging and output
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_stage(const float* __restrict__ f,
-                                               const uint8_t* __restrict__ mask, int W, int H,
-                                               int C, int Pf, LevelView lv, uint8_t* __restrict__ c,
-                                               float* __restrict__ b, float* __restrict__ u,
-                                               int* __restrict__ status) {
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  bool bad = false, known = false;
-  if (x < W && y < H) {
-    known = mask[(size_t)y * W + x] != 0;
-    c[(size_t)y * lv.P + x] = known ? 1 : 0;
-    for (int ch = 0; ch < C; ++ch) {
-      float v = known ? f[(size_t)ch * Pf * H + (size_t)y * Pf + x] : 0.0f;
-      bad |= known && !isfinite(v);
-      const size_t o = (size_t)ch * lv.plane + (size_t)y * lv.P + x;
-      b[o] = v;
-      u[o] = v;
-    }
-  }
-  // Report through one word shared by the whole grid: skip the atomic when the
-  // bit is already set, so that it is issued a handful of times, not per wave.
-  const unsigned long long anybad = __ballot(bad);
-  const unsigned long long anyknown = __ballot(known);
-  if ((threadIdx.x & 63) == 0 && (anybad || anyknown)) {
-    const int want = (anybad ? 1 : 0) | (anyknown ? 2 : 0);
-    const int have = __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((have & want) != want) atomicOr(status, want);
-  }
-}
-
 __global__ void __launch_bounds__(256) k_output(LevelView lv, const uint8_t* __restrict__ c,
                                                 const float* __restrict__ b, const float* u0,
                                                 const float* u1, const float* u2, const float* u3,
@@ -218,33 +188,58 @@ __device__ void store_partial(double acc, int ch, unsigned tile, unsigned ntiles
   if (threadIdx.x == 0) partials[(size_t)ch * ntiles + tile] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+constexpr int kFinThreads = 512;
+
 // One workgroup per channel: total of the partials (fixed order), optional
 // convergence test, optional local-CG iteration statistics of a block solve.
-__global__ void __launch_bounds__(kPassThreads) k_norm_finish(NormOut no, unsigned ntiles,
-                                                             const int* __restrict__ active,
-                                                             const int* __restrict__ iters,
-                                                             unsigned nblk, LevelView lv,
-                                                             unsigned long long* __restrict__ cgstat) {
+// Each thread adds the entries t, t + T, t + 2T, ... in that order, with
+// eight loads in flight.
+__global__ void __launch_bounds__(kFinThreads) k_norm_finish(NormOut no, unsigned ntiles,
+                                                            const int* __restrict__ active,
+                                                            const int* __restrict__ iters,
+                                                            unsigned nblk, LevelView lv,
+                                                            unsigned long long* __restrict__ cgstat) {
+  constexpr int T = kFinThreads, NW = kFinThreads / kWave, U = 8;
   const int ch = blockIdx.x;
   if (active && !active[ch]) return;
-  __shared__ double red[kPassThreads / kWave];
-  __shared__ unsigned long long ired[3][kPassThreads / kWave];
+  __shared__ double red[NW];
+  __shared__ unsigned long long ired[3][NW];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double* part = no.partials + (size_t)ch * ntiles;
   double s = 0.0;
-  for (unsigned i = threadIdx.x; i < ntiles; i += kPassThreads) s += part[i];
+  for (unsigned base = threadIdx.x; base < ntiles; base += U * T) {
+    double v[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const unsigned i = base + j * T;
+      v[j] = i < ntiles ? part[i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) s += v[j];
+  }
   s = wave_sum_d(s);
   if (lane == 0) red[wave] = s;
-  unsigned long long isum = 0, imax = 0, ipx = 0;
   if (iters) {
+    unsigned long long isum = 0, imax = 0, ipx = 0;
     const int S = lv.B - lv.o;
-    for (unsigned i = threadIdx.x; i < nblk; i += kPassThreads) {
-      const unsigned long long it = (unsigned)iters[(size_t)ch * nblk + i];
-      const int bx = (int)(i % (unsigned)lv.nbx), by = (int)(i / (unsigned)lv.nbx);
-      const int bw = min(lv.B, lv.W - bx * S), bh = min(lv.B, lv.H - by * S);
-      isum += it;
-      imax = it > imax ? it : imax;
-      ipx += it * (unsigned long long)(bw * bh);
+    const int* itc = iters + (size_t)ch * nblk;
+    for (unsigned base = threadIdx.x; base < nblk; base += U * T) {
+      int v[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const unsigned i = base + j * T;
+        v[j] = i < nblk ? itc[i] : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const unsigned i = base + j * T;
+        const unsigned long long it = (unsigned)v[j];
+        const int bx = (int)(i % (unsigned)lv.nbx), by = (int)(i / (unsigned)lv.nbx);
+        const int bw = min(lv.B, lv.W - bx * S), bh = min(lv.B, lv.H - by * S);
+        isum += it;
+        imax = it > imax ? it : imax;
+        if (i < nblk) ipx += it * (unsigned long long)(bw * bh);
+      }
     }
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
@@ -261,7 +256,8 @@ __global__ void __launch_bounds__(kPassThreads) k_norm_finish(NormOut no, unsign
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double tot = (red[0] + red[1]) + (red[2] + red[3]);
+    double tot = 0.0;
+    for (int w = 0; w < NW; ++w) tot += red[w];
     no.out[ch] = tot;
     if (no.check) {
       const double den = no.den[ch];
@@ -271,13 +267,89 @@ __global__ void __launch_bounds__(kPassThreads) k_norm_finish(NormOut no, unsign
     }
     if (iters && cgstat) {
       unsigned long long* cs = cgstat + 3 * ch;
-      unsigned long long mx = ired[1][0];
-      for (int w = 1; w < kPassThreads / kWave; ++w) mx = ired[1][w] > mx ? ired[1][w] : mx;
-      cs[0] += ired[0][0] + ired[0][1] + ired[0][2] + ired[0][3];
+      unsigned long long a0 = 0, a2 = 0, mx = 0;
+      for (int w = 0; w < NW; ++w) {
+        a0 += ired[0][w];
+        a2 += ired[2][w];
+        mx = ired[1][w] > mx ? ired[1][w] : mx;
+      }
+      cs[0] += a0;
       cs[1] = mx > cs[1] ? mx : cs[1];
-      cs[2] += ired[2][0] + ired[2][1] + ired[2][2] + ired[2][3];
+      cs[2] += a2;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// staging of the finest level
+// ---------------------------------------------------------------------------
+
+// One 64x16 tile of one channel: b = C f, c and (optionally) u = C f for the
+// tile, input checks, and the residual of C f (the reference residual of the
+// relative residual):  at an unknown pixel it is the sum of the known
+// neighbours' values, at a known pixel 0.
+__global__ void __launch_bounds__(kPassThreads) k_stage(const float* __restrict__ f,
+                                                       const uint8_t* __restrict__ mask, int W,
+                                                       int H, int Pf, LevelView lv,
+                                                       uint8_t* __restrict__ c, float* __restrict__ b,
+                                                       float* __restrict__ u, int* __restrict__ status,
+                                                       NormOut den, unsigned tiles_x, unsigned ntiles) {
+  const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int ch = lin / ntiles;
+  const unsigned tile = lin - (unsigned)ch * ntiles;
+  const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
+  __shared__ float t[kTileH + 2][kTileW + 2];
+  __shared__ uint8_t kn[kTileH + 2][kTileW + 2];
+  const float* fc = f + (size_t)ch * Pf * H;
+  bool bad = false, any = false;
+  for (int i = threadIdx.x; i < (kTileH + 2) * (kTileW + 2); i += kPassThreads) {
+    const int ty = i / (kTileW + 2), tx = i - ty * (kTileW + 2);
+    const int gx = x0 + tx - 1, gy = y0 + ty - 1;
+    float v = 0.0f;
+    uint8_t k = 0;
+    if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+      k = mask[(size_t)gy * W + gx] != 0;
+      if (k) v = fc[(size_t)gy * Pf + gx];
+      const bool inner = tx >= 1 && tx <= kTileW && ty >= 1 && ty <= kTileH;
+      if (inner) {
+        bad |= k && !isfinite(v);
+        any |= k;
+        const size_t oc = (size_t)gy * lv.P + gx;
+        if (ch == 0) c[oc] = k;
+        b[(size_t)ch * lv.plane + oc] = v;
+        if (u) u[(size_t)ch * lv.plane + oc] = v;
+      }
+    }
+    t[ty][tx] = v;
+    kn[ty][tx] = k;
+  }
+  // Report through one word shared by the whole grid: skip the atomic when the
+  // bit is already set, so that it is issued a handful of times, not per wave.
+  const unsigned long long anybad = __ballot(bad);
+  const unsigned long long anyknown = __ballot(any);
+  if ((threadIdx.x & 63) == 0 && (anybad || anyknown)) {
+    const int want = (anybad ? 1 : 0) | (anyknown ? 2 : 0);
+    const int have = __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((have & want) != want) atomicOr(status, want);
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 63, tyg = threadIdx.x >> 6;
+  const int gx = x0 + tx;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < kTileH / 4; ++k) {
+    const int ty = tyg * (kTileH / 4) + k;
+    const int gy = y0 + ty;
+    if (gx < W && gy < H && !kn[ty + 1][tx + 1]) {
+      double nsum = 0.0;
+      if (gx > 0) nsum += (double)t[ty + 1][tx];
+      if (gx < W - 1) nsum += (double)t[ty + 1][tx + 2];
+      if (gy > 0) nsum += (double)t[ty][tx + 1];
+      if (gy < H - 1) nsum += (double)t[ty + 2][tx + 1];
+      acc += nsum * nsum;
+    }
+  }
+  store_partial(acc, ch, tile, ntiles, den.partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -354,6 +426,8 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tile
   __syncthreads();
   const int tx = threadIdx.x & 63, tyg = threadIdx.x >> 6;
   const int gx = x0 + tx;
+  const bool rest = MODE == PASS_UPD && a.rest;
+  __shared__ float rt[MODE == PASS_UPD ? kTileH : 1][MODE == PASS_UPD ? kTileW : 1];
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < kTileH / 4; ++k) {
@@ -378,8 +452,42 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tile
         r = bb - ((double)n * (double)u - nsum);
       }
       const float rf = (float)r;
+      if constexpr (MODE == PASS_UPD) {
+        if (rest) {
+          rt[ty][tx] = rf;
+          continue;
+        }
+      }
       a.r[o] = rf;
       acc += r * r;
+    }
+  }
+  if constexpr (MODE == PASS_UPD) {
+    if (rest) {
+      // The tile's 32x8 coarse cells have all their children inside the tile.
+      __syncthreads();
+      const int X = (x0 >> 1) + (threadIdx.x & 31), Y = (y0 >> 1) + (threadIdx.x >> 5);
+      const LevelView& cl = a.clv;
+      if (X < cl.W && Y < cl.H) {
+        const size_t occ = (size_t)Y * cl.P + X;
+        double v = 0.0;
+        if (!a.cc[occ]) {
+          double sr = 0.0;
+          int n = 0;
+          for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+              const int y = 2 * Y + dy, x = 2 * X + dx;
+              if (y < lv.H && x < lv.W) { sr += (double)rt[y - y0][x - x0]; ++n; }
+            }
+          v = 4.0 * sr / (double)n;
+        }
+        const float vf = (float)v;
+        const size_t oco = (size_t)ch * cl.plane + occ;
+        a.bc[oco] = vf;
+        a.uc0[oco] = 0.0f;
+        a.rc[oco] = vf;
+        acc = (double)vf * (double)vf;
+      }
     }
   }
   store_partial(acc, ch, tile, ntiles, a.norm.partials);
@@ -638,9 +746,16 @@ size_t pass_tiles(const LevelView& lv) {
 }
 
 hipError_t launch_stage(const float* f, const uint8_t* mask, int W, int H, int C, int Pf,
-                        LevelView lv, uint8_t* c, float* b, float* u, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_stage, px_grid(W, H), dim3(256), 0, s, f, mask, W, H, C, Pf, lv, c, b, u,
-                     status);
+                        LevelView lv, uint8_t* c, float* b, float* u, int* status, NormOut den,
+                        hipStream_t s) {
+  const unsigned tx = (lv.W + kTileW - 1) / kTileW;
+  const unsigned nt = (unsigned)pass_tiles(lv);
+  hipLaunchKernelGGL(k_stage, dim3(nt * (unsigned)C), dim3(kPassThreads), 0, s, f, mask, W, H, Pf, lv,
+                     c, b, u, status, den, tx, nt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_norm_finish, dim3(C), dim3(kFinThreads), 0, s, den, nt, nullptr, nullptr, 0u,
+                     lv, nullptr);
   return hipGetLastError();
 }
 
@@ -671,7 +786,7 @@ hipError_t launch_pass(int mode, const PassArgs& a, int C, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const bool st = mode == PASS_UPD && a.iters;
-  hipLaunchKernelGGL(k_norm_finish, dim3(C), dim3(kPassThreads), 0, s, a.norm, nt, a.active,
+  hipLaunchKernelGGL(k_norm_finish, dim3(C), dim3(kFinThreads), 0, s, a.norm, nt, a.active,
                      st ? a.iters : nullptr, st ? (unsigned)(a.lv.nbx * a.lv.nby) : 0u, a.lv,
                      st ? a.cgstat : nullptr);
   return hipGetLastError();
@@ -686,7 +801,7 @@ hipError_t launch_restrict(LevelView fine, const float* rf, LevelView coarse, co
                      cc, bc, uc, rc, norm, active, tx, nt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_norm_finish, dim3(C), dim3(kPassThreads), 0, s, norm, nt, active, nullptr, 0u,
+  hipLaunchKernelGGL(k_norm_finish, dim3(C), dim3(kFinThreads), 0, s, norm, nt, active, nullptr, 0u,
                      coarse, nullptr);
   return hipGetLastError();
 }

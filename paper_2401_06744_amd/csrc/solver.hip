@@ -48,8 +48,8 @@ int num_blocks_axis(int n, int B, int o) { return n <= B ? 1 : (n - o + (B - o) 
 
 struct Opts {
   int B = 32, o = 6;
-  float gamma = 0.5f, tau = 0.02f;
-  int maxit = 64;
+  float gamma = 0.5f, tau = 0.005f;
+  int maxit = 16;
   int schedule = INPAINT_SCHED_RFMG;
   int max_cycles = 0;
   int pre = 1, post = 1;
@@ -366,7 +366,9 @@ struct Run {
     timed(INPAINT_K_RESIDUAL, l, [&] { return launch_pass(PASS_RES, a, C, s); });
   }
 
-  void oras(int l, bool check) {
+  // One ORAS iteration on level l.  With rest, the update pass also restricts
+  // the new residual to level l + 1 (the last pre-smoothing of a V-cycle).
+  void oras(int l, bool check, bool rest = false) {
     Level& L = ws->lv[l];
     BlockArgs b{};
     b.lv = L.v;
@@ -384,6 +386,16 @@ struct Run {
     a.norm = norm(l, check);
     a.iters = ws->iters;
     a.cgstat = ws->cgstat + (size_t)l * C * 3;
+    if (rest) {
+      Level& Cl = ws->lv[l + 1];
+      a.rest = 1;
+      a.clv = Cl.v;
+      a.cc = Cl.c;
+      a.bc = Cl.b;
+      a.uc0 = Cl.u[Cl.cur];
+      a.rc = Cl.r;
+      a.norm = norm(l + 1, false);
+    }
     timed(INPAINT_K_UPDATE, l, [&] { return launch_pass(PASS_UPD, a, C, s); });
     L.cur ^= 1;
     ++oras_iters;
@@ -438,8 +450,8 @@ struct Run {
       if (l == 0) residual(0, true);
       return;
     }
-    for (int i = 0; i < o.pre; ++i) oras(l, false);
-    restrict_to(l);
+    for (int i = 0; i < o.pre; ++i) oras(l, false, i == o.pre - 1);
+    if (o.pre == 0) restrict_to(l);
     vcycle(l + 1);
     prolong(l, PASS_PCORR, l == 0 && o.post == 0);
     for (int i = 0; i < o.post; ++i) oras(l, l == 0 && i == o.post - 1);
@@ -482,28 +494,21 @@ struct SolveResult {
 
 // Stage (f, mask) into level 0 and build the hierarchy.  Returns after the
 // input checks have been read back.
-void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy) {
+void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy, bool write_u) {
   Workspace* ws = R.ws;
   const int C = R.C;
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, R.s, ws->active, ws->status, ws->cgstat, C);
   HIPCHK(hipGetLastError());
   Level& L0 = ws->lv[0];
   L0.cur = 0;
+  // staging, input checks and the reference residual ||b - A C f|| (denominator
+  // of the relative residual)
+  NormOut den = R.norm(0, false);
+  den.out = ws->den;
   R.timed(INPAINT_K_STAGE, 0, [&] {
-    return launch_stage(f_d, m_d, ws->key.W, ws->key.H, C, ws->key.W, L0.v, L0.c, L0.b, L0.u[0],
-                        ws->status, R.s);
+    return launch_stage(f_d, m_d, ws->key.W, ws->key.H, C, ws->key.W, L0.v, L0.c, L0.b,
+                        (write_u || ws->L == 1) ? L0.u[0] : nullptr, ws->status, den, R.s);
   });
-  // denominator of the relative residual: the residual of u = C f
-  {
-    PassArgs a = R.pass_args(0);
-    a.u_in = L0.b;
-    a.u_out = nullptr;
-    NormOut n = R.norm(0, false);
-    n.out = ws->den;
-    a.norm = n;
-    a.active = nullptr;
-    R.timed(INPAINT_K_STAGE, 0, [&] { return launch_pass(PASS_RES, a, C, R.s); });
-  }
   if (hierarchy) {
     for (int l = 0; l + 1 < ws->L; ++l) {
       Level& F = ws->lv[l];
@@ -630,7 +635,7 @@ int solve_impl(const float* f, const uint8_t* mask, int W, int H, int C, double 
   if (!od) o_d = ws->o_dev;
   Run R{ws, o, s, C, tol};
   HIPCHK(hipEventRecord(ws->ev0, s));
-  prepare(R, f_d, m_d, o.schedule != INPAINT_SCHED_SINGLE);
+  prepare(R, f_d, m_d, o.schedule != INPAINT_SCHED_SINGLE, o.schedule == INPAINT_SCHED_SINGLE);
   const SolveResult res = run_solve(R, o_d);
   HIPCHK(hipEventRecord(ws->ev1, s));
   if (!od) HIPCHK(hipMemcpyAsync(out, ws->o_dev, nf, hipMemcpyDeviceToHost, s));
@@ -751,7 +756,7 @@ INPAINT_EXPORT int inpaint_rel_res(const float* u, const float* f, const uint8_t
     }
     Opts o;
     Run R{ws, o, s, channels, 0.5};
-    prepare(R, f_d, m_d, false);
+    prepare(R, f_d, m_d, false, false);
     Level& L0 = ws->lv[0];
     const hipMemcpyKind kind = is_device_ptr(u) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     for (int ch = 0; ch < channels; ++ch)
@@ -801,7 +806,7 @@ INPAINT_EXPORT int inpaint_debug_pyramid(const float* f, const uint8_t* mask, in
     Opts o;
     o.rhs = rhs_restriction;
     Run R{ws, o, s, channels, 0.5};
-    prepare(R, ws->f_dev, ws->m_dev, true);
+    prepare(R, ws->f_dev, ws->m_dev, true, false);
     if (levels_out) *levels_out = ws->L;
     size_t mo = 0, ro = 0;
     for (int l = 0; l < ws->L; ++l) {
@@ -835,7 +840,7 @@ INPAINT_EXPORT int inpaint_debug_oras_step(const float* u_in, const float* f, co
     HIPCHK(hipMemcpyAsync(ws->f_dev, f, (size_t)W * H * channels * sizeof(float), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(ws->m_dev, mask, (size_t)W * H, hipMemcpyHostToDevice, s));
     Run R{ws, o, s, channels, 0.5};
-    prepare(R, ws->f_dev, ws->m_dev, false);
+    prepare(R, ws->f_dev, ws->m_dev, false, false);
     Level& L0 = ws->lv[0];
     upload_field(u_in, L0, L0.u[0], channels, s);
     L0.cur = 0;
