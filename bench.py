@@ -19,6 +19,7 @@ Legs:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -36,6 +37,32 @@ FP32_NONPACKED_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop x 2.4 GHz (no packed
 CG_FLOPS_PER_PIXEL_ITER = 19   # 5-point apply (9) + 2 dot products (4) + 3 axpys (6)
 
 METRIC = "4K RGB frames/s at max err ≤0.5/255 vs oracle; %HBM roofline; p50/p99 latency"
+KERNEL_SRC = os.path.join(ROOT, "paper_2401_06744_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_4k_rgb.txt")
+COPY_BYTES = 1 << 29   # calibration copy: 512 MiB read + 512 MiB written
+
+
+def kernel_source_sha() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per finest-grid launch of `kernel` from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by the factor a plain
+    copy of known size gave), or None if the kernels changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if line and not line.startswith("#") and "=" in line:
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    key = f"{kernel}_bytes_per_launch"
+    return float(kv[key]) if key in kv else None
 
 
 def algorithmic_bytes(cls: str, W: int, H: int, C: int) -> float:
@@ -45,7 +72,11 @@ def algorithmic_bytes(cls: str, W: int, H: int, C: int) -> float:
     f4 = 4.0 * C * N
     return {
         "block_solve": 2 * f4 + N,            # read r, mask; write D_i v_i (once per pixel)
-        "update": 5 * f4 + N,                 # read u, corrections, b, mask; write u, r
+        # read u, corrections, b, mask; write u and r (20C + 1 B/px), or, for the
+        # update that also restricts (one per V-cycle level visit), write u and the
+        # coarse b, u, r instead of r (19C + 1.25 B/px); the finest grid sees one
+        # of each per V-cycle, so a launch averages the two
+        "update": 0.5 * ((5 * f4 + N) + (4.75 * f4 + 1.25 * N)),
         "prolong": 4 * f4 + f4 / 4 + N,       # read u, b, mask, coarse e (N/4); write u, r
         "restrict": f4 + 3 * f4 / 4 + N / 4,  # read r, coarse mask; write coarse b, u, r
         "residual": 3 * f4 + N,               # read u, b, mask; write r
@@ -67,6 +98,8 @@ def main() -> int:
     ap.add_argument("--width", type=int, default=3840)
     ap.add_argument("--height", type=int, default=2160)
     ap.add_argument("--density", type=float, default=0.04)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -167,6 +200,15 @@ def main() -> int:
     else:
         roof = {"bound": "hbm", "achieved": dk["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_frac, 4), "traffic": None, "kernel": dom}
+    roof["traffic"] = measured_traffic(dom)
+
+    if args.calibrate_copy:
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- accuracy of the last output
     rr = binding.inpaint_rel_res(od, fd, md)

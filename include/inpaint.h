@@ -3,7 +3,7 @@
  *
  * Operation (Kaemper, Chizhov, Weickert, "Efficient Parallel Algorithms for
  * Inpainting-Based Representations of 4K Images - Part I", Section 2.2,
- * Eq. 2.6):  for each channel solve  A u = b  with  A = C + (I - C) L  and
+ * the discrete system):  for each channel solve  A u = b  with  A = C + (I - C) L  and
  * b = C f, where C = diag(mask) and L is the 5-point negated Laplacian with
  * reflecting image boundaries (diagonal |N(i)|, -1 per direct neighbour).
  * Known pixels are Dirichlet data, every other pixel is filled by the discrete

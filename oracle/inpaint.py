@@ -7,7 +7,7 @@ product path.
 What is here, and the passage each part follows:
 
 * The discrete system ``A u = b`` with ``A = C + (I - C) L`` and ``b = C f``
-  (Section 2.2, the matrix entries of ``L`` and Eq. (2.6)): ``L`` is the
+  (Section 2.2: the entries of ``L`` and the discrete linear system): ``L`` is the
   5-point negated Laplacian with reflecting boundaries, diagonal
   ``|N(i)| / h^2`` and ``-1 / h^2`` for each direct neighbour.  ``h = 1``
   here; it cancels in ``A u = b`` on the finest grid.
@@ -87,14 +87,14 @@ def apply_L(v: np.ndarray, h: float = 1.0) -> np.ndarray:
 
 
 def apply_A(u: np.ndarray, mask: np.ndarray) -> np.ndarray:
-    """``A u = C u + (I - C) L u`` (Eq. 2.6), one channel."""
+    """``A u = C u + (I - C) L u`` (Section 2.2, the discrete system), one channel."""
     c = (np.asarray(mask) != 0).astype(np.float64)
     u = np.asarray(u, dtype=np.float64)
     return c * u + (1.0 - c) * apply_L(u)
 
 
 def rhs(f: np.ndarray, mask: np.ndarray) -> np.ndarray:
-    """``b = C f`` (Eq. 2.6), one channel.  ``f`` at unknown pixels is never read."""
+    """``b = C f`` (Section 2.2, the discrete system), one channel.  ``f`` at unknown pixels is never read."""
     c = np.asarray(mask) != 0
     return np.where(c, np.asarray(f, dtype=np.float64), 0.0)
 
@@ -263,7 +263,8 @@ def pou_weights_1d(n: int, B: int, o: int) -> list[np.ndarray]:
     """1-D partition-of-unity weights of every block along an axis of length ``n``.
 
     Inside an overlap of ``o`` pixels the weight falls linearly from 1 at the
-    innermost pixel to 0 at the outermost one (Section 3.1, Fig. 3.2); away
+    innermost pixel to 0 at the outermost one (Section 3.1 and its figure of
+    the overlap weights); away
     from overlaps (and toward the image edge) it is 1.  Needs ``o >= 2``.
     """
     blocks = block_starts(n, B, o)
@@ -429,7 +430,8 @@ def oras_local_matrix(mask: np.ndarray, x0: int, y0: int, w: int, h: int, gamma:
     adds 1 to the diagonal, except that a neighbour outside the block (an
     inner subdomain boundary) adds ``gamma`` instead: the Robin condition
     ``d_n v + alpha v = 0`` there, with ``gamma = 1`` the Dirichlet (RAS) case
-    and ``gamma -> 0`` the Neumann one (Section 3, Eq. 3.6).  Neighbours outside
+    and ``gamma -> 0`` the Neumann one (Section 3, the mixed transmission
+    condition of ORAS).  Neighbours outside
     the image add nothing (reflecting boundary).
     """
     c = np.asarray(mask) != 0

@@ -14,7 +14,8 @@ def test_4k_has_eight_levels_down_to_one_block():
 
 
 def test_256_has_four_levels():
-    """Fig. 4.3 shows a 256x256 mask at 256, 128, 64 and 32 pixels."""
+    """The mask-restriction figure of Section 4.3 shows a 256x256 mask at 256, 128, 64
+    and 32 pixels."""
     assert oracle.level_sizes(256, 256, 32) == [(256, 256), (128, 128), (64, 64), (32, 32)]
 
 
@@ -44,7 +45,8 @@ def test_blocks_cover_axis_with_uniform_overlap(n, B, o):
 @pytest.mark.parametrize("n", [1, 20, 32, 33, 59, 100, 257, 3840])
 @pytest.mark.parametrize("B,o", [(32, 6), (32, 2), (16, 4), (24, 8), (32, 16)])
 def test_partition_of_unity_1d(n, B, o):
-    """Eq. (3.4): sum_i R_i^T D_i R_i = I, with weight 0 at the outermost and 1 at
+    """Partition of unity of discrete ORAS (Section 3): sum_i R_i^T D_i R_i = I, with
+    weight 0 at the outermost and 1 at
     the innermost overlap pixel and linear in between (Section 3.1)."""
     blocks = oracle.block_starts(n, B, o)
     wts = oracle.pou_weights_1d(n, B, o)
