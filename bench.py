@@ -141,7 +141,6 @@ def main() -> int:
         lat.append(time.perf_counter() - ts)
         statuses.append(st)
         cycles.append(stats["cycles"])
-        cg_mean.append(stats["local_cg_mean"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
@@ -159,6 +158,7 @@ def main() -> int:
         _, st, stats = step(popts)
         kms += np.array(stats["kernel_ms"])
         kcalls += np.array(stats["kernel_calls"])
+        cg_mean.append(stats["local_cg_mean"])
         cg_fin += stats["local_cg_finest"]
         cg_px += stats["finest_cg_pixel_iters"]
         fin_solves += stats["finest_block_solves"]

@@ -82,8 +82,9 @@ typedef struct inpaint_opts {
   int schedule;        /* inpaint_schedule (default INPAINT_SCHED_RFMG) */
   int max_cycles;      /* cap on V-cycles (or finest ORAS iterations for MULTILEVEL and
                           SINGLE); default 30 for RFMG/FMG, 2000 otherwise */
-  int pre_smooth;      /* ORAS iterations before the coarse correction (default 1) */
-  int post_smooth;     /* ORAS iterations after it (default 1) */
+  int pre_smooth;      /* ORAS iterations before the coarse correction, at most 16
+                          (0 = default 1; a negative value = none) */
+  int post_smooth;     /* ORAS iterations after it (0 = default 1; negative = none) */
   int rhs_restriction; /* inpaint_rhs_restriction (default MODIFIED) */
   float coarse_tau;    /* relative stop of the CG solve on the coarsest grid, on squared
                           norms (default 1e-8) */

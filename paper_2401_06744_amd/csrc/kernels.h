@@ -9,11 +9,13 @@
 namespace inpaint {
 
 constexpr int kMaxChannels = 4;
+constexpr int kCounterGroups = 64;
+constexpr int kCounterLines = kCounterGroups + 1;
 constexpr int kMaxLevels = 24;
 
-// Tile of the grid passes: 64 columns x 16 rows, 256 threads (4 rows each).
+// Tile of the grid passes: 64 columns x 32 rows, 256 threads (8 rows each).
 constexpr int kTileW = 64;
-constexpr int kTileH = 16;
+constexpr int kTileH = 32;
 
 // One grid level as the kernels see it.  Fields are planar per channel with a
 // padded row pitch P (elements); one plane holds H*P elements.
@@ -24,10 +26,14 @@ struct LevelView {
   int B, o;      // block side and overlap (stride B - o)
 };
 
-// Per-channel norm reduction of a grid pass: every workgroup stores its partial
-// sum, then a one-workgroup-per-channel finish kernel adds them in a fixed order.
+// Per-channel norm reduction of a grid pass.  Every workgroup publishes its
+// partial sum and bumps a per-channel counter; the workgroup that arrives last
+// adds all partials in a fixed order (see reduce_norm in kernels.hip).
 struct NormOut {
-  double* partials;   // [C][ntiles]
+  double* partials;   // [C][ntiles], every entry < 0 (unset) between passes
+  unsigned* counter;  // [C][kCounterLines][32]: 64 group counters + 1 total, one
+                      // 128-byte line each, all 0 between passes
+  int* status;        // bit 2 (value 4) set if a partial never arrived
   double* out;        // [C] squared norm of the residual written by the pass
   // Optional convergence test on the finest grid (check != 0):
   const double* den;  // [C] squared norm of the reference residual
@@ -57,11 +63,6 @@ struct PassArgs {
   size_t planec;
   NormOut norm;
   const int* active;     // [C] or nullptr: skip channels already converged
-  // PASS_UPD only: local CG iteration counts of the block solve being applied,
-  // summed into cgstat[ch][3] (total, max, iterations x block pixels) by the
-  // finish kernel; nullptr to skip.
-  const int* iters;
-  unsigned long long* cgstat;
   // PASS_UPD with rest != 0: instead of writing the fine residual and its norm,
   // restrict it (Sections 4.1, 4.4) to the coarse level: write bc = uc0 = rc's
   // right-hand side, uc0 = 0, rc = bc, and reduce the coarse norm into `norm`.
@@ -82,7 +83,8 @@ struct BlockArgs {
   float gamma, tau;
   int maxit;
   const int* active;
-  int* iters;             // [C][nby*nbx] local CG iterations per block, or nullptr
+  int* itot;              // [C][nby*nbx] running total of local CG iterations per block,
+  int* imax;              // and the running maximum; both nullptr to skip
 };
 
 struct CoarseArgs {
@@ -116,6 +118,12 @@ hipError_t launch_output(LevelView lv, const uint8_t* c, const float* b,
                          const float* const* u_sel, float* out, int Pout, int C, hipStream_t s);
 hipError_t launch_copy_in(const float* src, int W, int H, int C, int Psrc, float* dst, LevelView lv,
                           hipStream_t s);
+
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s);
+// cgstat[ch][3] += (sum of itot, max of imax, sum of itot x block pixels) over
+// the blocks of one level.
+hipError_t launch_cg_stats(LevelView lv, const int* itot, const int* imax, int C,
+                           unsigned long long* cgstat, hipStream_t s);
 
 size_t pass_tiles(const LevelView& lv);
 

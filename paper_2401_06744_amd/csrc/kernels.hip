@@ -36,12 +36,12 @@ constexpr int kPassThreads = 256;
 // DPP wave_shr:1 -- lane i receives lane i-1; lane 0 receives 0.
 __device__ __forceinline__ float lane_from_left(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0x138, 0xf, 0xf, false));
+                                                               0x138, 0xf, 0xf, true));
 }
 // DPP wave_shl:1 -- lane i receives lane i+1; lane 63 receives 0.
 __device__ __forceinline__ float lane_from_right(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0x130, 0xf, 0xf, false));
+                                                               0x130, 0xf, 0xf, true));
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
@@ -174,110 +174,153 @@ __global__ void __launch_bounds__(256) k_rhs_down(LevelView fl, const uint8_t* _
 }
 
 // ---------------------------------------------------------------------------
-// norm reduction: per-workgroup partials, then a fixed-order finish kernel
+// norm reduction inside the pass: the last workgroup adds the partials
 // ---------------------------------------------------------------------------
+//
+// On gfx950 the L2 caches of the eight XCDs are not coherent with each other
+// and a device-scope release fence writes back the whole L2.  Instead, each
+// workgroup writes its partial with an agent-scope atomic store (written
+// through to the coherent level) and then increments a per-channel counter
+// with an agent-scope atomic.  The workgroup that sees the count reach
+// ntiles - 1 reads the partials with agent-scope atomic loads; an entry is
+// "unset" while negative (partials are sums of squares), so it waits for the
+// few that may still be in flight, adds them in index order (a result that does
+// not depend on which workgroup came last), resets every entry to -1 and the
+// counter to 0 for the next pass, and runs the optional convergence test.
+constexpr int kSpinBudget = 1 << 20;
 
-// Sum `acc` over the 256 threads of the workgroup and store it as the tile's
-// partial.  No fence or atomic: the finish kernel runs after this kernel ends.
-__device__ void store_partial(double acc, int ch, unsigned tile, unsigned ntiles, double* partials) {
-  __shared__ double red[kPassThreads / kWave];
+__device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, const NormOut& no) {
+  constexpr int NW = kPassThreads / kWave;
+  __shared__ double red[NW];
+  __shared__ int last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   acc = wave_sum_d(acc);
   if (lane == 0) red[wave] = acc;
   __syncthreads();
-  if (threadIdx.x == 0) partials[(size_t)ch * ntiles + tile] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-constexpr int kFinThreads = 512;
-
-// One workgroup per channel: total of the partials (fixed order), optional
-// convergence test, optional local-CG iteration statistics of a block solve.
-// Each thread adds the entries t, t + T, t + 2T, ... in that order, with
-// eight loads in flight.
-__global__ void __launch_bounds__(kFinThreads) k_norm_finish(NormOut no, unsigned ntiles,
-                                                            const int* __restrict__ active,
-                                                            const int* __restrict__ iters,
-                                                            unsigned nblk, LevelView lv,
-                                                            unsigned long long* __restrict__ cgstat) {
-  constexpr int T = kFinThreads, NW = kFinThreads / kWave, U = 8;
-  const int ch = blockIdx.x;
-  if (active && !active[ch]) return;
-  __shared__ double red[NW];
-  __shared__ unsigned long long ired[3][NW];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double* part = no.partials + (size_t)ch * ntiles;
+  double* part = no.partials + (size_t)ch * ntiles;
+  unsigned* cnt = no.counter + (size_t)ch * kCounterLines * 32;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += red[w];
+    __hip_atomic_store(part + tile, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // two-level count: tile -> group (tile mod 64) -> total, so that no
+    // counter sees more than ~ntiles/64 increments
+    const unsigned grp = tile % kCounterGroups;
+    const unsigned ngrp = ntiles < (unsigned)kCounterGroups ? ntiles : (unsigned)kCounterGroups;
+    const unsigned gsize = (ntiles - grp + kCounterGroups - 1) / kCounterGroups;
+    const unsigned prev =
+        __hip_atomic_fetch_add(cnt + grp * 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int l = 0;
+    if (prev == gsize - 1) {
+      const unsigned tp = __hip_atomic_fetch_add(cnt + kCounterGroups * 32, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+      l = tp == ngrp - 1;
+    }
+    last = l;
+  }
+  __syncthreads();
+  if (!last) return;
+  // Entries t, t + T, t + 2T, ... are added in that order; loads are issued in
+  // batches of U so that the coherent-level round trips overlap.
+  constexpr int U = 1;
   double s = 0.0;
-  for (unsigned base = threadIdx.x; base < ntiles; base += U * T) {
+  int spins = 0;
+  bool lost = false;
+  for (unsigned base = threadIdx.x; base < ntiles; base += U * kPassThreads) {
     double v[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      const unsigned i = base + j * T;
-      v[j] = i < ntiles ? part[i] : 0.0;
+      const unsigned i = base + j * kPassThreads;
+      v[j] = i < ntiles ? __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
     }
 #pragma unroll
-    for (int j = 0; j < U; ++j) s += v[j];
+    for (int j = 0; j < U; ++j) {
+      const unsigned i = base + j * kPassThreads;
+      if (i >= ntiles) continue;
+      while (v[j] < 0.0 && spins < kSpinBudget) {
+        __builtin_amdgcn_s_sleep(1);
+        ++spins;
+        v[j] = __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (v[j] < 0.0) {
+        lost = true;
+        v[j] = 0.0;
+      }
+      s += v[j];
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const unsigned i = base + j * kPassThreads;
+      if (i < ntiles) __hip_atomic_store(part + i, -1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
   s = wave_sum_d(s);
+  __syncthreads();
   if (lane == 0) red[wave] = s;
-  if (iters) {
-    unsigned long long isum = 0, imax = 0, ipx = 0;
-    const int S = lv.B - lv.o;
-    const int* itc = iters + (size_t)ch * nblk;
-    for (unsigned base = threadIdx.x; base < nblk; base += U * T) {
-      int v[U];
-#pragma unroll
-      for (int j = 0; j < U; ++j) {
-        const unsigned i = base + j * T;
-        v[j] = i < nblk ? itc[i] : 0;
-      }
-#pragma unroll
-      for (int j = 0; j < U; ++j) {
-        const unsigned i = base + j * T;
-        const unsigned long long it = (unsigned)v[j];
-        const int bx = (int)(i % (unsigned)lv.nbx), by = (int)(i / (unsigned)lv.nbx);
-        const int bw = min(lv.B, lv.W - bx * S), bh = min(lv.B, lv.H - by * S);
-        isum += it;
-        imax = it > imax ? it : imax;
-        if (i < nblk) ipx += it * (unsigned long long)(bw * bh);
-      }
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-      isum += __shfl_xor(isum, m);
-      const unsigned long long om = __shfl_xor(imax, m);
-      imax = om > imax ? om : imax;
-      ipx += __shfl_xor(ipx, m);
-    }
-    if (lane == 0) {
-      ired[0][wave] = isum;
-      ired[1][wave] = imax;
-      ired[2][wave] = ipx;
-    }
-  }
+  if (lost) atomicOr(no.status, 4);
   __syncthreads();
   if (threadIdx.x == 0) {
     double tot = 0.0;
     for (int w = 0; w < NW; ++w) tot += red[w];
     no.out[ch] = tot;
+    for (int gi = 0; gi < kCounterLines; ++gi)
+      __hip_atomic_store(cnt + gi * 32, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (no.check) {
       const double den = no.den[ch];
       const double rel = den > 0.0 ? sqrt(tot / den) : (tot > 0.0 ? INFINITY : 0.0);
       no.relres[ch] = rel;
       if (rel <= no.tol) no.active[ch] = 0;
     }
-    if (iters && cgstat) {
-      unsigned long long* cs = cgstat + 3 * ch;
-      unsigned long long a0 = 0, a2 = 0, mx = 0;
-      for (int w = 0; w < NW; ++w) {
-        a0 += ired[0][w];
-        a2 += ired[2][w];
-        mx = ired[1][w] > mx ? ired[1][w] : mx;
-      }
-      cs[0] += a0;
-      cs[1] = mx > cs[1] ? mx : cs[1];
-      cs[2] += a2;
+  }
+}
+
+// Local CG statistics of one level: one workgroup per channel.
+__global__ void __launch_bounds__(kPassThreads) k_cg_stats(LevelView lv, const int* __restrict__ itot,
+                                                          const int* __restrict__ imax,
+                                                          unsigned long long* __restrict__ cgstat) {
+  constexpr int NW = kPassThreads / kWave;
+  __shared__ unsigned long long red[3][NW];
+  const int ch = blockIdx.x;
+  const unsigned nblk = (unsigned)(lv.nbx * lv.nby);
+  const int S = lv.B - lv.o;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  unsigned long long isum = 0, mx = 0, ipx = 0;
+  for (unsigned i = threadIdx.x; i < nblk; i += kPassThreads) {
+    const unsigned long long it = (unsigned)itot[(size_t)ch * nblk + i];
+    const unsigned long long im = (unsigned)imax[(size_t)ch * nblk + i];
+    const int bx = (int)(i % (unsigned)lv.nbx), by = (int)(i / (unsigned)lv.nbx);
+    const int bw = min(lv.B, lv.W - bx * S), bh = min(lv.B, lv.H - by * S);
+    isum += it;
+    mx = im > mx ? im : mx;
+    ipx += it * (unsigned long long)(bw * bh);
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    isum += __shfl_xor(isum, m);
+    const unsigned long long om = __shfl_xor(mx, m);
+    mx = om > mx ? om : mx;
+    ipx += __shfl_xor(ipx, m);
+  }
+  if (lane == 0) {
+    red[0][wave] = isum;
+    red[1][wave] = mx;
+    red[2][wave] = ipx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long* cs = cgstat + 3 * ch;
+    for (int w = 0; w < NW; ++w) {
+      cs[0] += red[0][w];
+      cs[1] = red[1][w] > cs[1] ? red[1][w] : cs[1];
+      cs[2] += red[2][w];
     }
   }
+}
+
+// Sets every norm partial to -1 ("unset") once per workspace.
+__global__ void k_fill(double* p, size_t n, double v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -349,148 +392,243 @@ __global__ void __launch_bounds__(kPassThreads) k_stage(const float* __restrict_
       acc += nsum * nsum;
     }
   }
-  store_partial(acc, ch, tile, ntiles, den.partials);
+  reduce_norm(acc, ch, tile, ntiles, den);
 }
 
 // ---------------------------------------------------------------------------
 // fused grid pass
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double prolong_at(const float* __restrict__ uc, int Wc, int Hc, int Pc,
-                                             int gx, int gy) {
-  const int X = gx >> 1, Y = gy >> 1;
-  const int Xf = (gx & 1) ? min(X + 1, Wc - 1) : max(X - 1, 0);
-  const int Yf = (gy & 1) ? min(Y + 1, Hc - 1) : max(Y - 1, 0);
-  const double a = uc[(size_t)Y * Pc + X], b = uc[(size_t)Y * Pc + Xf];
-  const double c = uc[(size_t)Yf * Pc + X], d = uc[(size_t)Yf * Pc + Xf];
+// Floor division by a small positive divisor that is the same for the whole
+// grid, through a float reciprocal and one correction step (exact for n < 2^24).
+__device__ __forceinline__ int div_small(int n, int d, float rd) {
+  int q = (int)((float)n * rd);
+  q += (q + 1) * d <= n ? 1 : 0;
+  q -= q * d > n ? 1 : 0;
+  return q;
+}
+
+// Where pixel index g (along one axis) sits in the ORAS blocks: the block b1
+// whose start is the last at or before g, the local index l1 in it, whether the
+// previous block also covers g (h0), and the parts of the correction-buffer
+// offset for this axis.
+struct BlockAxis {
+  int b1, l1;
+  bool h0;
+};
+__device__ __forceinline__ BlockAxis block_axis(int g, int S, float rS, int o, int nb) {
+  BlockAxis r;
+  r.b1 = min(div_small(g, S, rS), nb - 1);
+  r.l1 = g - r.b1 * S;
+  r.h0 = r.b1 > 0 && r.l1 < o;
+  return r;
+}
+
+// Bilinear cell-centred prolongation weights along one axis: fine index g maps
+// to the nearest coarse index n and the second one f (clamped at the edge).
+__device__ __forceinline__ void prolong_axis(int g, int nc, int& n, int& f) {
+  n = g >> 1;
+  f = (g & 1) ? min(n + 1, nc - 1) : max(n - 1, 0);
+}
+
+__device__ __forceinline__ double bilinear(double a, double b, double c, double d) {
   // ((9/16 a + 3/16 b) + 3/16 c) + 1/16 d, each product and sum rounded once
   double s = __dadd_rn(__dmul_rn(0.5625, a), __dmul_rn(0.1875, b));
   s = __dadd_rn(s, __dmul_rn(0.1875, c));
   return __dadd_rn(s, __dmul_rn(0.0625, d));
 }
 
+// New iterate at (gx, gy) (inside the image) for one pass mode.  Column data
+// (cx*) is computed once per thread, row data per row.
 template <int MODE>
-__device__ __forceinline__ float new_iterate(const PassArgs& a, int ch, int gx, int gy) {
-  const LevelView& lv = a.lv;
-  const size_t o = (size_t)ch * lv.plane + (size_t)gy * lv.P + gx;
-  if constexpr (MODE == PASS_RES) {
-    return a.u_in[o];
-  } else if constexpr (MODE == PASS_UPD) {
-    const int B = lv.B, S = lv.B - lv.o;
-    const int bx1 = min(gx / S, lv.nbx - 1), lx1 = gx - bx1 * S;
-    const int by1 = min(gy / S, lv.nby - 1), ly1 = gy - by1 * S;
-    const bool hx0 = bx1 > 0 && lx1 < lv.o, hy0 = by1 > 0 && ly1 < lv.o;
-    const float* cb = a.contrib + (size_t)ch * ((size_t)lv.nbx * lv.nby * B * B);
-    auto at = [&](int by, int bx, int ly, int lx) {
-      return cb[(((size_t)by * lv.nbx + bx) * B + ly) * B + lx];
-    };
-    float d = 0.0f;
-    if (hy0) {
-      if (hx0) d += at(by1 - 1, bx1 - 1, ly1 + S, lx1 + S);
-      d += at(by1 - 1, bx1, ly1 + S, lx1);
+struct Former {
+  const PassArgs& a;
+  const float* __restrict__ uin;
+  const float* __restrict__ bb;
+  const float* __restrict__ cb;  // corrections of this channel (UPD)
+  const float* __restrict__ uc;  // coarse field of this channel (PSOL, PCORR)
+  int S, o, B, nbx, nby;
+  float rS;
+
+  __device__ Former(const PassArgs& a_, int ch) : a(a_) {
+    const LevelView& lv = a.lv;
+    uin = a.u_in + (size_t)ch * lv.plane;
+    bb = a.b + (size_t)ch * lv.plane;
+    B = lv.B;
+    S = lv.B - lv.o;
+    o = lv.o;
+    nbx = lv.nbx;
+    nby = lv.nby;
+    rS = 1.0f / (float)S;
+    cb = MODE == PASS_UPD ? a.contrib + (size_t)ch * ((size_t)nbx * nby * B * B) : nullptr;
+    uc = (MODE == PASS_PSOL || MODE == PASS_PCORR) ? a.uc + (size_t)ch * a.planec : nullptr;
+  }
+
+  struct Col {
+    int gx;
+    int cx1, cx0;  // UPD: column part of the correction offsets of blocks bx1, bx1 - 1
+    bool h0;
+    int xn, xf;    // PSOL/PCORR: coarse columns
+  };
+  __device__ Col col(int gx) const {
+    Col c;
+    c.gx = gx;
+    if constexpr (MODE == PASS_UPD) {
+      const BlockAxis ax = block_axis(gx, S, rS, o, nbx);
+      c.cx1 = ax.b1 * B * B + ax.l1;
+      c.cx0 = (ax.b1 - 1) * B * B + ax.l1 + S;
+      c.h0 = ax.h0;
     }
-    if (hx0) d += at(by1, bx1 - 1, ly1, lx1 + S);
-    d += at(by1, bx1, ly1, lx1);
-    return a.u_in[o] + d;
-  } else {
-    const size_t oc = (size_t)gy * lv.P + gx;
-    const bool known = a.c[oc] != 0;
-    if constexpr (MODE == PASS_PSOL) {
-      if (known) return a.b[o];
-      return (float)prolong_at(a.uc + (size_t)ch * a.planec, a.Wc, a.Hc, a.Pc, gx, gy);
+    if constexpr (MODE == PASS_PSOL || MODE == PASS_PCORR) prolong_axis(gx, a.Wc, c.xn, c.xf);
+    return c;
+  }
+
+  __device__ float value(const Col& c, int gy) const {
+    const LevelView& lv = a.lv;
+    const int off = gy * lv.P + c.gx;
+    if constexpr (MODE == PASS_RES) {
+      return uin[off];
+    } else if constexpr (MODE == PASS_UPD) {
+      const BlockAxis ay = block_axis(gy, S, rS, o, nby);
+      const int ry1 = ay.b1 * nbx * B * B + ay.l1 * B;
+      const int ry0 = (ay.b1 - 1) * nbx * B * B + (ay.l1 + S) * B;
+      float d = 0.0f;
+      if (ay.h0) {
+        if (c.h0) d += cb[ry0 + c.cx0];
+        d += cb[ry0 + c.cx1];
+      }
+      if (c.h0) d += cb[ry1 + c.cx0];
+      d += cb[ry1 + c.cx1];
+      return uin[off] + d;
     } else {
-      const float u = a.u_in[o];
-      if (known) return u;
-      return (float)((double)u + prolong_at(a.uc + (size_t)ch * a.planec, a.Wc, a.Hc, a.Pc, gx, gy));
+      const bool known = a.c[off] != 0;
+      int yn, yf;
+      prolong_axis(gy, a.Hc, yn, yf);
+      const double p = bilinear(uc[yn * a.Pc + c.xn], uc[yn * a.Pc + c.xf], uc[yf * a.Pc + c.xn],
+                                uc[yf * a.Pc + c.xf]);
+      if constexpr (MODE == PASS_PSOL) {
+        return known ? bb[off] : (float)p;
+      } else {
+        const float u = uin[off];
+        return known ? u : (float)((double)u + p);
+      }
     }
   }
-}
+};
 
+// One fused grid pass over a 64x32 tile of one channel.
+//   phase 1: the new iterate on the tile plus a 1-pixel halo, into LDS.  A halo
+//            pixel outside the image takes the value of the pixel it mirrors,
+//            so that the reflecting boundary needs no special case below.
+//   phase 2: write the iterate; residual r = b - u at known pixels and
+//            r = b - (4u - (l + r + up + down)) elsewhere, in float64; write it
+//            (or keep it in LDS for the fused restriction); norm partial.
 template <int MODE>
 __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tiles_x,
                                                       unsigned ntiles) {
+  constexpr int TW = kTileW + 2, TH = kTileH + 2;
+  constexpr int NG = kPassThreads / kTileW;  // row groups
+  constexpr int RJ = (TH + NG - 1) / NG;     // phase-1 rows per thread
   const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
   const int ch = lin / ntiles;
   const unsigned tile = lin - (unsigned)ch * ntiles;
   if (a.active && !a.active[ch]) return;
   const LevelView& lv = a.lv;
   const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
-  __shared__ float t[kTileH + 2][kTileW + 2];
-  for (int i = threadIdx.x; i < (kTileH + 2) * (kTileW + 2); i += kPassThreads) {
-    const int ty = i / (kTileW + 2), tx = i - ty * (kTileW + 2);
-    const int gx = x0 + tx - 1, gy = y0 + ty - 1;
-    float v = 0.0f;
-    if (gx >= 0 && gx < lv.W && gy >= 0 && gy < lv.H) v = new_iterate<MODE>(a, ch, gx, gy);
-    t[ty][tx] = v;
+  __shared__ float t[TH][TW];
+  const Former<MODE> F(a, ch);
+  const int c = threadIdx.x & (kTileW - 1), g = threadIdx.x / kTileW;
+  {
+    const auto col = F.col(min(x0 + c, lv.W - 1));
+    float v[RJ];
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) {
+      const int ty = g + NG * j;
+      const int gy = min(max(y0 - 1 + ty, 0), lv.H - 1);
+      v[j] = ty < TH ? F.value(col, gy) : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < RJ; ++j) {
+      const int ty = g + NG * j;
+      if (ty < TH) t[ty][c + 1] = v[j];
+    }
+  }
+  if (threadIdx.x < 2 * TH) {
+    // halo columns tx = 0 and tx = TW - 1
+    const int side = threadIdx.x / TH, ty = threadIdx.x - side * TH;
+    const int gx = side == 0 ? max(x0 - 1, 0) : min(x0 + kTileW, lv.W - 1);
+    const int gy = min(max(y0 - 1 + ty, 0), lv.H - 1);
+    t[ty][side == 0 ? 0 : TW - 1] = F.value(F.col(gx), gy);
   }
   __syncthreads();
-  const int tx = threadIdx.x & 63, tyg = threadIdx.x >> 6;
-  const int gx = x0 + tx;
+  constexpr int RK = kTileH / NG;  // phase-2 rows per thread
+  const int gx = x0 + c;
+  const bool colin = gx < lv.W;
   const bool rest = MODE == PASS_UPD && a.rest;
   __shared__ float rt[MODE == PASS_UPD ? kTileH : 1][MODE == PASS_UPD ? kTileW : 1];
+  float* __restrict__ uo = MODE != PASS_RES ? a.u_out + (size_t)ch * lv.plane : nullptr;
+  float* __restrict__ ro = a.r + (size_t)ch * lv.plane;
   double acc = 0.0;
 #pragma unroll
-  for (int k = 0; k < kTileH / 4; ++k) {
-    const int ty = tyg * (kTileH / 4) + k;
+  for (int k = 0; k < RK; ++k) {
+    const int ty = g * RK + k;
     const int gy = y0 + ty;
-    if (gx < lv.W && gy < lv.H) {
-      const size_t oc = (size_t)gy * lv.P + gx;
-      const size_t o = (size_t)ch * lv.plane + oc;
-      const float u = t[ty + 1][tx + 1];
-      if constexpr (MODE != PASS_RES) a.u_out[o] = u;
-      const double bb = a.b[o];
-      double r;
-      if (a.c[oc]) {
-        r = bb - (double)u;
-      } else {
-        double nsum = 0.0;
-        int n = 0;
-        if (gx > 0) { nsum += (double)t[ty + 1][tx]; ++n; }
-        if (gx < lv.W - 1) { nsum += (double)t[ty + 1][tx + 2]; ++n; }
-        if (gy > 0) { nsum += (double)t[ty][tx + 1]; ++n; }
-        if (gy < lv.H - 1) { nsum += (double)t[ty + 2][tx + 1]; ++n; }
-        r = bb - ((double)n * (double)u - nsum);
-      }
+    if (colin && gy < lv.H) {
+      const int off = gy * lv.P + gx;
+      const float u = t[ty + 1][c + 1];
+      if constexpr (MODE != PASS_RES) uo[off] = u;
+      const double bv = F.bb[off];
+      const double ud = u;
+      const double nb = ((double)t[ty + 1][c] + (double)t[ty + 1][c + 2]) +
+                        ((double)t[ty][c + 1] + (double)t[ty + 2][c + 1]);
+      const double r = a.c[off] ? bv - ud : bv - fma(4.0, ud, -nb);
       const float rf = (float)r;
       if constexpr (MODE == PASS_UPD) {
         if (rest) {
-          rt[ty][tx] = rf;
+          rt[ty][c] = rf;
           continue;
         }
       }
-      a.r[o] = rf;
+      ro[off] = rf;
       acc += r * r;
     }
   }
   if constexpr (MODE == PASS_UPD) {
     if (rest) {
-      // The tile's 32x8 coarse cells have all their children inside the tile.
+      // The tile's coarse cells have all their children inside the tile.
       __syncthreads();
-      const int X = (x0 >> 1) + (threadIdx.x & 31), Y = (y0 >> 1) + (threadIdx.x >> 5);
       const LevelView& cl = a.clv;
-      if (X < cl.W && Y < cl.H) {
-        const size_t occ = (size_t)Y * cl.P + X;
-        double v = 0.0;
-        if (!a.cc[occ]) {
-          double sr = 0.0;
-          int n = 0;
-          for (int dy = 0; dy < 2; ++dy)
-            for (int dx = 0; dx < 2; ++dx) {
-              const int y = 2 * Y + dy, x = 2 * X + dx;
-              if (y < lv.H && x < lv.W) { sr += (double)rt[y - y0][x - x0]; ++n; }
-            }
-          v = 4.0 * sr / (double)n;
+      constexpr int CW = kTileW / 2, CH = kTileH / 2;
+#pragma unroll
+      for (int q = threadIdx.x; q < CW * CH; q += kPassThreads) {
+        const int X = (x0 >> 1) + (q % CW), Y = (y0 >> 1) + (q / CW);
+        if (X < cl.W && Y < cl.H) {
+          const int occ = Y * cl.P + X;
+          double v = 0.0;
+          if (!a.cc[occ]) {
+            double sr = 0.0;
+            int n = 0;
+            for (int dy = 0; dy < 2; ++dy)
+              for (int dx = 0; dx < 2; ++dx) {
+                const int y = 2 * Y + dy, x = 2 * X + dx;
+                if (y < lv.H && x < lv.W) {
+                  sr += (double)rt[y - y0][x - x0];
+                  ++n;
+                }
+              }
+            v = 4.0 * sr / (double)n;
+          }
+          const float vf = (float)v;
+          const size_t oco = (size_t)ch * cl.plane + occ;
+          a.bc[oco] = vf;
+          a.uc0[oco] = 0.0f;
+          a.rc[oco] = vf;
+          acc += (double)vf * (double)vf;
         }
-        const float vf = (float)v;
-        const size_t oco = (size_t)ch * cl.plane + occ;
-        a.bc[oco] = vf;
-        a.uc0[oco] = 0.0f;
-        a.rc[oco] = vf;
-        acc = (double)vf * (double)vf;
       }
     }
   }
-  store_partial(acc, ch, tile, ntiles, a.norm.partials);
+  reduce_norm(acc, ch, tile, ntiles, a.norm);
 }
 
 // ---------------------------------------------------------------------------
@@ -535,7 +673,7 @@ __global__ void __launch_bounds__(kPassThreads) k_restrict(LevelView fl, const f
       acc += (double)vf * (double)vf;
     }
   }
-  store_partial(acc, ch, tile, ntiles, no.partials);
+  reduce_norm(acc, ch, tile, ntiles, no);
 }
 
 // ---------------------------------------------------------------------------
@@ -676,7 +814,11 @@ __global__ void __launch_bounds__(kWave) k_block_solve(BlockArgs a, unsigned nbl
     const int ly = cg.g * R + k;
     if (colok && ly < bh) out[ly * B + cg.lx] = wx * pou_weight(ly, lv.nby, by, B, lv.o) * v[k];
   }
-  if (a.iters && cg.lane == 0) a.iters[(size_t)ch * nblk + bi] = it;
+  if (a.itot && cg.lane == 0) {
+    const size_t ib = (size_t)ch * nblk + bi;
+    a.itot[ib] += it;
+    a.imax[ib] = max(a.imax[ib], it);
+  }
 }
 
 // The coarsest grid is a single block.  Residual in float64 from u, then CG,
@@ -741,6 +883,17 @@ dim3 px_grid(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
 
 }  // namespace
 
+hipError_t launch_cg_stats(LevelView lv, const int* itot, const int* imax, int C,
+                           unsigned long long* cgstat, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_stats, dim3(C), dim3(kPassThreads), 0, s, lv, itot, imax, cgstat);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
 size_t pass_tiles(const LevelView& lv) {
   return (size_t)((lv.W + kTileW - 1) / kTileW) * (size_t)((lv.H + kTileH - 1) / kTileH);
 }
@@ -752,10 +905,6 @@ hipError_t launch_stage(const float* f, const uint8_t* mask, int W, int H, int C
   const unsigned nt = (unsigned)pass_tiles(lv);
   hipLaunchKernelGGL(k_stage, dim3(nt * (unsigned)C), dim3(kPassThreads), 0, s, f, mask, W, H, Pf, lv,
                      c, b, u, status, den, tx, nt);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_norm_finish, dim3(C), dim3(kFinThreads), 0, s, den, nt, nullptr, nullptr, 0u,
-                     lv, nullptr);
   return hipGetLastError();
 }
 
@@ -783,12 +932,6 @@ hipError_t launch_pass(int mode, const PassArgs& a, int C, hipStream_t s) {
     case PASS_PCORR: hipLaunchKernelGGL(k_pass<PASS_PCORR>, grid, dim3(kPassThreads), 0, s, a, tx, nt); break;
     default: return hipErrorInvalidValue;
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const bool st = mode == PASS_UPD && a.iters;
-  hipLaunchKernelGGL(k_norm_finish, dim3(C), dim3(kFinThreads), 0, s, a.norm, nt, a.active,
-                     st ? a.iters : nullptr, st ? (unsigned)(a.lv.nbx * a.lv.nby) : 0u, a.lv,
-                     st ? a.cgstat : nullptr);
   return hipGetLastError();
 }
 
@@ -799,10 +942,6 @@ hipError_t launch_restrict(LevelView fine, const float* rf, LevelView coarse, co
   const unsigned nt = (unsigned)pass_tiles(coarse);
   hipLaunchKernelGGL(k_restrict, dim3(nt * (unsigned)C), dim3(kPassThreads), 0, s, fine, rf, coarse,
                      cc, bc, uc, rc, norm, active, tx, nt);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_norm_finish, dim3(C), dim3(kFinThreads), 0, s, norm, nt, active, nullptr, 0u,
-                     coarse, nullptr);
   return hipGetLastError();
 }
 

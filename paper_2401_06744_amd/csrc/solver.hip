@@ -71,8 +71,8 @@ Opts resolve(const inpaint_opts* p) {
     if (p->max_local_iters) o.maxit = p->max_local_iters;
     o.schedule = p->schedule;
     if (p->max_cycles) o.max_cycles = p->max_cycles;
-    if (p->pre_smooth) o.pre = p->pre_smooth;
-    if (p->post_smooth) o.post = p->post_smooth;
+    if (p->pre_smooth) o.pre = p->pre_smooth < 0 ? 0 : p->pre_smooth;
+    if (p->post_smooth) o.post = p->post_smooth < 0 ? 0 : p->post_smooth;
     o.rhs = p->rhs_restriction;
     if (p->coarse_tau != 0.0f) o.coarse_tau = p->coarse_tau;
     if (p->coarse_max_iters) o.coarse_maxit = p->coarse_max_iters;
@@ -87,8 +87,7 @@ Opts resolve(const inpaint_opts* p) {
     fail(INPAINT_E_INVALID, "unknown schedule");
   if (o.rhs != INPAINT_RHS_MODIFIED && o.rhs != INPAINT_RHS_NAIVE)
     fail(INPAINT_E_INVALID, "unknown rhs_restriction");
-  if (o.pre < 0 || o.post < 0 || o.pre > 16 || o.post > 16)
-    fail(INPAINT_E_INVALID, "smoothing counts must lie in [0, 16]");
+  if (o.pre > 16 || o.post > 16) fail(INPAINT_E_INVALID, "smoothing counts must be at most 16");
   if (!(o.coarse_tau >= 0.0f)) fail(INPAINT_E_INVALID, "coarse_tau must be >= 0");
   if (o.max_cycles < 0) fail(INPAINT_E_INVALID, "max_cycles must be >= 0");
   if (o.max_cycles == 0)
@@ -107,6 +106,8 @@ struct Level {
   float* u[2] = {nullptr, nullptr};
   float* r = nullptr;
   float* contrib = nullptr;
+  int* itot = nullptr;  // [C][nblk] local CG iterations per block, summed over a solve
+  int* imax = nullptr;  // [C][nblk] their maximum (itot and imax are contiguous)
   int cur = 0;
 };
 
@@ -123,8 +124,8 @@ struct Workspace {
   Level lv[kMaxLevels];
   void* base = nullptr;
   size_t bytes = 0;
-  double* partials = nullptr;
-  int* iters = nullptr;     // [C][max blocks of a level] local CG iterations per block
+  double* partials = nullptr;   // [C][max tiles], kept at -1 between passes
+  unsigned* counters = nullptr; // [C], kept at 0 between passes
   double* snorm = nullptr;  // [L][C]
   double* den = nullptr;    // [C]
   double* relres = nullptr; // [C]
@@ -179,9 +180,9 @@ std::unique_ptr<Workspace> create_workspace(const Key& k) {
     off = round_up(off + n, 256);
     return at;
   };
-  struct Offs { size_t c, b, u0, u1, r, contrib; };
+  struct Offs { size_t c, b, u0, u1, r, contrib, it; };
   std::vector<Offs> lo(ws->L);
-  size_t maxtiles = 1, maxblk = 1;
+  size_t maxtiles = 1;
   for (int l = 0; l < ws->L; ++l) {
     LevelView& v = ws->lv[l].v;
     v.W = sizes[l].first;
@@ -199,16 +200,16 @@ std::unique_ptr<Workspace> create_workspace(const Key& k) {
     lo[l].u1 = take(f);
     lo[l].r = take(f);
     lo[l].contrib = take((size_t)C * v.nbx * v.nby * k.B * k.B * sizeof(float));
+    lo[l].it = take((size_t)2 * C * v.nbx * v.nby * sizeof(int));
     maxtiles = std::max(maxtiles, pass_tiles(v));
-    maxblk = std::max(maxblk, (size_t)v.nbx * v.nby);
   }
   const size_t o_part = take((size_t)C * maxtiles * sizeof(double));
-  const size_t o_it = take((size_t)C * maxblk * sizeof(int));
+  const size_t o_cnt = take((size_t)C * kCounterLines * 32 * sizeof(unsigned));
   const size_t o_sn = take((size_t)ws->L * C * sizeof(double));
   const size_t o_den = take((size_t)C * sizeof(double));
-  const size_t o_rel = take((size_t)C * sizeof(double));
-  const size_t o_act = take((size_t)C * sizeof(int));
-  const size_t o_st = take(4 * sizeof(int));
+  // relres[4] doubles, active[4] ints, status[4] ints: one 64-byte block so
+  // that a poll is a single copy
+  const size_t o_flags = take(64);
   const size_t o_cg = take((size_t)kMaxLevels * C * 3 * sizeof(unsigned long long));
   ws->bytes = off;
   HIPCHK(hipMalloc(&ws->base, off));
@@ -221,14 +222,19 @@ std::unique_ptr<Workspace> create_workspace(const Key& k) {
     L.u[1] = (float*)(base + lo[l].u1);
     L.r = (float*)(base + lo[l].r);
     L.contrib = (float*)(base + lo[l].contrib);
+    L.itot = (int*)(base + lo[l].it);
+    L.imax = L.itot + (size_t)C * L.v.nbx * L.v.nby;
   }
   ws->partials = (double*)(base + o_part);
-  ws->iters = (int*)(base + o_it);
+  ws->counters = (unsigned*)(base + o_cnt);
+  HIPCHK(hipMemset(ws->counters, 0, (size_t)C * kCounterLines * 32 * sizeof(unsigned)));
+  HIPCHK(launch_fill(ws->partials, (size_t)C * maxtiles, -1.0, nullptr));
+  HIPCHK(hipDeviceSynchronize());
   ws->snorm = (double*)(base + o_sn);
   ws->den = (double*)(base + o_den);
-  ws->relres = (double*)(base + o_rel);
-  ws->active = (int*)(base + o_act);
-  ws->status = (int*)(base + o_st);
+  ws->relres = (double*)(base + o_flags);
+  ws->active = (int*)(base + o_flags + 32);
+  ws->status = (int*)(base + o_flags + 48);
   ws->cgstat = (unsigned long long*)(base + o_cg);
   HIPCHK(hipHostMalloc(&ws->host, 4096, hipHostMallocDefault));
   HIPCHK(hipEventCreate(&ws->ev0));
@@ -336,6 +342,8 @@ struct Run {
   NormOut norm(int l, bool check) const {
     NormOut n{};
     n.partials = ws->partials;
+    n.counter = ws->counters;
+    n.status = ws->status;
     n.out = ws->snorm + (size_t)l * C;
     n.den = ws->den;
     n.relres = ws->relres;
@@ -380,12 +388,11 @@ struct Run {
     b.tau = o.tau;
     b.maxit = o.maxit;
     b.active = ws->active;
-    b.iters = ws->iters;
+    b.itot = o.profile ? L.itot : nullptr;
+    b.imax = o.profile ? L.imax : nullptr;
     timed(INPAINT_K_BLOCK_SOLVE, l, [&] { return launch_block_solve(b, C, s); });
     PassArgs a = pass_args(l);
     a.norm = norm(l, check);
-    a.iters = ws->iters;
-    a.cgstat = ws->cgstat + (size_t)l * C * 3;
     if (rest) {
       Level& Cl = ws->lv[l + 1];
       a.rest = 1;
@@ -499,6 +506,12 @@ void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy, bool 
   const int C = R.C;
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, R.s, ws->active, ws->status, ws->cgstat, C);
   HIPCHK(hipGetLastError());
+  if (R.o.profile)
+    for (int l = 0; l < ws->L; ++l) {
+      const Level& L = ws->lv[l];
+      // two int arrays of C*nblk entries = C*nblk doubles of zero bits
+      HIPCHK(launch_fill((double*)L.itot, (size_t)C * L.v.nbx * L.v.nby, 0.0, R.s));
+    }
   Level& L0 = ws->lv[0];
   L0.cur = 0;
   // staging, input checks and the reference residual ||b - A C f|| (denominator
@@ -533,11 +546,12 @@ bool poll(Run& R, std::vector<int>& final_cur, std::vector<double>& rel) {
   Workspace* ws = R.ws;
   const int C = R.C;
   char* h = (char*)ws->host;
-  HIPCHK(hipMemcpyAsync(h, ws->active, C * sizeof(int), hipMemcpyDeviceToHost, R.s));
-  HIPCHK(hipMemcpyAsync(h + 64, ws->relres, C * sizeof(double), hipMemcpyDeviceToHost, R.s));
+  HIPCHK(hipMemcpyAsync(h, ws->relres, 64, hipMemcpyDeviceToHost, R.s));
   HIPCHK(hipStreamSynchronize(R.s));
-  const int* act = (const int*)h;
-  const double* rr = (const double*)(h + 64);
+  const double* rr = (const double*)h;
+  const int* act = (const int*)(h + 32);
+  const int* st = (const int*)(h + 48);
+  if (st[0] & 4) fail(INPAINT_E_DEVICE, "a norm partial never arrived (spin budget exhausted)");
   bool all = true;
   for (int ch = 0; ch < C; ++ch) {
     if (final_cur[ch] < 0) {
@@ -581,6 +595,10 @@ SolveResult run_solve(Run& R, float* out_d) {
   R.timed(INPAINT_K_OUTPUT, 0, [&] {
     return launch_output(ws->lv[0].v, ws->lv[0].c, ws->lv[0].b, sel, out_d, ws->key.W, C, R.s);
   });
+  if (R.o.profile)
+    for (int l = 0; l < ws->L; ++l)
+      HIPCHK(launch_cg_stats(ws->lv[l].v, ws->lv[l].itot, ws->lv[l].imax, C,
+                             ws->cgstat + (size_t)l * C * 3, R.s));
   res.cycles = cycles;
   res.rel = 0.0;
   for (int ch = 0; ch < C; ++ch) res.rel = std::max(res.rel, rel[ch]);

@@ -163,7 +163,7 @@ def test_repeatable_and_device_pointers_and_alias():
     {"schedule": binding.SCHED_FMG}, {"schedule": binding.SCHED_MULTILEVEL},
     {"block": 16, "overlap": 4}, {"overlap": 2}, {"overlap": 16, "block": 32},
     {"gamma": 1.0}, {"rhs_restriction": binding.RHS_NAIVE}, {"pre_smooth": 2, "post_smooth": 2},
-    {"post_smooth": 0, "pre_smooth": 2},
+    {"post_smooth": -1, "pre_smooth": 2}, {"pre_smooth": -1, "post_smooth": 2},
 ])
 def test_options_reach_the_same_solution(kw):
     f = synth.frame_image(180, 140, 1, seed=41)
