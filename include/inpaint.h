@@ -91,7 +91,19 @@ typedef struct inpaint_opts {
   int coarse_max_iters;/* cap on that solve (default 256) */
   int profile;         /* non-zero: time every finest-grid kernel launch with HIP events on the
                           solve's stream and report it in inpaint_stats (adds event records) */
+  int precision;       /* inpaint_precision of the correction fields (default FP32) */
 } inpaint_opts;
+
+/* Storage precision of the correction fields: the weighted block corrections on
+   every level and every field of the coarser levels.  The finest grid's iterate,
+   known values and residual stay float32, every residual is evaluated in float64
+   and all arithmetic is float32, so each V-cycle is one step of iterative
+   refinement whose correction is computed from 16-bit fields. */
+typedef enum inpaint_precision {
+  INPAINT_PREC_FP32 = 0,
+  INPAINT_PREC_FP16 = 1, /* IEEE half, stored scaled by the reference residual's rms */
+  INPAINT_PREC_BF16 = 2  /* bfloat16 */
+} inpaint_precision;
 
 /* Kernel classes reported by the profile fields of inpaint_stats. */
 typedef enum inpaint_kernel {

@@ -23,6 +23,7 @@ KERNELS = ["stage", "pyramid", "block_solve", "update", "prolong", "restrict", "
            "residual", "output"]
 SCHED_RFMG, SCHED_FMG, SCHED_MULTILEVEL, SCHED_SINGLE = 0, 1, 2, 3
 RHS_MODIFIED, RHS_NAIVE = 0, 1
+PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
 
 EXPORTED = [
     "inpaint_solve", "inpaint_solve_ex", "inpaint_rel_res", "inpaint_last_error",
@@ -37,7 +38,7 @@ class InpaintOpts(ct.Structure):
         ("gamma", ct.c_float), ("tau", ct.c_float), ("max_local_iters", ct.c_int),
         ("schedule", ct.c_int), ("max_cycles", ct.c_int), ("pre_smooth", ct.c_int),
         ("post_smooth", ct.c_int), ("rhs_restriction", ct.c_int), ("coarse_tau", ct.c_float),
-        ("coarse_max_iters", ct.c_int), ("profile", ct.c_int),
+        ("coarse_max_iters", ct.c_int), ("profile", ct.c_int), ("precision", ct.c_int),
     ]
 
 

@@ -17,6 +17,11 @@ constexpr int kMaxLevels = 24;
 constexpr int kTileW = 64;
 constexpr int kTileH = 32;
 
+// Storage precision of the correction fields (the weighted block corrections
+// on every level and every field of the coarser levels).  The finest grid's
+// iterate, known values and residual are always float32.
+enum Prec : int { PREC_F32 = 0, PREC_F16 = 1, PREC_BF16 = 2 };
+
 // One grid level as the kernels see it.  Fields are planar per channel with a
 // padded row pitch P (elements); one plane holds H*P elements.
 struct LevelView {
@@ -24,6 +29,15 @@ struct LevelView {
   size_t plane;
   int nbx, nby;  // ORAS blocks along x and y
   int B, o;      // block side and overlap (stride B - o)
+};
+
+// Scale of a field stored in 16 bits: stored = value / (f * (rel ? rho[ch] : 1)).
+// rho[ch] is the rms of the channel's reference residual, so that residuals
+// and corrections keep their magnitudes inside the float16 range at every
+// accuracy from the first cycle to the tolerance.  Ignored for float32 fields.
+struct Sc {
+  float f;
+  int rel;
 };
 
 // Per-channel norm reduction of a grid pass.  Every workgroup publishes its
@@ -41,6 +55,10 @@ struct NormOut {
   int* active;        // [C] set to 0 once relres <= tol
   double tol;
   int check;
+  // Optional (stage only): rho[ch] = sqrt(out[ch] * inv_n), the rms of the
+  // reference residual, floored to a tiny positive value.
+  float* rho;
+  double inv_n;
 };
 
 enum PassMode : int {
@@ -50,52 +68,82 @@ enum PassMode : int {
   PASS_PCORR = 3,  // u_new = u_in + (mask ? 0 : P u_c)   (coarse-grid correction)
 };
 
+// The level's own iterate, known values / right-hand side and residual are
+// float32 on the finest grid (level0 = 1) and of the correction type `prec`
+// elsewhere; corrections, the coarse field and the fused restriction's outputs
+// are always of type `prec`.
 struct PassArgs {
   LevelView lv;
+  int prec, level0;
+  // 1 when b is 0 at every unknown pixel (the level holds a solution problem,
+  // not a correction problem); b is then not read by PASS_UPD/PSOL/PCORR.
+  int solution;
   const uint8_t* c;
-  const float* b;
-  const float* u_in;
-  float* u_out;
-  float* r;
-  const float* contrib;  // PASS_UPD: [C][nby*nbx][B][B]
-  const float* uc;       // PASS_PSOL/PCORR: coarse field [C][Hc][Pc]
+  const void* b;
+  const void* u_in;
+  void* u_out;
+  void* r;
+  const void* contrib;   // PASS_UPD: [C][nby*nbx][B][B]
+  const void* uc;        // PASS_PSOL/PCORR: coarse field [C][Hc][Pc]
   int Wc, Hc, Pc;
   size_t planec;
   NormOut norm;
   const int* active;     // [C] or nullptr: skip channels already converged
   // PASS_UPD with rest != 0: instead of writing the fine residual and its norm,
-  // restrict it (Sections 4.1, 4.4) to the coarse level: write bc = uc0 = rc's
-  // right-hand side, uc0 = 0, rc = bc, and reduce the coarse norm into `norm`.
+  // restrict it (Sections 4.1, 4.4) to the coarse level: write bc = rc = the
+  // coarse right-hand side, uc0 = 0, and reduce the coarse norm into `norm`.
   int rest;
   LevelView clv;
   const uint8_t* cc;
-  float* bc;
-  float* uc0;
-  float* rc;
+  void* bc;
+  void* uc0;
+  void* rc;
+  const float* rho;      // [C]
+  Sc s_u, s_b, s_r, s_contrib, s_uc, s_cr;  // s_cr: coarse b and r of the restriction
 };
 
 struct BlockArgs {
   LevelView lv;
+  int prec, level0;
   const uint8_t* c;
-  const float* r;         // residual [C][H][P]
+  const void* r;          // residual [C][H][P] (float32 on the finest grid)
   const double* snorm;    // [C] squared global residual norm
-  float* contrib;         // [C][nby*nbx][B][B] weighted corrections D_i v_i
+  void* contrib;          // [C][nby*nbx][B][B] weighted corrections D_i v_i (type prec)
   float gamma, tau;
   int maxit;
   const int* active;
   int* itot;              // [C][nby*nbx] running total of local CG iterations per block,
   int* imax;              // and the running maximum; both nullptr to skip
+  const float* rho;
+  Sc s_r, s_contrib;
 };
 
 struct CoarseArgs {
   LevelView lv;  // a single block covers the level
+  int prec, level0;
   const uint8_t* c;
-  const float* b;
-  float* u;      // in/out
+  const void* b;
+  void* u;       // in/out
   int init;      // 1: start from u = C b;  0: continue from u
   float rel_tol; // stop when ||rho||^2 <= rel_tol * ||rho_0||^2
   int maxit;
   const int* active;
+  const float* rho;
+  Sc s_b, s_u;
+};
+
+struct RestrictArgs {
+  LevelView fl, cl;
+  int prec, level0;       // level0: the fine level is the finest grid (float32 residual)
+  const void* rf;
+  const uint8_t* cc;
+  void* bc;
+  void* uc;
+  void* rc;
+  NormOut norm;
+  const int* active;
+  const float* rho;
+  Sc s_rf, s_cr;
 };
 
 // Launchers (all enqueue on `s`, return hipError_t of the launch).
@@ -106,19 +154,16 @@ hipError_t launch_stage(const float* f, const uint8_t* mask, int W, int H, int C
                         hipStream_t s);
 hipError_t launch_mask_down(LevelView fine, const uint8_t* cf, LevelView coarse, uint8_t* cc,
                             hipStream_t s);
-hipError_t launch_rhs_down(LevelView fine, const uint8_t* cf, const float* bf, LevelView coarse,
-                           const uint8_t* cc, float* bc, int C, int naive, hipStream_t s);
+// Coarse known values (unscaled); the fine level is float32 when fine_f32.
+hipError_t launch_rhs_down(LevelView fine, const uint8_t* cf, const void* bf, LevelView coarse,
+                           const uint8_t* cc, void* bc, int C, int naive, int prec, int fine_f32,
+                           hipStream_t s);
 hipError_t launch_pass(int mode, const PassArgs& a, int C, hipStream_t s);
-hipError_t launch_restrict(LevelView fine, const float* rf, LevelView coarse, const uint8_t* cc,
-                           float* bc, float* uc, float* rc, NormOut norm, const int* active,
-                           int C, hipStream_t s);
+hipError_t launch_restrict(const RestrictArgs& a, int C, hipStream_t s);
 hipError_t launch_block_solve(const BlockArgs& a, int C, hipStream_t s);
 hipError_t launch_coarse_solve(const CoarseArgs& a, int C, hipStream_t s);
 hipError_t launch_output(LevelView lv, const uint8_t* c, const float* b,
                          const float* const* u_sel, float* out, int Pout, int C, hipStream_t s);
-hipError_t launch_copy_in(const float* src, int W, int H, int C, int Psrc, float* dst, LevelView lv,
-                          hipStream_t s);
-
 hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s);
 // cgstat[ch][3] += (sum of itot, max of imax, sum of itot x block pixels) over
 // the blocks of one level.
@@ -126,5 +171,6 @@ hipError_t launch_cg_stats(LevelView lv, const int* itot, const int* imax, int C
                            unsigned long long* cgstat, hipStream_t s);
 
 size_t pass_tiles(const LevelView& lv);
+size_t prec_bytes(int prec);
 
 }  // namespace inpaint

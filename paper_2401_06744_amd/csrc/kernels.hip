@@ -1,7 +1,11 @@
 // gfx950 kernels of the homogeneous diffusion inpainting solver.
 //
-// Every field is float32, planar per channel with a padded row pitch; the
-// mask is uint8 (1 = known).  Level l uses the integer 5-point stencil
+// Fields are planar per channel with a padded row pitch; the mask is uint8
+// (1 = known).  The finest grid's iterate, known values and residual are
+// float32; the weighted block corrections and every field of the coarser
+// levels are float32, float16 or bfloat16 ("correction precision"), with all
+// arithmetic in float32 (residuals in float64) and 16-bit fields stored scaled
+// (see Sc in kernels.h).  Level l uses the integer 5-point stencil
 // h_l^2 L (diagonal = number of in-image neighbours, -1 per neighbour), so the
 // operator of every level is  A_l = C_l + (I - C_l) h_l^2 L_l  and coarse
 // right-hand sides carry the factor (H/h)^2 = 4 (Sections 2.2 and 4.1).
@@ -10,7 +14,7 @@
 //   stage        b_0 = C f, mask normalised to 0/1, u_0 = C f, input checks
 //   mask_down    coarse mask by max pooling (Section 4.3)
 //   rhs_down     coarse known values, naive or modified (Section 4.3)
-//   pass<MODE>   one fused grid pass: form the new iterate on a 64x16 tile plus
+//   pass<MODE>   one fused grid pass: form the new iterate on a 64x32 tile plus
 //                a 1-pixel halo in LDS (ORAS update, cascade prolongation or
 //                coarse-grid correction), write it, write the float64-evaluated
 //                residual and reduce its squared norm per channel
@@ -23,11 +27,70 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace inpaint {
 namespace {
 
 constexpr int kWave = 64;
 constexpr int kPassThreads = 256;
+
+using f16 = _Float16;
+using bf16 = __bf16;
+
+template <class T>
+constexpr bool is_f32() {
+  return std::is_same<T, float>::value;
+}
+
+__device__ __forceinline__ float scale_of(Sc s, const float* rho, int ch) {
+  return s.rel ? s.f * rho[ch] : s.f;
+}
+
+// One channel of a field with element type T: load and store float values,
+// undoing and applying the channel's scale for 16-bit types.
+template <class T>
+struct Fld {
+  T* p;
+  float s, inv;
+  __device__ __forceinline__ Fld(const void* base, size_t chan_off, Sc sc, const float* rho, int ch) {
+    p = (T*)base + chan_off;
+    if constexpr (is_f32<T>()) {
+      s = inv = 1.0f;
+    } else {
+      s = scale_of(sc, rho, ch);
+      inv = 1.0f / s;
+    }
+  }
+  __device__ __forceinline__ float ld(int i) const {
+    if constexpr (is_f32<T>())
+      return p[i];
+    else
+      return (float)p[i] * s;
+  }
+  __device__ __forceinline__ void st(int i, float v) const {
+    if constexpr (is_f32<T>())
+      p[i] = v;
+    else
+      p[i] = (T)(v * inv);
+  }
+};
+
+template <class T>
+struct Tag {
+  using type = T;
+};
+
+// Calls fn(Tag<level type>, Tag<correction type>) for a precision and level.
+template <class Fn>
+hipError_t with_types(int prec, int level0, Fn&& fn) {
+  switch (prec) {
+    case PREC_F32: return fn(Tag<float>{}, Tag<float>{});
+    case PREC_F16: return level0 ? fn(Tag<float>{}, Tag<f16>{}) : fn(Tag<f16>{}, Tag<f16>{});
+    case PREC_BF16: return level0 ? fn(Tag<float>{}, Tag<bf16>{}) : fn(Tag<bf16>{}, Tag<bf16>{});
+    default: return hipErrorInvalidValue;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // cross-lane helpers
@@ -118,16 +181,17 @@ __global__ void __launch_bounds__(256) k_mask_down(LevelView fl, const uint8_t* 
 // neighbour in the same cell by the fine mask and one in an adjacent cell by
 // that cell's coarse mask; neighbours outside the image are not counted.  If
 // every weight is 0 the plain mean of the known children is used.
+template <class TF, class TC>
 __global__ void __launch_bounds__(256) k_rhs_down(LevelView fl, const uint8_t* __restrict__ cf,
-                                                  const float* __restrict__ bf, LevelView cl,
+                                                  const TF* __restrict__ bf, LevelView cl,
                                                   const uint8_t* __restrict__ cc,
-                                                  float* __restrict__ bc, int C, int naive) {
+                                                  TC* __restrict__ bc, int C, int naive) {
   const int X = blockIdx.x * 64 + (threadIdx.x & 63);
   const int Y = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (X >= cl.W || Y >= cl.H) return;
   const size_t oc = (size_t)Y * cl.P + X;
   if (!cc[oc]) {
-    for (int ch = 0; ch < C; ++ch) bc[(size_t)ch * cl.plane + oc] = 0.0f;
+    for (int ch = 0; ch < C; ++ch) bc[(size_t)ch * cl.plane + oc] = (TC)0.0f;
     return;
   }
   int wts[4];
@@ -157,10 +221,10 @@ __global__ void __launch_bounds__(256) k_rhs_down(LevelView fl, const uint8_t* _
   int wsum = 0;
   for (int k = 0; k < nk; ++k) wsum += wts[k];
   for (int ch = 0; ch < C; ++ch) {
-    const float* bp = bf + (size_t)ch * fl.plane;
+    const TF* bp = bf + (size_t)ch * fl.plane;
     double num = 0.0, plain = 0.0;
     for (int k = 0; k < nk; ++k) {
-      const double v = (double)bp[offs[k]];
+      const double v = (double)(float)bp[offs[k]];
       num += (double)wts[k] * v;
       plain += v;
     }
@@ -169,7 +233,7 @@ __global__ void __launch_bounds__(256) k_rhs_down(LevelView fl, const uint8_t* _
       val = num / (double)wsum;
     else
       val = plain / (double)(nk > 0 ? nk : 1);
-    bc[(size_t)ch * cl.plane + oc] = (float)val;
+    bc[(size_t)ch * cl.plane + oc] = (TC)(float)val;
   }
 }
 
@@ -263,6 +327,7 @@ __device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, 
     double tot = 0.0;
     for (int w = 0; w < NW; ++w) tot += red[w];
     no.out[ch] = tot;
+    if (no.rho) no.rho[ch] = (float)fmax(sqrt(tot * no.inv_n), 1e-30);
     for (int gi = 0; gi < kCounterLines; ++gi)
       __hip_atomic_store(cnt + gi * 32, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (no.check) {
@@ -439,29 +504,30 @@ __device__ __forceinline__ double bilinear(double a, double b, double c, double 
 }
 
 // New iterate at (gx, gy) (inside the image) for one pass mode.  Column data
-// (cx*) is computed once per thread, row data per row.
-template <int MODE>
+// is computed once per thread, row data per row.  TU: element type of this
+// level's iterate and known values; TC: corrections and the coarse field.
+template <int MODE, class TU, class TC>
 struct Former {
   const PassArgs& a;
-  const float* __restrict__ uin;
-  const float* __restrict__ bb;
-  const float* __restrict__ cb;  // corrections of this channel (UPD)
-  const float* __restrict__ uc;  // coarse field of this channel (PSOL, PCORR)
+  Fld<TU> uin, bb;
+  Fld<TC> cb, uc;   // corrections of this channel (UPD); coarse field (PSOL, PCORR)
   int S, o, B, nbx, nby;
   float rS;
 
-  __device__ Former(const PassArgs& a_, int ch) : a(a_) {
+  __device__ Former(const PassArgs& a_, int ch)
+      : a(a_),
+        uin(a_.u_in, (size_t)ch * a_.lv.plane, a_.s_u, a_.rho, ch),
+        bb(a_.b, (size_t)ch * a_.lv.plane, a_.s_b, a_.rho, ch),
+        cb(a_.contrib, (size_t)ch * ((size_t)a_.lv.nbx * a_.lv.nby * a_.lv.B * a_.lv.B), a_.s_contrib,
+           a_.rho, ch),
+        uc(a_.uc, (size_t)ch * a_.planec, a_.s_uc, a_.rho, ch) {
     const LevelView& lv = a.lv;
-    uin = a.u_in + (size_t)ch * lv.plane;
-    bb = a.b + (size_t)ch * lv.plane;
     B = lv.B;
     S = lv.B - lv.o;
     o = lv.o;
     nbx = lv.nbx;
     nby = lv.nby;
     rS = 1.0f / (float)S;
-    cb = MODE == PASS_UPD ? a.contrib + (size_t)ch * ((size_t)nbx * nby * B * B) : nullptr;
-    uc = (MODE == PASS_PSOL || MODE == PASS_PCORR) ? a.uc + (size_t)ch * a.planec : nullptr;
   }
 
   struct Col {
@@ -487,29 +553,29 @@ struct Former {
     const LevelView& lv = a.lv;
     const int off = gy * lv.P + c.gx;
     if constexpr (MODE == PASS_RES) {
-      return uin[off];
+      return uin.ld(off);
     } else if constexpr (MODE == PASS_UPD) {
       const BlockAxis ay = block_axis(gy, S, rS, o, nby);
       const int ry1 = ay.b1 * nbx * B * B + ay.l1 * B;
       const int ry0 = (ay.b1 - 1) * nbx * B * B + (ay.l1 + S) * B;
       float d = 0.0f;
       if (ay.h0) {
-        if (c.h0) d += cb[ry0 + c.cx0];
-        d += cb[ry0 + c.cx1];
+        if (c.h0) d += cb.ld(ry0 + c.cx0);
+        d += cb.ld(ry0 + c.cx1);
       }
-      if (c.h0) d += cb[ry1 + c.cx0];
-      d += cb[ry1 + c.cx1];
-      return uin[off] + d;
+      if (c.h0) d += cb.ld(ry1 + c.cx0);
+      d += cb.ld(ry1 + c.cx1);
+      return uin.ld(off) + d;
     } else {
       const bool known = a.c[off] != 0;
       int yn, yf;
       prolong_axis(gy, a.Hc, yn, yf);
-      const double p = bilinear(uc[yn * a.Pc + c.xn], uc[yn * a.Pc + c.xf], uc[yf * a.Pc + c.xn],
-                                uc[yf * a.Pc + c.xf]);
+      const double p = bilinear(uc.ld(yn * a.Pc + c.xn), uc.ld(yn * a.Pc + c.xf),
+                                uc.ld(yf * a.Pc + c.xn), uc.ld(yf * a.Pc + c.xf));
       if constexpr (MODE == PASS_PSOL) {
-        return known ? bb[off] : (float)p;
+        return known ? bb.ld(off) : (float)p;
       } else {
-        const float u = uin[off];
+        const float u = uin.ld(off);
         return known ? u : (float)((double)u + p);
       }
     }
@@ -523,7 +589,7 @@ struct Former {
 //   phase 2: write the iterate; residual r = b - u at known pixels and
 //            r = b - (4u - (l + r + up + down)) elsewhere, in float64; write it
 //            (or keep it in LDS for the fused restriction); norm partial.
-template <int MODE>
+template <int MODE, class TU, class TC>
 __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tiles_x,
                                                       unsigned ntiles) {
   constexpr int TW = kTileW + 2, TH = kTileH + 2;
@@ -536,7 +602,7 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tile
   const LevelView& lv = a.lv;
   const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
   __shared__ float t[TH][TW];
-  const Former<MODE> F(a, ch);
+  const Former<MODE, TU, TC> F(a, ch);
   const int c = threadIdx.x & (kTileW - 1), g = threadIdx.x / kTileW;
   {
     const auto col = F.col(min(x0 + c, lv.W - 1));
@@ -566,8 +632,8 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tile
   const bool colin = gx < lv.W;
   const bool rest = MODE == PASS_UPD && a.rest;
   __shared__ float rt[MODE == PASS_UPD ? kTileH : 1][MODE == PASS_UPD ? kTileW : 1];
-  float* __restrict__ uo = MODE != PASS_RES ? a.u_out + (size_t)ch * lv.plane : nullptr;
-  float* __restrict__ ro = a.r + (size_t)ch * lv.plane;
+  const Fld<TU> uo(a.u_out, (size_t)ch * lv.plane, a.s_u, a.rho, ch);
+  const Fld<TU> ro(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < RK; ++k) {
@@ -576,12 +642,22 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tile
     if (colin && gy < lv.H) {
       const int off = gy * lv.P + gx;
       const float u = t[ty + 1][c + 1];
-      if constexpr (MODE != PASS_RES) uo[off] = u;
-      const double bv = F.bb[off];
+      if constexpr (MODE != PASS_RES) uo.st(off, u);
       const double ud = u;
       const double nb = ((double)t[ty + 1][c] + (double)t[ty + 1][c + 2]) +
                         ((double)t[ty][c + 1] + (double)t[ty + 2][c + 1]);
-      const double r = a.c[off] ? bv - ud : bv - fma(4.0, ud, -nb);
+      const bool known = a.c[off] != 0;
+      double r;
+      if constexpr (MODE == PASS_RES) {
+        const double bv = F.bb.ld(off);
+        r = known ? bv - ud : bv - fma(4.0, ud, -nb);
+      } else {
+        // Every pass but the residual-only one leaves u == b at known pixels, so
+        // the residual there is exactly 0; and b is 0 at the unknown pixels of a
+        // solution problem, so it is read only for correction problems.
+        const double bv = a.solution ? 0.0 : (double)F.bb.ld(off);
+        r = known ? 0.0 : bv - fma(4.0, ud, -nb);
+      }
       const float rf = (float)r;
       if constexpr (MODE == PASS_UPD) {
         if (rest) {
@@ -589,7 +665,7 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tile
           continue;
         }
       }
-      ro[off] = rf;
+      ro.st(off, rf);
       acc += r * r;
     }
   }
@@ -598,6 +674,9 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tile
       // The tile's coarse cells have all their children inside the tile.
       __syncthreads();
       const LevelView& cl = a.clv;
+      const Fld<TC> bco(a.bc, (size_t)ch * cl.plane, a.s_cr, a.rho, ch);
+      const Fld<TC> rco(a.rc, (size_t)ch * cl.plane, a.s_cr, a.rho, ch);
+      const Fld<TC> uco(a.uc0, (size_t)ch * cl.plane, a.s_cr, a.rho, ch);
       constexpr int CW = kTileW / 2, CH = kTileH / 2;
 #pragma unroll
       for (int q = threadIdx.x; q < CW * CH; q += kPassThreads) {
@@ -619,10 +698,9 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tile
             v = 4.0 * sr / (double)n;
           }
           const float vf = (float)v;
-          const size_t oco = (size_t)ch * cl.plane + occ;
-          a.bc[oco] = vf;
-          a.uc0[oco] = 0.0f;
-          a.rc[oco] = vf;
+          bco.st(occ, vf);
+          uco.st(occ, 0.0f);
+          rco.st(occ, vf);
           acc += (double)vf * (double)vf;
         }
       }
@@ -635,45 +713,46 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tile
 // residual restriction (Sections 4.1, 4.4)
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kPassThreads) k_restrict(LevelView fl, const float* __restrict__ rf,
-                                                          LevelView cl, const uint8_t* __restrict__ cc,
-                                                          float* __restrict__ bc, float* __restrict__ uc,
-                                                          float* __restrict__ rc, NormOut no,
-                                                          const int* __restrict__ active,
-                                                          unsigned tiles_x, unsigned ntiles) {
+template <class TF, class TC>
+__global__ void __launch_bounds__(kPassThreads) k_restrict(RestrictArgs a, unsigned tiles_x,
+                                                          unsigned ntiles) {
   const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
   const int ch = lin / ntiles;
   const unsigned tile = lin - (unsigned)ch * ntiles;
-  if (active && !active[ch]) return;
+  if (a.active && !a.active[ch]) return;
+  const LevelView& fl = a.fl;
+  const LevelView& cl = a.cl;
   const int X = (int)(tile % tiles_x) * kTileW + (threadIdx.x & 63);
   const int Yb = (int)(tile / tiles_x) * kTileH + (threadIdx.x >> 6) * (kTileH / 4);
   double acc = 0.0;
-  const float* r = rf + (size_t)ch * fl.plane;
+  const Fld<TF> r(a.rf, (size_t)ch * fl.plane, a.s_rf, a.rho, ch);
+  const Fld<TC> bc(a.bc, (size_t)ch * cl.plane, a.s_cr, a.rho, ch);
+  const Fld<TC> uc(a.uc, (size_t)ch * cl.plane, a.s_cr, a.rho, ch);
+  const Fld<TC> rc(a.rc, (size_t)ch * cl.plane, a.s_cr, a.rho, ch);
 #pragma unroll
   for (int k = 0; k < kTileH / 4; ++k) {
     const int Y = Yb + k;
     if (X < cl.W && Y < cl.H) {
-      const size_t oc = (size_t)Y * cl.P + X;
+      const int oc = Y * cl.P + X;
       double v = 0.0;
-      if (!cc[oc]) {
+      if (!a.cc[oc]) {
         double s = 0.0;
         int n = 0;
         for (int dy = 0; dy < 2; ++dy)
           for (int dx = 0; dx < 2; ++dx) {
             const int y = 2 * Y + dy, x = 2 * X + dx;
-            if (y < fl.H && x < fl.W) { s += (double)r[(size_t)y * fl.P + x]; ++n; }
+            if (y < fl.H && x < fl.W) { s += (double)r.ld(y * fl.P + x); ++n; }
           }
         v = 4.0 * s / (double)n;
       }
       const float vf = (float)v;
-      const size_t o = (size_t)ch * cl.plane + oc;
-      bc[o] = vf;
-      uc[o] = 0.0f;
-      rc[o] = vf;
+      bc.st(oc, vf);
+      uc.st(oc, 0.0f);
+      rc.st(oc, vf);
       acc += (double)vf * (double)vf;
     }
   }
-  reduce_norm(acc, ch, tile, ntiles, no);
+  reduce_norm(acc, ch, tile, ntiles, a.norm);
 }
 
 // ---------------------------------------------------------------------------
@@ -782,7 +861,7 @@ __device__ __forceinline__ float pou_weight(int l, int nb, int k, int B, int o) 
   return 1.0f;
 }
 
-template <int B>
+template <int B, class TR, class TC>
 __global__ void __launch_bounds__(kWave) k_block_solve(BlockArgs a, unsigned nblk) {
   const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
   const int ch = lin / nblk;
@@ -797,22 +876,23 @@ __global__ void __launch_bounds__(kWave) k_block_solve(BlockArgs a, unsigned nbl
   cg.setup(x0, y0, bw, bh, lv.W, lv.H, a.gamma, a.c, lv.P);
   constexpr int R = BlockCG<B>::R;
   float rho[R], v[R];
-  const float* r = a.r + (size_t)ch * lv.plane;
+  const Fld<TR> r(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);
   const bool colok = cg.lx < bw;
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int ly = cg.g * R + k;
-    rho[k] = (colok && ly < bh) ? r[(size_t)(y0 + ly) * lv.P + x0 + cg.lx] : 0.0f;
+    rho[k] = (colok && ly < bh) ? r.ld((y0 + ly) * lv.P + x0 + cg.lx) : 0.0f;
   }
   const double frac = (double)bw * (double)bh / ((double)lv.W * (double)lv.H);
   const float thr = (float)((double)a.tau * a.snorm[ch] * frac);
   const int it = cg.solve(rho, v, thr, a.maxit);
-  float* out = a.contrib + (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B;
+  const Fld<TC> out(a.contrib, (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B,
+                    a.s_contrib, a.rho, ch);
   const float wx = pou_weight(cg.lx, lv.nbx, bx, B, lv.o);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int ly = cg.g * R + k;
-    if (colok && ly < bh) out[ly * B + cg.lx] = wx * pou_weight(ly, lv.nby, by, B, lv.o) * v[k];
+    if (colok && ly < bh) out.st(ly * B + cg.lx, wx * pou_weight(ly, lv.nby, by, B, lv.o) * v[k]);
   }
   if (a.itot && cg.lane == 0) {
     const size_t ib = (size_t)ch * nblk + bi;
@@ -823,7 +903,7 @@ __global__ void __launch_bounds__(kWave) k_block_solve(BlockArgs a, unsigned nbl
 
 // The coarsest grid is a single block.  Residual in float64 from u, then CG,
 // then u += v.  One wavefront per channel.
-template <int B>
+template <int B, class T>
 __global__ void __launch_bounds__(kWave) k_coarse_solve(CoarseArgs a) {
   const int ch = blockIdx.x;
   if (a.active && !a.active[ch]) return;
@@ -833,17 +913,17 @@ __global__ void __launch_bounds__(kWave) k_coarse_solve(CoarseArgs a) {
   constexpr int R = BlockCG<B>::R;
   const bool colok = cg.lx < lv.W;
   float u[R], bb[R], known[R];
-  const float* bp = a.b + (size_t)ch * lv.plane;
-  float* up = a.u + (size_t)ch * lv.plane;
+  const Fld<T> bp(a.b, (size_t)ch * lv.plane, a.s_b, a.rho, ch);
+  const Fld<T> up(a.u, (size_t)ch * lv.plane, a.s_u, a.rho, ch);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int ly = cg.g * R + k;
     const bool ok = colok && ly < lv.H;
-    const size_t o = (size_t)ly * lv.P + cg.lx;
+    const int o = ly * lv.P + cg.lx;
     const bool kn = ok && a.c[o] != 0;
     known[k] = kn ? 1.0f : 0.0f;
-    bb[k] = ok ? bp[o] : 0.0f;
-    u[k] = ok ? (a.init ? (kn ? bb[k] : 0.0f) : up[o]) : 0.0f;
+    bb[k] = ok ? bp.ld(o) : 0.0f;
+    u[k] = ok ? (a.init ? (kn ? bb[k] : 0.0f) : up.ld(o)) : 0.0f;
   }
   // residual r = b - A u (float64 arithmetic), 0 at known pixels
   float rho[R];
@@ -871,10 +951,7 @@ __global__ void __launch_bounds__(kWave) k_coarse_solve(CoarseArgs a) {
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int ly = cg.g * R + k;
-    if (colok && ly < lv.H) {
-      const size_t o = (size_t)ly * lv.P + cg.lx;
-      up[o] = known[k] != 0.0f ? bb[k] : u[k] + v[k];
-    }
+    if (colok && ly < lv.H) up.st(ly * lv.P + cg.lx, known[k] != 0.0f ? bb[k] : u[k] + v[k]);
   }
   (void)it;
 }
@@ -914,59 +991,86 @@ hipError_t launch_mask_down(LevelView fine, const uint8_t* cf, LevelView coarse,
   return hipGetLastError();
 }
 
-hipError_t launch_rhs_down(LevelView fine, const uint8_t* cf, const float* bf, LevelView coarse,
-                           const uint8_t* cc, float* bc, int C, int naive, hipStream_t s) {
-  hipLaunchKernelGGL(k_rhs_down, px_grid(coarse.W, coarse.H), dim3(256), 0, s, fine, cf, bf, coarse,
-                     cc, bc, C, naive);
-  return hipGetLastError();
+hipError_t launch_rhs_down(LevelView fine, const uint8_t* cf, const void* bf, LevelView coarse,
+                           const uint8_t* cc, void* bc, int C, int naive, int prec, int fine_f32,
+                           hipStream_t s) {
+  return with_types(prec, fine_f32, [&](auto tf, auto tc) {
+    using TF = typename decltype(tf)::type;
+    using TC = typename decltype(tc)::type;
+    hipLaunchKernelGGL((k_rhs_down<TF, TC>), px_grid(coarse.W, coarse.H), dim3(256), 0, s, fine, cf,
+                       (const TF*)bf, coarse, cc, (TC*)bc, C, naive);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_pass(int mode, const PassArgs& a, int C, hipStream_t s) {
   const unsigned tx = (a.lv.W + kTileW - 1) / kTileW;
   const unsigned nt = (unsigned)pass_tiles(a.lv);
   const dim3 grid(nt * (unsigned)C);
-  switch (mode) {
-    case PASS_RES: hipLaunchKernelGGL(k_pass<PASS_RES>, grid, dim3(kPassThreads), 0, s, a, tx, nt); break;
-    case PASS_UPD: hipLaunchKernelGGL(k_pass<PASS_UPD>, grid, dim3(kPassThreads), 0, s, a, tx, nt); break;
-    case PASS_PSOL: hipLaunchKernelGGL(k_pass<PASS_PSOL>, grid, dim3(kPassThreads), 0, s, a, tx, nt); break;
-    case PASS_PCORR: hipLaunchKernelGGL(k_pass<PASS_PCORR>, grid, dim3(kPassThreads), 0, s, a, tx, nt); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return with_types(a.prec, a.level0, [&](auto tu, auto tc) {
+    using TU = typename decltype(tu)::type;
+    using TC = typename decltype(tc)::type;
+    switch (mode) {
+      case PASS_RES:
+        hipLaunchKernelGGL((k_pass<PASS_RES, TU, TC>), grid, dim3(kPassThreads), 0, s, a, tx, nt);
+        break;
+      case PASS_UPD:
+        hipLaunchKernelGGL((k_pass<PASS_UPD, TU, TC>), grid, dim3(kPassThreads), 0, s, a, tx, nt);
+        break;
+      case PASS_PSOL:
+        hipLaunchKernelGGL((k_pass<PASS_PSOL, TU, TC>), grid, dim3(kPassThreads), 0, s, a, tx, nt);
+        break;
+      case PASS_PCORR:
+        hipLaunchKernelGGL((k_pass<PASS_PCORR, TU, TC>), grid, dim3(kPassThreads), 0, s, a, tx, nt);
+        break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  });
 }
 
-hipError_t launch_restrict(LevelView fine, const float* rf, LevelView coarse, const uint8_t* cc,
-                           float* bc, float* uc, float* rc, NormOut norm, const int* active,
-                           int C, hipStream_t s) {
-  const unsigned tx = (coarse.W + kTileW - 1) / kTileW;
-  const unsigned nt = (unsigned)pass_tiles(coarse);
-  hipLaunchKernelGGL(k_restrict, dim3(nt * (unsigned)C), dim3(kPassThreads), 0, s, fine, rf, coarse,
-                     cc, bc, uc, rc, norm, active, tx, nt);
-  return hipGetLastError();
+hipError_t launch_restrict(const RestrictArgs& a, int C, hipStream_t s) {
+  const unsigned tx = (a.cl.W + kTileW - 1) / kTileW;
+  const unsigned nt = (unsigned)pass_tiles(a.cl);
+  return with_types(a.prec, a.level0, [&](auto tf, auto tc) {
+    using TF = typename decltype(tf)::type;
+    using TC = typename decltype(tc)::type;
+    hipLaunchKernelGGL((k_restrict<TF, TC>), dim3(nt * (unsigned)C), dim3(kPassThreads), 0, s, a, tx, nt);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_block_solve(const BlockArgs& a, int C, hipStream_t s) {
   const unsigned nblk = (unsigned)a.lv.nbx * (unsigned)a.lv.nby;
   const dim3 grid(nblk * (unsigned)C);
-  if (a.lv.B == 32)
-    hipLaunchKernelGGL(k_block_solve<32>, grid, dim3(kWave), 0, s, a, nblk);
-  else if (a.lv.B == 16)
-    hipLaunchKernelGGL(k_block_solve<16>, grid, dim3(kWave), 0, s, a, nblk);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  return with_types(a.prec, a.level0, [&](auto tr, auto tc) {
+    using TR = typename decltype(tr)::type;
+    using TC = typename decltype(tc)::type;
+    if (a.lv.B == 32)
+      hipLaunchKernelGGL((k_block_solve<32, TR, TC>), grid, dim3(kWave), 0, s, a, nblk);
+    else if (a.lv.B == 16)
+      hipLaunchKernelGGL((k_block_solve<16, TR, TC>), grid, dim3(kWave), 0, s, a, nblk);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_coarse_solve(const CoarseArgs& a, int C, hipStream_t s) {
   if (a.lv.W > a.lv.B || a.lv.H > a.lv.B) return hipErrorInvalidValue;
-  if (a.lv.B == 32)
-    hipLaunchKernelGGL(k_coarse_solve<32>, dim3(C), dim3(kWave), 0, s, a);
-  else if (a.lv.B == 16)
-    hipLaunchKernelGGL(k_coarse_solve<16>, dim3(C), dim3(kWave), 0, s, a);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  return with_types(a.prec, a.level0, [&](auto tu, auto) {
+    using T = typename decltype(tu)::type;
+    if (a.lv.B == 32)
+      hipLaunchKernelGGL((k_coarse_solve<32, T>), dim3(C), dim3(kWave), 0, s, a);
+    else if (a.lv.B == 16)
+      hipLaunchKernelGGL((k_coarse_solve<16, T>), dim3(C), dim3(kWave), 0, s, a);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  });
 }
+
+size_t prec_bytes(int prec) { return prec == PREC_F32 ? 4 : 2; }
 
 hipError_t launch_output(LevelView lv, const uint8_t* c, const float* b, const float* const* u_sel,
                          float* out, int Pout, int C, hipStream_t s) {

@@ -57,6 +57,7 @@ struct Opts {
   float coarse_tau = 1e-8f;
   int coarse_maxit = 256;
   int profile = 0;
+  int prec = PREC_F32;
 };
 
 Opts resolve(const inpaint_opts* p) {
@@ -77,7 +78,10 @@ Opts resolve(const inpaint_opts* p) {
     if (p->coarse_tau != 0.0f) o.coarse_tau = p->coarse_tau;
     if (p->coarse_max_iters) o.coarse_maxit = p->coarse_max_iters;
     o.profile = p->profile;
+    o.prec = p->precision;
   }
+  if (o.prec != PREC_F32 && o.prec != PREC_F16 && o.prec != PREC_BF16)
+    fail(INPAINT_E_INVALID, "unknown precision");
   if (o.B != 16 && o.B != 32) fail(INPAINT_E_INVALID, "block must be 16 or 32");
   if (o.o < 2 || 2 * o.o > o.B) fail(INPAINT_E_INVALID, "overlap must satisfy 2 <= overlap <= block/2");
   if (!(o.gamma > 0.0f && o.gamma <= 1.0f)) fail(INPAINT_E_INVALID, "gamma must lie in (0, 1]");
@@ -112,9 +116,10 @@ struct Level {
 };
 
 struct Key {
-  int dev, W, H, C, B, o, coarsest;
+  int dev, W, H, C, B, o, coarsest, prec;
   bool operator<(const Key& k) const {
-    return std::tie(dev, W, H, C, B, o, coarsest) < std::tie(k.dev, k.W, k.H, k.C, k.B, k.o, k.coarsest);
+    return std::tie(dev, W, H, C, B, o, coarsest, prec) <
+           std::tie(k.dev, k.W, k.H, k.C, k.B, k.o, k.coarsest, k.prec);
   }
 };
 
@@ -128,6 +133,7 @@ struct Workspace {
   unsigned* counters = nullptr; // [C], kept at 0 between passes
   double* snorm = nullptr;  // [L][C]
   double* den = nullptr;    // [C]
+  float* rho = nullptr;     // [C] rms of the reference residual (scale of 16-bit fields)
   double* relres = nullptr; // [C]
   int* active = nullptr;    // [C]
   int* status = nullptr;    // [4]
@@ -193,13 +199,16 @@ std::unique_ptr<Workspace> create_workspace(const Key& k) {
     v.o = k.o;
     v.nbx = num_blocks_axis(v.W, k.B, k.o);
     v.nby = num_blocks_axis(v.H, k.B, k.o);
-    const size_t f = (size_t)C * v.plane * sizeof(float);
+    // the finest grid keeps float32 iterate, known values and residual; the
+    // corrections and all coarser fields use the correction precision
+    const size_t es = prec_bytes(k.prec);
+    const size_t f = (size_t)C * v.plane * (l == 0 ? sizeof(float) : es);
     lo[l].c = take(v.plane);
     lo[l].b = take(f);
     lo[l].u0 = take(f);
     lo[l].u1 = take(f);
     lo[l].r = take(f);
-    lo[l].contrib = take((size_t)C * v.nbx * v.nby * k.B * k.B * sizeof(float));
+    lo[l].contrib = take((size_t)C * v.nbx * v.nby * k.B * k.B * es);
     lo[l].it = take((size_t)2 * C * v.nbx * v.nby * sizeof(int));
     maxtiles = std::max(maxtiles, pass_tiles(v));
   }
@@ -207,6 +216,7 @@ std::unique_ptr<Workspace> create_workspace(const Key& k) {
   const size_t o_cnt = take((size_t)C * kCounterLines * 32 * sizeof(unsigned));
   const size_t o_sn = take((size_t)ws->L * C * sizeof(double));
   const size_t o_den = take((size_t)C * sizeof(double));
+  const size_t o_rho = take((size_t)C * sizeof(float));
   // relres[4] doubles, active[4] ints, status[4] ints: one 64-byte block so
   // that a poll is a single copy
   const size_t o_flags = take(64);
@@ -232,6 +242,7 @@ std::unique_ptr<Workspace> create_workspace(const Key& k) {
   HIPCHK(hipDeviceSynchronize());
   ws->snorm = (double*)(base + o_sn);
   ws->den = (double*)(base + o_den);
+  ws->rho = (float*)(base + o_rho);
   ws->relres = (double*)(base + o_flags);
   ws->active = (int*)(base + o_flags + 32);
   ws->status = (int*)(base + o_flags + 48);
@@ -258,10 +269,10 @@ struct Lease {
   }
 };
 
-void acquire(Lease& lease, int W, int H, int C, int B, int o, int coarsest) {
+void acquire(Lease& lease, int W, int H, int C, int B, int o, int coarsest, int prec = PREC_F32) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
-  const Key k{dev, W, H, C, B, o, coarsest};
+  const Key k{dev, W, H, C, B, o, coarsest, prec};
   {
     std::lock_guard<std::mutex> g(g_mu);
     for (auto& w : g_cache[k])
@@ -311,6 +322,7 @@ struct Run {
   long oras_iters = 0;
   long block_solves = 0;
   long long finest_block_solves = 0;
+  int top = 0;  // level whose b holds known values (a solution problem); coarser ones hold corrections
   struct Rec { int cls; hipEvent_t a, b; };
   std::vector<Rec> recs;
   size_t next_ev = 0;
@@ -353,10 +365,29 @@ struct Run {
     return n;
   }
 
+  // Scales of 16-bit fields (kernels.h, Sc), relative to the reference
+  // residual's rms rho: residuals and right-hand sides of level l carry the
+  // integer stencil's factor 4^l; errors and corrections do not.  Fields of a
+  // solution problem (iterate, known values: grey levels) are not scaled.
+  static constexpr float kRes = 1e-3f, kErr = 1e-2f;
+  static Sc sc_res(int l) { return Sc{kRes * std::ldexp(1.0f, 2 * l), 1}; }
+  static Sc sc_err() { return Sc{kErr, 1}; }
+  static Sc sc_one() { return Sc{1.0f, 0}; }
+  int prec() const { return ws->key.prec; }
+
   PassArgs pass_args(int l) const {
     const Level& L = ws->lv[l];
     PassArgs a{};
     a.lv = L.v;
+    a.prec = prec();
+    a.level0 = l == 0;
+    a.solution = l == top ? 1 : 0;
+    a.rho = ws->rho;
+    a.s_u = a.solution ? sc_one() : sc_err();
+    a.s_b = a.solution ? sc_one() : sc_res(l);
+    a.s_r = sc_res(l);
+    a.s_contrib = sc_err();
+    a.s_cr = sc_res(l + 1);
     a.c = L.c;
     a.b = L.b;
     a.u_in = L.u[L.cur];
@@ -380,6 +411,11 @@ struct Run {
     Level& L = ws->lv[l];
     BlockArgs b{};
     b.lv = L.v;
+    b.prec = prec();
+    b.level0 = l == 0;
+    b.rho = ws->rho;
+    b.s_r = sc_res(l);
+    b.s_contrib = sc_err();
     b.c = L.c;
     b.r = L.r;
     b.snorm = ws->snorm + (size_t)l * C;
@@ -415,6 +451,8 @@ struct Run {
     const Level& Lc = ws->lv[l + 1];
     PassArgs a = pass_args(l);
     a.uc = Lc.u[Lc.cur];
+    // the coarse field is a solution in the cascade and a correction in a V-cycle
+    a.s_uc = mode == PASS_PSOL ? sc_one() : sc_err();
     a.Wc = Lc.v.W;
     a.Hc = Lc.v.H;
     a.Pc = Lc.v.P;
@@ -427,16 +465,34 @@ struct Run {
   void restrict_to(int l) {
     const Level& F = ws->lv[l];
     Level& Cl = ws->lv[l + 1];
-    const NormOut n = norm(l + 1, false);
-    timed(INPAINT_K_RESTRICT, l, [&] {
-      return launch_restrict(F.v, F.r, Cl.v, Cl.c, Cl.b, Cl.u[Cl.cur], Cl.r, n, ws->active, C, s);
-    });
+    RestrictArgs a{};
+    a.fl = F.v;
+    a.cl = Cl.v;
+    a.prec = prec();
+    a.level0 = l == 0;
+    a.rf = F.r;
+    a.cc = Cl.c;
+    a.bc = Cl.b;
+    a.uc = Cl.u[Cl.cur];
+    a.rc = Cl.r;
+    a.norm = norm(l + 1, false);
+    a.active = ws->active;
+    a.rho = ws->rho;
+    a.s_rf = sc_res(l);
+    a.s_cr = sc_res(l + 1);
+    timed(INPAINT_K_RESTRICT, l, [&] { return launch_restrict(a, C, s); });
   }
 
   void coarse(int l, bool init) {
     Level& L = ws->lv[l];
     CoarseArgs a{};
     a.lv = L.v;
+    a.prec = prec();
+    a.level0 = l == 0;
+    a.rho = ws->rho;
+    const bool sol = l == top;
+    a.s_b = sol ? sc_one() : sc_res(l);
+    a.s_u = sol ? sc_one() : sc_err();
     a.c = L.c;
     a.b = L.b;
     a.u = L.u[L.cur];
@@ -474,8 +530,10 @@ struct Run {
       residual(0, true);
       return;
     }
+    top = Lc;
     coarse(Lc, true);
     for (int l = Lc - 1; l >= 0; --l) {
+      top = l;
       prolong(l, PASS_PSOL, l == 0);
       if (l == 0) break;
       if (o.schedule == INPAINT_SCHED_FMG)
@@ -518,6 +576,8 @@ void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy, bool 
   // of the relative residual)
   NormOut den = R.norm(0, false);
   den.out = ws->den;
+  den.rho = ws->rho;
+  den.inv_n = 1.0 / ((double)ws->key.W * (double)ws->key.H);
   R.timed(INPAINT_K_STAGE, 0, [&] {
     return launch_stage(f_d, m_d, ws->key.W, ws->key.H, C, ws->key.W, L0.v, L0.c, L0.b,
                         (write_u || ws->L == 1) ? L0.u[0] : nullptr, ws->status, den, R.s);
@@ -530,7 +590,7 @@ void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy, bool 
       R.timed(INPAINT_K_PYRAMID, l, [&] { return launch_mask_down(F.v, F.c, Cl.v, Cl.c, R.s); });
       R.timed(INPAINT_K_PYRAMID, l, [&] {
         return launch_rhs_down(F.v, F.c, F.b, Cl.v, Cl.c, Cl.b, C,
-                               R.o.rhs == INPAINT_RHS_NAIVE ? 1 : 0, R.s);
+                               R.o.rhs == INPAINT_RHS_NAIVE ? 1 : 0, R.prec(), l == 0 ? 1 : 0, R.s);
       });
     }
   }
@@ -635,7 +695,7 @@ int solve_impl(const float* f, const uint8_t* mask, int W, int H, int C, double 
   if (overlap(out, nf, mask, (size_t)W * H)) fail(INPAINT_E_INVALID, "out overlaps mask");
   hipStream_t s = (hipStream_t)stream;
   Lease lease;
-  acquire(lease, W, H, C, o.B, o.o, o.B);
+  acquire(lease, W, H, C, o.B, o.o, o.B, o.prec);
   Workspace* ws = lease.ws;
   const bool fd = is_device_ptr(f), md = is_device_ptr(mask), od = is_device_ptr(out);
   if (!fd || !md || !od) ensure_staging(ws);

@@ -47,6 +47,6 @@ def test_host_only_calls_without_gpu():
 
 
 def test_opts_struct_layout_matches_header():
-    # 14 fields of 4 bytes each
-    assert ctypes.sizeof(binding.InpaintOpts) == 14 * 4
+    # 15 fields of 4 bytes each
+    assert ctypes.sizeof(binding.InpaintOpts) == 15 * 4
     assert ctypes.sizeof(binding.InpaintStats) == 8 + 3 * 4 + 4 + 8 + 4 + 4 + 8 + 8 + 8 + 9 * 4 + 9 * 4

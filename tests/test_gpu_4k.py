@@ -15,24 +15,28 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.timeout(900)
 def test_4k_rgb_matches_oracle():
+    """All three storage precisions of the correction fields (float32, float16,
+    bfloat16) on the same frame and the same oracle solution."""
     import torch
 
     f, m = synth.config_4k()
     fd = torch.from_numpy(f).cuda()
     md = torch.from_numpy(m).cuda()
-    out, st, stats = binding.inpaint_solve_ex(fd, md, 1e-6)
-    torch.cuda.synchronize()
-    assert st == binding.OK
-    assert stats["levels"] == 8
-    u = out.cpu().numpy()
     k = m != 0
-    rr = oracle.rel_res(u.astype(np.float64), f.astype(np.float64), m)
-    print(f"4K rel_res per channel {rr} cycles {stats['cycles']}", flush=True)
-    assert np.all(rr <= 1e-6), rr
-    for ch in range(3):
-        assert np.array_equal(u[ch][k], f[ch][k])
-        assert u[ch].min() >= f[ch][k].min() - 1e-3 and u[ch].max() <= f[ch][k].max() + 1e-3
     ref0 = oracle.solve_pcg(f[0].astype(np.float64), m, tol=1e-12)[0]
-    err = float(np.abs(u[0].astype(np.float64) - ref0).max())
-    print(f"4K channel 0 max abs error vs oracle {err:.3e}", flush=True)
-    assert err <= 0.5
+    for prec in (binding.PREC_FP32, binding.PREC_FP16, binding.PREC_BF16):
+        opts = binding.make_opts(precision=prec)
+        out, st, stats = binding.inpaint_solve_ex(fd, md, 1e-6, opts=opts)
+        torch.cuda.synchronize()
+        assert st == binding.OK
+        assert stats["levels"] == 8
+        u = out.cpu().numpy()
+        rr = oracle.rel_res(u.astype(np.float64), f.astype(np.float64), m)
+        print(f"4K precision {prec}: rel_res per channel {rr} cycles {stats['cycles']}", flush=True)
+        assert np.all(rr <= 1e-6), rr
+        for ch in range(3):
+            assert np.array_equal(u[ch][k], f[ch][k])
+            assert u[ch].min() >= f[ch][k].min() - 1e-3 and u[ch].max() <= f[ch][k].max() + 1e-3
+        err = float(np.abs(u[0].astype(np.float64) - ref0).max())
+        print(f"4K precision {prec}: channel 0 max abs error vs oracle {err:.3e}", flush=True)
+        assert err <= 0.5

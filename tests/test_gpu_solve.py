@@ -189,3 +189,28 @@ def test_rel_res_entry_point_matches_oracle():
     got = binding.inpaint_rel_res(u, f, m)
     ref = oracle.rel_res(u.astype(np.float64), f.astype(np.float64), m)
     np.testing.assert_allclose(got, ref, rtol=1e-12)
+
+
+@pytest.mark.parametrize("prec", [binding.PREC_FP16, binding.PREC_BF16])
+@pytest.mark.parametrize("W,H,C,dens,seed", [
+    (256, 256, 1, 0.05, 1), (301, 157, 3, 0.01, 2), (77, 53, 2, 0.1, 3), (1000, 3, 1, 0.05, 4),
+    (31, 29, 1, 0.05, 5),
+])
+def test_precision_forms_match_oracle(prec, W, H, C, dens, seed):
+    """16-bit correction storage with float64 residuals reaches the same tolerance."""
+    f = synth.frame_image(W, H, C, seed=seed)
+    m = synth.bernoulli_mask(W, H, dens, seed=seed + 7)
+    out, st, _ = _solve(f, m, precision=prec)
+    assert st == binding.OK
+    _check(out, f, m)
+
+
+def test_precision_forms_are_repeatable_and_channel_independent():
+    f = synth.frame_image(160, 96, 3, seed=71)
+    m = synth.bernoulli_mask(160, 96, 0.03, seed=72)
+    for prec in (binding.PREC_FP16, binding.PREC_BF16):
+        a, _, _ = _solve(f, m, precision=prec)
+        b, _, _ = _solve(f, m, precision=prec)
+        assert np.array_equal(a, b)
+        single, _, _ = _solve(np.ascontiguousarray(f[1:2]), m, precision=prec)
+        assert np.array_equal(single[0], a[1])
