@@ -135,6 +135,10 @@ typedef struct inpaint_stats {
      inpaint_kernel class, from HIP events recorded around each launch */
   float kernel_ms[INPAINT_NUM_KERNELS];
   int kernel_calls[INPAINT_NUM_KERNELS];
+  int status;            /* this problem's inpaint_status (set by the batched and served solves) */
+  double t_submit_ms;    /* served requests: submission, start of the first launch and completion, */
+  double t_start_ms;     /* in ms on the server's clock (0 at inpaint_server_create); 0 otherwise */
+  double t_done_ms;
 } inpaint_stats;
 
 /*
@@ -164,6 +168,45 @@ int inpaint_solve_ex(const float* f, const uint8_t* mask, int W, int H, int chan
  */
 int inpaint_rel_res(const float* u, const float* f, const uint8_t* mask, int W, int H,
                     int channels, double* rel_res_out);
+
+/*
+ * One problem of a batched or served solve, with the conventions of
+ * inpaint_solve: f and out planar float32 [channels][H][W], mask uint8 [H][W],
+ * each pointer host or device memory, owned by the caller.
+ */
+typedef struct inpaint_problem {
+  const float* f;
+  const uint8_t* mask;
+  int W, H, channels;
+  float* out;
+} inpaint_problem;
+
+/*
+ * Solve n independent problems of any sizes together (the data-parallel form
+ * of the method: images and channels carry no coupling, Section 2.2).  Every
+ * step of the cycle runs as one launch over all problems in lockstep by level;
+ * each problem keeps its own hierarchy, norms and convergence test, and one
+ * V-cycle of the whole batch is replayed from a captured HIP graph.  Each
+ * result is bit-identical to solving that problem alone with inpaint_solve_ex
+ * and the same options.
+ *   problems  host array of n problems; their outputs must not overlap each other
+ *   n         >= 1
+ *   tol       in (0, 1), the target relative residual of every problem
+ *   opts      as for inpaint_solve_ex (opts.profile is ignored); NULL = defaults
+ *   stream    hipStream_t as void*, NULL = the null stream
+ *   stats     NULL or an array of n inpaint_stats, one per problem (gpu_ms is
+ *             the device time of the whole batch; status is that problem's
+ *             inpaint_status; the local CG and kernel profile fields are 0)
+ * Returns INPAINT_OK when every problem converged; otherwise the status of the
+ * first problem (lowest index) that failed, else INPAINT_NOT_CONVERGED if some
+ * problem reached the cycle cap.  A bad argument of any problem rejects the
+ * whole call before any work (E_INVALID, the message names the problem).  A
+ * problem whose data is rejected on the device (no known pixel, non-finite f
+ * at a known pixel) gets its error status in stats and is left out; the others
+ * are solved.  Returns after every result is in place.
+ */
+int inpaint_solve_batched(const inpaint_problem* problems, int n, double tol,
+                          const inpaint_opts* opts, void* stream, inpaint_stats* stats);
 
 /* Message for the last error on the calling thread ("" if none). */
 const char* inpaint_last_error(void);

@@ -29,6 +29,7 @@ EXPORTED = [
     "inpaint_solve", "inpaint_solve_ex", "inpaint_rel_res", "inpaint_last_error",
     "inpaint_version", "inpaint_hierarchy_size", "inpaint_debug_pyramid",
     "inpaint_debug_oras_step", "inpaint_debug_restrict", "inpaint_debug_prolong",
+    "inpaint_solve_batched",
 ]
 
 
@@ -49,6 +50,8 @@ class InpaintStats(ct.Structure):
         ("gpu_ms", ct.c_float), ("local_cg_finest", ct.c_double),
         ("finest_block_solves", ct.c_longlong), ("finest_cg_pixel_iters", ct.c_double),
         ("kernel_ms", ct.c_float * 9), ("kernel_calls", ct.c_int * 9),
+        ("status", ct.c_int), ("t_submit_ms", ct.c_double), ("t_start_ms", ct.c_double),
+        ("t_done_ms", ct.c_double),
     ]
 
     def as_dict(self) -> dict:
@@ -57,6 +60,11 @@ class InpaintStats(ct.Structure):
             v = getattr(self, k)
             d[k] = list(v) if k in ("kernel_ms", "kernel_calls") else v
         return d
+
+
+class InpaintProblem(ct.Structure):
+    _fields_ = [("f", ct.c_void_p), ("mask", ct.c_void_p), ("W", ct.c_int), ("H", ct.c_int),
+                ("channels", ct.c_int), ("out", ct.c_void_p)]
 
 
 class InpaintError(RuntimeError):
@@ -90,6 +98,8 @@ def lib() -> ct.CDLL:
         L.inpaint_debug_oras_step.argtypes = [vp, vp, vp, i, i, i, ct.POINTER(InpaintOpts), vp]
         L.inpaint_debug_restrict.argtypes = [vp, vp, i, i, vp]
         L.inpaint_debug_prolong.argtypes = [vp, i, i, vp, vp, vp, i, vp]
+        L.inpaint_solve_batched.argtypes = [ct.POINTER(InpaintProblem), i, d,
+                                            ct.POINTER(InpaintOpts), vp, ct.POINTER(InpaintStats)]
         for name in EXPORTED:
             fn = getattr(L, name)
             if fn.restype is ct.c_int or fn.restype is None:
@@ -178,6 +188,38 @@ def inpaint_solve_ex(f, mask, tol: float = 1e-6, out=None, opts: InpaintOpts | N
                                        ct.byref(opts) if opts is not None else None,
                                        _stream_handle(stream), ct.byref(stats)))
     return out, st, stats.as_dict()
+
+
+def _problems(items):
+    arr = (InpaintProblem * len(items))()
+    outs = []
+    for k, it in enumerate(items):
+        f, mask = it[0], it[1]
+        out = it[2] if len(it) > 2 and it[2] is not None else _empty_like(f)
+        C, H, W = _shape(f)
+        arr[k].f = _ptr(f)
+        arr[k].mask = _ptr(mask)
+        arr[k].W, arr[k].H, arr[k].channels = W, H, C
+        arr[k].out = _ptr(out)
+        outs.append(out)
+    return arr, outs
+
+
+def inpaint_solve_batched(problems, tol: float = 1e-6, opts: InpaintOpts | None = None,
+                          stream=None, raise_on_error: bool = True):
+    """Solve a list of (f, mask) or (f, mask, out) problems in one batch.
+
+    Returns (outs, status, per-problem stats dicts).  With raise_on_error a
+    negative status raises InpaintError; otherwise it is returned and each
+    problem's own status is in its stats."""
+    arr, outs = _problems(problems)
+    stats = (InpaintStats * max(1, len(problems)))()
+    st = lib().inpaint_solve_batched(arr, len(problems), tol,
+                                     ct.byref(opts) if opts is not None else None,
+                                     _stream_handle(stream), stats)
+    if raise_on_error:
+        _check(st)
+    return outs, st, [stats[k].as_dict() for k in range(len(problems))]
 
 
 def inpaint_rel_res(u, f, mask) -> np.ndarray:

@@ -1,0 +1,719 @@
+// Batched solve: n independent problems of any sizes advance together.  Every
+// step of the method (the cascade and V-cycle of Section 4.2, the two halves of
+// an ORAS iteration of Algorithm 2) becomes one launch over all problems that
+// take part in it, problems in lockstep by level.  Each problem keeps its own
+// workspace, norms and convergence flags and runs the same arithmetic in the
+// same order as a solve of that problem alone, so its result is bit-identical.
+// One V-cycle of the whole batch is captured once as a HIP graph and replayed
+// until every problem has converged.
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <list>
+#include <map>
+
+#include "batch.h"
+
+namespace inpaint {
+namespace {
+
+// ---------------------------------------------------------------------------
+// batch-only kernels
+// ---------------------------------------------------------------------------
+
+struct ResetArgs {
+  int* active;
+  int* status;
+  unsigned long long* cgstat;
+  int C;
+};
+
+// Copy of one problem's 64-byte flag block (relres[4] doubles, active[4] and
+// status[4] ints) into the batch's gathered array.
+struct GatherArgs {
+  const int* src;
+  int* dst;
+};
+
+__global__ void __launch_bounds__(64) k_reset_b(const ResetArgs* __restrict__ args) {
+  const ResetArgs a = args[blockIdx.x];
+  const int t = threadIdx.x;
+  if (t < a.C) a.active[t] = 1;
+  if (t < 4) a.status[t] = 0;
+  for (int i = t; i < 3 * a.C * kMaxLevels; i += blockDim.x) a.cgstat[i] = 0;
+}
+
+__global__ void __launch_bounds__(64) k_gather(const GatherArgs* __restrict__ args) {
+  const GatherArgs a = args[blockIdx.x];
+  const int t = threadIdx.x;
+  if (t < 16) a.dst[t] = a.src[t];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+
+void Plan::begin(int kind, int mode, int level0) {
+  open = Step{kind, mode, level0, 0, 0, 0, 0};
+  pend.clear();
+  pstart.assign(1, 0u);
+}
+
+void Plan::end() {
+  if (open.n == 0) return;
+  open.total = pstart.back();
+  open.args = append(pend.data(), pend.size());
+  open.start = append(pstart.data(), pstart.size() * sizeof(unsigned));
+  steps.push_back(open);
+  open.n = 0;
+}
+
+size_t Plan::append(const void* p, size_t n) {
+  const size_t at = round_up(host.size(), 64);
+  host.resize(at + n);
+  std::memcpy(host.data() + at, p, n);
+  return at;
+}
+
+void Plan::clear() {
+  steps.clear();
+  host.clear();
+  delta.clear();
+  cur0.clear();
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  exec = nullptr;
+  graph = nullptr;
+  dev = nullptr;
+}
+
+Plan::~Plan() { clear(); }
+
+hipError_t issue(const Plan& P, int prec, int B, hipStream_t s) {
+  for (const Step& st : P.steps) {
+    const void* a = P.dev + st.args;
+    const unsigned* start = (const unsigned*)(P.dev + st.start);
+    hipError_t e = hipSuccess;
+    switch (st.kind) {
+      case S_RESET:
+        hipLaunchKernelGGL(k_reset_b, dim3(st.n), dim3(64), 0, s, (const ResetArgs*)a);
+        e = hipGetLastError();
+        break;
+      case S_GATHER:
+        hipLaunchKernelGGL(k_gather, dim3(st.n), dim3(64), 0, s, (const GatherArgs*)a);
+        e = hipGetLastError();
+        break;
+      case S_STAGE: e = launch_stage_b((const StageArgs*)a, start, st.n, st.total, s); break;
+      case S_MASK: e = launch_mask_b((const MaskArgs*)a, start, st.n, st.total, s); break;
+      case S_RHS:
+        e = launch_rhs_b((const RhsArgs*)a, start, st.n, st.total, prec, st.level0, s);
+        break;
+      case S_PASS:
+        e = launch_pass_b(st.mode, (const PassArgs*)a, start, st.n, st.total, prec, st.level0, s);
+        break;
+      case S_RESTRICT:
+        e = launch_restrict_b((const RestrictArgs*)a, start, st.n, st.total, prec, st.level0, s);
+        break;
+      case S_BLOCK:
+        e = launch_block_b((const BlockArgs*)a, start, st.n, st.total, prec, st.level0, B, s);
+        break;
+      case S_COARSE:
+        e = launch_coarse_b((const CoarseArgs*)a, start, st.n, st.total, prec, st.level0, B, s);
+        break;
+      case S_OUTPUT: e = launch_output_b((const OutputArgs*)a, start, st.n, st.total, s); break;
+      default: e = hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// plan builders: each walks the members in lockstep and calls their Run's
+// argument builders in the order a solve of that member alone would launch
+// ---------------------------------------------------------------------------
+
+namespace {
+
+template <class Pred>
+std::vector<Member*> subset(const std::vector<Member*>& ms, Pred pred) {
+  std::vector<Member*> r;
+  for (Member* m : ms)
+    if (pred(m)) r.push_back(m);
+  return r;
+}
+
+int max_coarsest(const std::vector<Member*>& ms) {
+  int v = 0;
+  for (const Member* m : ms) v = std::max(v, m->Lc());
+  return v;
+}
+
+// One ORAS iteration on level l of every member in ms.
+void step_oras(Plan& P, const std::vector<Member*>& ms, int l, bool check, bool rest) {
+  P.begin(S_BLOCK, 0, l == 0);
+  for (Member* m : ms) {
+    const BlockArgs a = m->R->make_block(l);
+    P.add(a, work_block(a, m->C));
+  }
+  P.end();
+  P.begin(S_PASS, PASS_UPD, l == 0);
+  for (Member* m : ms) {
+    const PassArgs a = m->R->make_update(l, check, rest);
+    P.add(a, work_pass(a, m->C));
+  }
+  P.end();
+}
+
+void step_residual(Plan& P, const std::vector<Member*>& ms) {
+  P.begin(S_PASS, PASS_RES, 1);
+  for (Member* m : ms) {
+    const PassArgs a = m->R->make_residual(0, true);
+    P.add(a, work_pass(a, m->C));
+  }
+  P.end();
+}
+
+// A V-cycle on level l0 of every member (Section 4.2): the members' down
+// sweeps run level by level, the coarsest-grid solves of all members in one
+// launch (two when some member has a single level), then the up sweeps.
+void build_vcycle(Plan& P, const std::vector<Member*>& ms, int l0, const Opts& o) {
+  const int maxLc = max_coarsest(ms);
+  for (int l = l0; l < maxLc; ++l) {
+    const auto part = subset(ms, [&](Member* m) { return l < m->Lc(); });
+    for (int i = 0; i < o.pre; ++i) step_oras(P, part, l, false, i == o.pre - 1);
+    if (o.pre == 0) {
+      P.begin(S_RESTRICT, 0, l == 0);
+      for (Member* m : part) {
+        const RestrictArgs a = m->R->make_restrict(l);
+        P.add(a, work_restrict(a, m->C));
+      }
+      P.end();
+    }
+  }
+  P.begin(S_COARSE, 0, 0);
+  for (Member* m : ms)
+    if (m->Lc() > 0) {
+      const CoarseArgs a = m->R->make_coarse(m->Lc(), true);
+      P.add(a, work_coarse(a, m->C));
+    }
+  P.end();
+  const auto flat = subset(ms, [](Member* m) { return m->Lc() == 0; });
+  P.begin(S_COARSE, 0, 1);
+  for (Member* m : flat) {
+    const CoarseArgs a = m->R->make_coarse(0, false);
+    P.add(a, work_coarse(a, m->C));
+  }
+  P.end();
+  step_residual(P, flat);
+  for (int l = maxLc - 1; l >= l0; --l) {
+    const auto part = subset(ms, [&](Member* m) { return l < m->Lc(); });
+    P.begin(S_PASS, PASS_PCORR, l == 0);
+    for (Member* m : part) {
+      const PassArgs a = m->R->make_prolong(l, PASS_PCORR, l == 0 && o.post == 0);
+      P.add(a, work_pass(a, m->C));
+    }
+    P.end();
+    for (int i = 0; i < o.post; ++i) step_oras(P, part, l, l == 0 && i == o.post - 1, false);
+  }
+}
+
+// The coarse-to-fine initial guess (Section 4.2) of every member.
+void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
+  if (o.schedule == INPAINT_SCHED_SINGLE) {
+    step_residual(P, ms);
+    return;
+  }
+  step_residual(P, subset(ms, [](Member* m) { return m->Lc() == 0; }));
+  const auto deep = subset(ms, [](Member* m) { return m->Lc() > 0; });
+  P.begin(S_COARSE, 0, 0);
+  for (Member* m : deep) {
+    m->R->top = m->Lc();
+    const CoarseArgs a = m->R->make_coarse(m->Lc(), true);
+    P.add(a, work_coarse(a, m->C));
+  }
+  P.end();
+  for (int l = max_coarsest(deep) - 1; l >= 0; --l) {
+    const auto part = subset(deep, [&](Member* m) { return l < m->Lc(); });
+    P.begin(S_PASS, PASS_PSOL, l == 0);
+    for (Member* m : part) {
+      m->R->top = l;
+      const PassArgs a = m->R->make_prolong(l, PASS_PSOL, l == 0);
+      P.add(a, work_pass(a, m->C));
+    }
+    P.end();
+    if (l == 0) break;
+    if (o.schedule == INPAINT_SCHED_FMG)
+      build_vcycle(P, part, l, o);
+    else
+      step_oras(P, part, l, false, false);
+  }
+}
+
+void build_cycle(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
+  if (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG)
+    build_vcycle(P, ms, 0, o);
+  else
+    step_oras(P, ms, 0, true, false);
+}
+
+void add_gather(Plan& P, const std::vector<Member*>& ms, int* flags_dev) {
+  P.begin(S_GATHER);
+  for (Member* m : ms) P.add(GatherArgs{(const int*)m->ws->relres, flags_dev + 16 * m->slot}, 1u);
+  P.end();
+}
+
+// Build a plan with `body` and record, per member, what one run of it adds to
+// the member's counters and which level-0 buffer holds the iterate afterwards.
+template <class Body>
+void build(Plan& P, const std::vector<Member*>& ms, Body&& body) {
+  std::vector<std::array<long long, 3>> before;
+  for (Member* m : ms) before.push_back({m->R->oras_iters, m->R->block_solves, m->R->finest_block_solves});
+  body();
+  P.delta.clear();
+  P.cur0.clear();
+  for (size_t i = 0; i < ms.size(); ++i) {
+    const Run& R = *ms[i]->R;
+    P.delta.push_back({R.oras_iters - before[i][0], R.block_solves - before[i][1],
+                       R.finest_block_solves - before[i][2]});
+    P.cur0.push_back(ms[i]->ws->lv[0].cur);
+  }
+}
+
+std::vector<int> level_state(const std::vector<Member*>& ms) {
+  std::vector<int> s;
+  for (Member* m : ms)
+    for (int l = 0; l < m->ws->L; ++l) s.push_back(m->ws->lv[l].cur);
+  return s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// batch contexts (device copies of the plans, graphs, flag buffers), cached by
+// the workspaces, options and tolerance of a batch
+// ---------------------------------------------------------------------------
+
+BatchCtx::~BatchCtx() {
+  int old = -1;
+  (void)hipGetDevice(&old);
+  (void)hipSetDevice(dev_id);
+  cascade.clear();
+  for (Plan& p : cycle) p.clear();
+  if (plan_dev) (void)hipFree(plan_dev);
+  if (call_dev) (void)hipFree(call_dev);
+  if (flags_dev) (void)hipFree(flags_dev);
+  if (flags_host) (void)hipHostFree(flags_host);
+  if (cap) (void)hipStreamDestroy(cap);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (old >= 0) (void)hipSetDevice(old);
+}
+
+namespace {
+
+std::mutex g_bmu;
+std::list<std::shared_ptr<BatchCtx>> g_bcache;  // most recently used first
+constexpr size_t kBatchCacheSize = 8;
+
+std::string ctx_key(int dev, const std::vector<Member*>& ms, const Opts& o, double tol) {
+  std::string k;
+  auto put = [&](const void* p, size_t n) { k.append((const char*)p, n); };
+  put(&dev, sizeof dev);
+  put(&o, sizeof o);
+  put(&tol, sizeof tol);
+  for (const Member* m : ms) put(&m->ws, sizeof m->ws);
+  return k;
+}
+
+std::shared_ptr<BatchCtx> batch_ctx(int dev, const std::vector<Member*>& ms, const Opts& o,
+                                    double tol, int n) {
+  const std::string key = ctx_key(dev, ms, o, tol);
+  {
+    std::lock_guard<std::mutex> g(g_bmu);
+    for (auto it = g_bcache.begin(); it != g_bcache.end(); ++it)
+      if ((*it)->key == key) {
+        auto c = *it;
+        g_bcache.erase(it);
+        g_bcache.push_front(c);
+        return c;
+      }
+  }
+  auto c = std::make_shared<BatchCtx>();
+  c->key = key;
+  c->dev_id = dev;
+  c->n = n;
+  HIPCHK(hipMalloc(&c->flags_dev, (size_t)n * 64));
+  HIPCHK(hipHostMalloc(&c->flags_host, (size_t)n * 64, hipHostMallocDefault));
+  HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  HIPCHK(hipEventCreate(&c->ev0));
+  HIPCHK(hipEventCreate(&c->ev1));
+  std::lock_guard<std::mutex> g(g_bmu);
+  g_bcache.push_front(c);
+  while (g_bcache.size() > kBatchCacheSize) g_bcache.pop_back();
+  return c;
+}
+
+// Copy the plans' argument arrays into one device buffer owned by `*buf`
+// (grown as needed) and point each plan at its part.
+void upload(std::vector<Plan*> plans, unsigned char** buf, size_t* cap, hipStream_t s) {
+  size_t need = 0;
+  for (Plan* p : plans) need += round_up(p->host.size(), 256);
+  if (need > *cap) {
+    if (*buf) {
+      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(hipFree(*buf));
+      *buf = nullptr;
+      *cap = 0;
+    }
+    HIPCHK(hipMalloc(buf, need));
+    *cap = need;
+  }
+  size_t off = 0;
+  for (Plan* p : plans) {
+    p->dev = *buf + off;
+    if (!p->host.empty())
+      HIPCHK(hipMemcpyAsync(p->dev, p->host.data(), p->host.size(), hipMemcpyHostToDevice, s));
+    off += round_up(p->host.size(), 256);
+  }
+}
+
+void capture(Plan& P, BatchCtx& c, int prec, int B) {
+  HIPCHK(hipStreamBeginCapture(c.cap, hipStreamCaptureModeThreadLocal));
+  const hipError_t e = issue(P, prec, B, c.cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(c.cap, &g);
+  HIPCHK(e);
+  HIPCHK(e2);
+  P.graph = g;
+  HIPCHK(hipGraphInstantiate(&P.exec, g, nullptr, nullptr, 0));
+}
+
+void run_plan(const Plan& P, int prec, int B, hipStream_t s) {
+  if (P.exec)
+    HIPCHK(hipGraphLaunch(P.exec, s));
+  else
+    HIPCHK(issue(P, prec, B, s));
+}
+
+// Read the gathered flags of every member; returns true when all are done.
+bool poll_members(BatchCtx& c, const std::vector<Member*>& ms, const Plan& P, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)c.n * 64, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  bool all = true;
+  for (size_t i = 0; i < ms.size(); ++i) {
+    Member* m = ms[i];
+    const int* blk = c.flags_host + 16 * m->slot;
+    const double* rr = (const double*)blk;
+    const int* act = blk + 8;
+    const int* st = blk + 12;
+    if (st[0] & 4) fail(INPAINT_E_DEVICE, "a norm partial never arrived (spin budget exhausted)");
+    if (m->done) continue;
+    bool d = true;
+    for (int ch = 0; ch < m->C; ++ch) {
+      if (m->final_cur[ch] < 0) {
+        m->rel[ch] = rr[ch];
+        if (!act[ch] || !std::isfinite(rr[ch])) m->final_cur[ch] = P.cur0[i];
+      }
+      d = d && m->final_cur[ch] >= 0;
+    }
+    m->done = d;
+    all = all && d;
+  }
+  return all;
+}
+
+void account(const std::vector<Member*>& ms, const Plan& P) {
+  for (size_t i = 0; i < ms.size(); ++i) {
+    Member* m = ms[i];
+    if (m->done) continue;
+    m->oras += P.delta[i][0];
+    m->blocks += P.delta[i][1];
+    m->finest_blocks += P.delta[i][2];
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the batched solve
+// ---------------------------------------------------------------------------
+
+void init_member(Member& m, const inpaint_problem& p, int idx, const Opts& o, double tol,
+                 hipStream_t s) {
+  m.idx = m.slot = idx;
+  m.W = p.W;
+  m.H = p.H;
+  m.C = p.channels;
+  acquire(m.lease, m.W, m.H, m.C, o.B, o.o, o.B, o.prec);
+  m.ws = m.lease.ws;
+  m.R.reset(new Run{m.ws, o, s, m.C, tol});
+  const bool fd = is_device_ptr(p.f), md = is_device_ptr(p.mask), od = is_device_ptr(p.out);
+  if (!fd || !md || !od) ensure_staging(m.ws);
+  const size_t nf = (size_t)m.W * m.H * m.C * sizeof(float);
+  m.f_d = p.f;
+  m.m_d = p.mask;
+  m.o_d = p.out;
+  m.out_host = !od;
+  m.out = p.out;
+  if (!fd) {
+    HIPCHK(hipMemcpyAsync(m.ws->f_dev, p.f, nf, hipMemcpyHostToDevice, s));
+    m.f_d = m.ws->f_dev;
+  }
+  if (!md) {
+    HIPCHK(hipMemcpyAsync(m.ws->m_dev, p.mask, (size_t)m.W * m.H, hipMemcpyHostToDevice, s));
+    m.m_d = m.ws->m_dev;
+  }
+  if (!od) m.o_d = m.ws->o_dev;
+  m.final_cur.assign(m.C, -1);
+  m.rel.assign(m.C, 0.0);
+}
+
+// Prepare plan: reset flags, stage every member's (f, mask) into level 0 with
+// its reference residual, build the coarse masks and known values level by
+// level, gather the flags (the input checks).
+void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* flags_dev) {
+  const bool single = o.schedule == INPAINT_SCHED_SINGLE;
+  P.begin(S_RESET);
+  for (Member* m : ms) P.add(ResetArgs{m->ws->active, m->ws->status, m->ws->cgstat, m->C}, 1u);
+  P.end();
+  P.begin(S_STAGE);
+  for (Member* m : ms) {
+    Workspace* ws = m->ws;
+    Level& L0 = ws->lv[0];
+    L0.cur = 0;
+    NormOut den = m->R->norm(0, false);
+    den.out = ws->den;
+    den.rho = ws->rho;
+    den.inv_n = 1.0 / ((double)m->W * (double)m->H);
+    const StageArgs a{m->f_d, m->m_d, m->W, m->H, m->W, m->C, L0.v, L0.c, L0.b,
+                      (single || ws->L == 1) ? L0.u[0] : nullptr, ws->status, den};
+    P.add(a, work_stage(a));
+  }
+  P.end();
+  if (!single) {
+    int maxL = 0;
+    for (Member* m : ms) maxL = std::max(maxL, m->ws->L);
+    for (int l = 0; l + 1 < maxL; ++l) {
+      const auto part = subset(ms, [&](Member* m) { return l + 1 < m->ws->L; });
+      P.begin(S_MASK);
+      for (Member* m : part) {
+        Level& F = m->ws->lv[l];
+        Level& Cl = m->ws->lv[l + 1];
+        Cl.cur = 0;
+        const MaskArgs a{F.v, Cl.v, F.c, Cl.c};
+        P.add(a, work_mask(a));
+      }
+      P.end();
+      P.begin(S_RHS, 0, l == 0);
+      for (Member* m : part) {
+        Level& F = m->ws->lv[l];
+        Level& Cl = m->ws->lv[l + 1];
+        const RhsArgs a{F.v, Cl.v, F.c, F.b, Cl.c, Cl.b, m->C, o.rhs == INPAINT_RHS_NAIVE ? 1 : 0};
+        P.add(a, work_rhs(a));
+      }
+      P.end();
+    }
+  }
+  add_gather(P, ms, flags_dev);
+}
+
+void build_output(Plan& P, const std::vector<Member*>& ms) {
+  P.begin(S_OUTPUT);
+  for (Member* m : ms) {
+    const Level& L0 = m->ws->lv[0];
+    OutputArgs a{};
+    a.lv = L0.v;
+    a.c = L0.c;
+    a.b = L0.b;
+    for (int ch = 0; ch < kMaxChannels; ++ch) a.u[ch] = L0.u[m->final_cur[ch < m->C ? ch : 0]];
+    a.out = m->o_d;
+    a.Pout = m->W;
+    a.C = m->C;
+    P.add(a, work_output(a));
+  }
+  P.end();
+}
+
+int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const inpaint_opts* opts,
+                       void* stream, inpaint_stats* stats) {
+  if (!probs) fail(INPAINT_E_INVALID, "NULL problem array");
+  if (n < 1) fail(INPAINT_E_INVALID, "n must be >= 1");
+  if (!(tol > 0.0 && tol < 1.0)) fail(INPAINT_E_INVALID, "tol must lie in (0, 1)");
+  Opts o = resolve(opts);
+  o.profile = 0;
+  for (int i = 0; i < n; ++i) {
+    const inpaint_problem& p = probs[i];
+    try {
+      check_dims(p.f, p.mask, p.W, p.H, p.channels);
+      if (!p.out) fail(INPAINT_E_INVALID, "NULL pointer argument");
+      const size_t nf = (size_t)p.W * p.H * p.channels * sizeof(float);
+      if (p.out != p.f && overlap(p.out, nf, p.f, nf)) fail(INPAINT_E_INVALID, "out partially overlaps f");
+      if (overlap(p.out, nf, p.mask, (size_t)p.W * p.H)) fail(INPAINT_E_INVALID, "out overlaps mask");
+    } catch (const Fail& e) {
+      g_err = "problem " + std::to_string(i) + ": " + g_err;
+      throw;
+    }
+  }
+  {
+    std::vector<std::pair<const char*, const char*>> spans;
+    for (int i = 0; i < n; ++i) {
+      const char* a = (const char*)probs[i].out;
+      spans.push_back({a, a + (size_t)probs[i].W * probs[i].H * probs[i].channels * sizeof(float)});
+    }
+    std::sort(spans.begin(), spans.end());
+    for (int i = 1; i < n; ++i)
+      if (spans[i].first < spans[i - 1].second)
+        fail(INPAINT_E_INVALID, "the outputs of two problems overlap");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::vector<std::unique_ptr<Member>> own;
+  std::vector<Member*> all;
+  for (int i = 0; i < n; ++i) {
+    own.emplace_back(new Member());
+    init_member(*own.back(), probs[i], i, o, tol, s);
+    all.push_back(own.back().get());
+  }
+  auto ctx = batch_ctx(dev, all, o, tol, n);
+  BatchCtx& c = *ctx;
+  const int prec = o.prec, B = o.B;
+
+  // prepare: staging and hierarchies; members whose data is rejected leave
+  HIPCHK(hipEventRecord(c.ev0, s));
+  Plan prep;
+  build(prep, all, [&] { build_prepare(prep, all, o, c.flags_dev); });
+  upload({&prep}, &c.call_dev, &c.call_cap, s);
+  HIPCHK(issue(prep, prec, B, s));
+  HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)n * 64, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<Member*> live;
+  std::string live_key;
+  for (Member* m : all) {
+    const int st = c.flags_host[16 * m->slot + 12];
+    if (st & 1) {
+      m->status = INPAINT_E_INVALID;
+      m->msg = "f is not finite at a known pixel";
+    } else if (!(st & 2)) {
+      m->status = INPAINT_E_EMPTY_MASK;
+      m->msg = "mask has no known pixel: the system is singular";
+    }
+    live_key.push_back(m->status == INPAINT_OK ? 1 : 0);
+    if (m->status == INPAINT_OK) live.push_back(m);
+  }
+
+  if (!live.empty()) {
+    // cascade and cycle plans, built once per batch context
+    if (c.live_key != live_key) {
+      c.cascade.clear();
+      for (Plan& p : c.cycle) p.clear();
+      c.live_key = live_key;
+      build(c.cascade, live, [&] {
+        build_cascade(c.cascade, live, o);
+        add_gather(c.cascade, live, c.flags_dev);
+      });
+      const std::vector<int> s0 = level_state(live);
+      c.ncycle = 0;
+      for (int k = 0; k < 2; ++k) {
+        Plan& P = c.cycle[k];
+        build(P, live, [&] {
+          build_cycle(P, live, o);
+          add_gather(P, live, c.flags_dev);
+        });
+        c.ncycle = k + 1;
+        if (level_state(live) == s0) break;
+      }
+      if (level_state(live) != s0) fail(INPAINT_E_DEVICE, "cycle plans do not return to their start state");
+      upload({&c.cascade, &c.cycle[0], &c.cycle[1]}, &c.plan_dev, &c.plan_cap, s);
+      HIPCHK(hipStreamSynchronize(s));
+      for (int k = 0; k < c.ncycle; ++k) capture(c.cycle[k], c, prec, B);
+    }
+    run_plan(c.cascade, prec, B, s);
+    account(live, c.cascade);
+    bool done = poll_members(c, live, c.cascade, s);
+    int cycles = 0;
+    while (!done && cycles < o.max_cycles) {
+      const Plan& P = c.cycle[cycles % c.ncycle];
+      for (Member* m : live)
+        if (!m->done) ++m->cycles;
+      account(live, P);
+      run_plan(P, prec, B, s);
+      ++cycles;
+      done = poll_members(c, live, P, s);
+    }
+    const Plan& last = cycles == 0 ? c.cascade : c.cycle[(cycles - 1) % c.ncycle];
+    for (size_t i = 0; i < live.size(); ++i) {
+      Member* m = live[i];
+      bool diverged = false;
+      for (int ch = 0; ch < m->C; ++ch) {
+        if (m->final_cur[ch] < 0) m->final_cur[ch] = last.cur0[i];
+        if (!std::isfinite(m->rel[ch])) diverged = true;
+      }
+      if (diverged) {
+        m->status = INPAINT_E_DIVERGED;
+        m->msg = "the residual became non-finite";
+      } else if (!m->done) {
+        m->status = INPAINT_NOT_CONVERGED;
+        m->msg = "cycle cap reached before the tolerance";
+      }
+    }
+    Plan out;
+    build_output(out, live);
+    upload({&out}, &c.call_dev, &c.call_cap, s);
+    HIPCHK(issue(out, prec, B, s));
+  }
+  HIPCHK(hipEventRecord(c.ev1, s));
+  for (Member* m : live)
+    if (m->out_host)
+      HIPCHK(hipMemcpyAsync(m->out, m->o_d, (size_t)m->W * m->H * m->C * sizeof(float),
+                            hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, c.ev0, c.ev1));
+  int ret = INPAINT_OK;
+  std::string msg;
+  for (Member* m : all) {
+    if (ret == INPAINT_OK || (ret == INPAINT_NOT_CONVERGED && m->status < 0)) {
+      if (m->status != INPAINT_OK) {
+        ret = m->status;
+        msg = "problem " + std::to_string(m->idx) + ": " + m->msg;
+      }
+    }
+    if (stats) {
+      inpaint_stats& st = stats[m->idx];
+      std::memset(&st, 0, sizeof st);
+      st.status = m->status;
+      st.levels = m->ws->L;
+      st.gpu_ms = ms;
+      if (m->status == INPAINT_OK || m->status == INPAINT_NOT_CONVERGED ||
+          m->status == INPAINT_E_DIVERGED) {
+        double r = 0.0;
+        for (int ch = 0; ch < m->C; ++ch) r = std::max(r, m->rel[ch]);
+        st.rel_res = m->status == INPAINT_E_DIVERGED ? NAN : r;
+        st.cycles = m->cycles;
+        st.oras_iters = (int)(m->oras * m->C);
+        st.finest_block_solves = m->finest_blocks;
+      }
+    }
+  }
+  g_err = msg;
+  return ret;
+}
+
+}  // namespace inpaint
+
+#define INPAINT_EXPORT __attribute__((visibility("default")))
+
+extern "C" {
+
+INPAINT_EXPORT int inpaint_solve_batched(const inpaint_problem* problems, int n, double tol,
+                                         const inpaint_opts* opts, void* stream,
+                                         inpaint_stats* stats) {
+  return inpaint::guarded(
+      [&] { return inpaint::solve_batched_impl(problems, n, tol, opts, stream, stats); });
+}
+
+}  // extern "C"

@@ -1,0 +1,437 @@
+// Host-side driver shared by the single-problem, batched and serving entry
+// points: options, workspaces (the grid hierarchy of one problem in HBM), the
+// cycle driver's argument builders and the input staging.  Internal; the
+// public ABI is include/inpaint.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "inpaint.h"
+#include "kernels.h"
+
+namespace inpaint {
+
+extern thread_local std::string g_err;
+
+struct Fail {
+  int code;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      fail(e_ == hipErrorOutOfMemory ? INPAINT_E_NOMEM : INPAINT_E_DEVICE,        \
+           std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+inline int num_blocks_axis(int n, int B, int o) { return n <= B ? 1 : (n - o + (B - o) - 1) / (B - o); }
+
+// ---------------------------------------------------------------------------
+// options
+// ---------------------------------------------------------------------------
+
+struct Opts {
+  int B = 32, o = 6;
+  float gamma = 0.5f, tau = 0.005f;
+  int maxit = 16;
+  int schedule = INPAINT_SCHED_RFMG;
+  int max_cycles = 0;
+  int pre = 1, post = 1;
+  int rhs = INPAINT_RHS_MODIFIED;
+  float coarse_tau = 1e-8f;
+  int coarse_maxit = 256;
+  int profile = 0;
+  int prec = PREC_F32;
+};
+
+// Validated options with defaults filled in (throws Fail on a bad value).
+Opts resolve(const inpaint_opts* p);
+
+// ---------------------------------------------------------------------------
+// workspaces
+// ---------------------------------------------------------------------------
+
+struct Level {
+  LevelView v;
+  uint8_t* c = nullptr;
+  float* b = nullptr;
+  float* u[2] = {nullptr, nullptr};
+  float* r = nullptr;
+  float* contrib = nullptr;
+  int* itot = nullptr;  // [C][nblk] local CG iterations per block, summed over a solve
+  int* imax = nullptr;  // [C][nblk] their maximum (itot and imax are contiguous)
+  int cur = 0;
+};
+
+struct Key {
+  int dev, W, H, C, B, o, coarsest, prec;
+  bool operator<(const Key& k) const {
+    return std::tie(dev, W, H, C, B, o, coarsest, prec) <
+           std::tie(k.dev, k.W, k.H, k.C, k.B, k.o, k.coarsest, k.prec);
+  }
+};
+
+struct Workspace {
+  Key key{};
+  int L = 0;
+  Level lv[kMaxLevels];
+  void* base = nullptr;
+  size_t bytes = 0;
+  double* partials = nullptr;   // [C][max tiles], kept at -1 between passes
+  unsigned* counters = nullptr; // [C], kept at 0 between passes
+  double* snorm = nullptr;  // [L][C]
+  double* den = nullptr;    // [C]
+  float* rho = nullptr;     // [C] rms of the reference residual (scale of 16-bit fields)
+  double* relres = nullptr; // [C]
+  int* active = nullptr;    // [C]
+  int* status = nullptr;    // [4]
+  unsigned long long* cgstat = nullptr;  // [L][C][3]: total, max, pixel-weighted local CG iterations
+  std::vector<hipEvent_t> evpool;        // events for per-launch profiling
+  // host-pointer staging (allocated on first use)
+  void* stage_base = nullptr;
+  float* f_dev = nullptr;
+  uint8_t* m_dev = nullptr;
+  float* o_dev = nullptr;
+  // pinned readback
+  void* host = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool busy = false;
+
+  ~Workspace();
+};
+
+// Level sizes: halve with ceil until both sides are at most `coarsest`.
+std::vector<std::pair<int, int>> level_sizes(int W, int H, int coarsest);
+
+struct Lease {
+  Workspace* ws = nullptr;
+  Lease() = default;
+  Lease(const Lease&) = delete;
+  Lease& operator=(const Lease&) = delete;
+  ~Lease();
+};
+
+// Lease a free workspace for (device, sizes, channels, block, overlap,
+// coarsest side, precision), creating it on first use.  Workspaces are kept
+// for the life of the process.
+void acquire(Lease& lease, int W, int H, int C, int B, int o, int coarsest, int prec = PREC_F32);
+// Device buffers for host-memory inputs and outputs (allocated on first use).
+void ensure_staging(Workspace* ws);
+bool is_device_ptr(const void* p);
+
+// ---------------------------------------------------------------------------
+// the cycle driver
+// ---------------------------------------------------------------------------
+
+struct Run {
+  Workspace* ws;
+  Opts o;
+  hipStream_t s;
+  int C;
+  double tol;
+  long oras_iters = 0;
+  long block_solves = 0;
+  long long finest_block_solves = 0;
+  int top = 0;  // level whose b holds known values (a solution problem); coarser ones hold corrections
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  size_t next_ev = 0;
+
+  hipEvent_t pool_event() {
+    if (next_ev == ws->evpool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      ws->evpool.push_back(e);
+    }
+    return ws->evpool[next_ev++];
+  }
+
+  // Launch through `fn`; on the finest grid with profiling on, bracket it by
+  // two events on the same stream.
+  template <class Fn>
+  void timed(int cls, int level, Fn&& fn) {
+    if (!o.profile || level != 0) {
+      HIPCHK(fn());
+      return;
+    }
+    hipEvent_t a = pool_event(), b = pool_event();
+    HIPCHK(hipEventRecord(a, s));
+    HIPCHK(fn());
+    HIPCHK(hipEventRecord(b, s));
+    recs.push_back({cls, a, b});
+  }
+
+  NormOut norm(int l, bool check) const {
+    NormOut n{};
+    n.partials = ws->partials;
+    n.counter = ws->counters;
+    n.status = ws->status;
+    n.out = ws->snorm + (size_t)l * C;
+    n.den = ws->den;
+    n.relres = ws->relres;
+    n.active = ws->active;
+    n.tol = tol;
+    n.check = check ? 1 : 0;
+    return n;
+  }
+
+  // Scales of 16-bit fields (kernels.h, Sc), relative to the reference
+  // residual's rms rho: residuals and right-hand sides of level l carry the
+  // integer stencil's factor 4^l; errors and corrections do not.  Fields of a
+  // solution problem (iterate, known values: grey levels) are not scaled.
+  static constexpr float kRes = 1e-3f, kErr = 1e-2f;
+  static Sc sc_res(int l) { return Sc{kRes * std::ldexp(1.0f, 2 * l), 1}; }
+  static Sc sc_err() { return Sc{kErr, 1}; }
+  static Sc sc_one() { return Sc{1.0f, 0}; }
+  int prec() const { return ws->key.prec; }
+
+  PassArgs pass_args(int l) const {
+    const Level& L = ws->lv[l];
+    PassArgs a{};
+    a.lv = L.v;
+    a.prec = prec();
+    a.level0 = l == 0;
+    a.solution = l == top ? 1 : 0;
+    a.rho = ws->rho;
+    a.s_u = a.solution ? sc_one() : sc_err();
+    a.s_b = a.solution ? sc_one() : sc_res(l);
+    a.s_r = sc_res(l);
+    a.s_contrib = sc_err();
+    a.s_cr = sc_res(l + 1);
+    a.c = L.c;
+    a.b = L.b;
+    a.u_in = L.u[L.cur];
+    a.u_out = L.u[L.cur ^ 1];
+    a.r = L.r;
+    a.contrib = L.contrib;
+    a.active = ws->active;
+    return a;
+  }
+
+  // ---- argument builders: each returns the arguments of one launch and
+  // advances the host-side state (which buffer holds the iterate, counters)
+  // exactly as running that launch would.
+
+  PassArgs make_residual(int l, bool check) {
+    PassArgs a = pass_args(l);
+    a.u_out = nullptr;
+    a.norm = norm(l, check);
+    return a;
+  }
+
+  BlockArgs make_block(int l) {
+    Level& L = ws->lv[l];
+    BlockArgs b{};
+    b.lv = L.v;
+    b.prec = prec();
+    b.level0 = l == 0;
+    b.rho = ws->rho;
+    b.s_r = sc_res(l);
+    b.s_contrib = sc_err();
+    b.c = L.c;
+    b.r = L.r;
+    b.snorm = ws->snorm + (size_t)l * C;
+    b.contrib = L.contrib;
+    b.gamma = o.gamma;
+    b.tau = o.tau;
+    b.maxit = o.maxit;
+    b.active = ws->active;
+    b.itot = o.profile ? L.itot : nullptr;
+    b.imax = o.profile ? L.imax : nullptr;
+    return b;
+  }
+
+  // The update half of an ORAS iteration.  With rest, it also restricts the
+  // new residual to level l + 1 (the last pre-smoothing of a V-cycle).
+  PassArgs make_update(int l, bool check, bool rest) {
+    Level& L = ws->lv[l];
+    PassArgs a = pass_args(l);
+    a.norm = norm(l, check);
+    if (rest) {
+      Level& Cl = ws->lv[l + 1];
+      a.rest = 1;
+      a.clv = Cl.v;
+      a.cc = Cl.c;
+      a.bc = Cl.b;
+      a.uc0 = Cl.u[Cl.cur];
+      a.rc = Cl.r;
+      a.norm = norm(l + 1, false);
+    }
+    L.cur ^= 1;
+    ++oras_iters;
+    block_solves += (long)L.v.nbx * L.v.nby * C;
+    if (l == 0) finest_block_solves += (long long)L.v.nbx * L.v.nby * C;
+    return a;
+  }
+
+  PassArgs make_prolong(int l, int mode, bool check) {
+    Level& L = ws->lv[l];
+    const Level& Lc = ws->lv[l + 1];
+    PassArgs a = pass_args(l);
+    a.uc = Lc.u[Lc.cur];
+    // the coarse field is a solution in the cascade and a correction in a V-cycle
+    a.s_uc = mode == PASS_PSOL ? sc_one() : sc_err();
+    a.Wc = Lc.v.W;
+    a.Hc = Lc.v.H;
+    a.Pc = Lc.v.P;
+    a.planec = Lc.v.plane;
+    a.norm = norm(l, check);
+    L.cur ^= 1;
+    return a;
+  }
+
+  RestrictArgs make_restrict(int l) {
+    const Level& F = ws->lv[l];
+    Level& Cl = ws->lv[l + 1];
+    RestrictArgs a{};
+    a.fl = F.v;
+    a.cl = Cl.v;
+    a.prec = prec();
+    a.level0 = l == 0;
+    a.rf = F.r;
+    a.cc = Cl.c;
+    a.bc = Cl.b;
+    a.uc = Cl.u[Cl.cur];
+    a.rc = Cl.r;
+    a.norm = norm(l + 1, false);
+    a.active = ws->active;
+    a.rho = ws->rho;
+    a.s_rf = sc_res(l);
+    a.s_cr = sc_res(l + 1);
+    return a;
+  }
+
+  CoarseArgs make_coarse(int l, bool init) {
+    Level& L = ws->lv[l];
+    CoarseArgs a{};
+    a.lv = L.v;
+    a.prec = prec();
+    a.level0 = l == 0;
+    a.rho = ws->rho;
+    const bool sol = l == top;
+    a.s_b = sol ? sc_one() : sc_res(l);
+    a.s_u = sol ? sc_one() : sc_err();
+    a.c = L.c;
+    a.b = L.b;
+    a.u = L.u[L.cur];
+    a.init = init ? 1 : 0;
+    a.rel_tol = o.coarse_tau;
+    a.maxit = o.coarse_maxit;
+    a.active = ws->active;
+    return a;
+  }
+
+  // ---- single-problem launches
+
+  void residual(int l, bool check) {
+    const PassArgs a = make_residual(l, check);
+    timed(INPAINT_K_RESIDUAL, l, [&] { return launch_pass(PASS_RES, a, C, s); });
+  }
+
+  void oras(int l, bool check, bool rest = false) {
+    const BlockArgs b = make_block(l);
+    timed(INPAINT_K_BLOCK_SOLVE, l, [&] { return launch_block_solve(b, C, s); });
+    const PassArgs a = make_update(l, check, rest);
+    timed(INPAINT_K_UPDATE, l, [&] { return launch_pass(PASS_UPD, a, C, s); });
+  }
+
+  void prolong(int l, int mode, bool check) {
+    const PassArgs a = make_prolong(l, mode, check);
+    timed(INPAINT_K_PROLONG, l, [&] { return launch_pass(mode, a, C, s); });
+  }
+
+  void restrict_to(int l) {
+    const RestrictArgs a = make_restrict(l);
+    timed(INPAINT_K_RESTRICT, l, [&] { return launch_restrict(a, C, s); });
+  }
+
+  void coarse(int l, bool init) {
+    const CoarseArgs a = make_coarse(l, init);
+    timed(INPAINT_K_COARSE, l, [&] { return launch_coarse_solve(a, C, s); });
+  }
+
+  // One V-cycle on level l for the problem held in (b_l, u_l).  On return
+  // (l > 0) u_l holds the correction; at l == 0 the residual of the finest
+  // grid and its norm are current.
+  void vcycle(int l) {
+    const int Lc = ws->L - 1;
+    if (l == Lc) {
+      coarse(l, l != 0);
+      if (l == 0) residual(0, true);
+      return;
+    }
+    for (int i = 0; i < o.pre; ++i) oras(l, false, i == o.pre - 1);
+    if (o.pre == 0) restrict_to(l);
+    vcycle(l + 1);
+    prolong(l, PASS_PCORR, l == 0 && o.post == 0);
+    for (int i = 0; i < o.post; ++i) oras(l, l == 0 && i == o.post - 1);
+  }
+
+  // Coarse-to-fine initial guess (Section 4.2): exact-ish solve on the
+  // coarsest grid, then on every finer level prolongate the solution, reset
+  // the known pixels and smooth with one ORAS iteration (reduced FMG) or a
+  // V-cycle (full FMG); the finest level is left to the V-cycles.
+  void cascade() {
+    const int Lc = ws->L - 1;
+    if (Lc == 0) {
+      residual(0, true);
+      return;
+    }
+    top = Lc;
+    coarse(Lc, true);
+    for (int l = Lc - 1; l >= 0; --l) {
+      top = l;
+      prolong(l, PASS_PSOL, l == 0);
+      if (l == 0) break;
+      if (o.schedule == INPAINT_SCHED_FMG)
+        vcycle(l);
+      else
+        oras(l, false);
+    }
+  }
+};
+
+struct SolveResult {
+  int status = INPAINT_OK;
+  double rel = 0.0;
+  int cycles = 0;
+};
+
+// Stage (f, mask) into level 0 and build the hierarchy; returns after the
+// input checks have been read back.
+void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy, bool write_u);
+SolveResult run_solve(Run& R, float* out_d);
+void check_dims(const void* a, const void* b, int W, int H, int C);
+bool overlap(const void* a, size_t na, const void* b, size_t nb);
+
+template <class Fn>
+int guarded(Fn&& fn) {
+  g_err.clear();
+  try {
+    return fn();
+  } catch (const Fail& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return INPAINT_E_NOMEM;
+  } catch (...) {
+    g_err = "unexpected exception";
+    return INPAINT_E_DEVICE;
+  }
+}
+
+}  // namespace inpaint

@@ -146,6 +146,74 @@ struct RestrictArgs {
   Sc s_rf, s_cr;
 };
 
+struct StageArgs {
+  const float* f;
+  const uint8_t* mask;
+  int W, H, Pf, C;
+  LevelView lv;
+  uint8_t* c;
+  float* b;
+  float* u;      // nullptr: not written
+  int* status;
+  NormOut den;
+};
+
+struct MaskArgs {
+  LevelView fl, cl;
+  const uint8_t* cf;
+  uint8_t* cc;
+};
+
+struct RhsArgs {
+  LevelView fl, cl;
+  const uint8_t* cf;
+  const void* bf;
+  const uint8_t* cc;
+  void* bc;
+  int C, naive;
+};
+
+struct OutputArgs {
+  LevelView lv;
+  const uint8_t* c;
+  const float* b;
+  const float* u[kMaxChannels];
+  float* out;
+  int Pout, C;
+};
+
+// Work items (workgroups) of one problem in each kernel; a batched launch
+// gives problem p the global items [start[p], start[p + 1]).
+unsigned work_stage(const StageArgs& a);
+unsigned work_mask(const MaskArgs& a);
+unsigned work_rhs(const RhsArgs& a);
+unsigned work_pass(const PassArgs& a, int C);
+unsigned work_restrict(const RestrictArgs& a, int C);
+unsigned work_block(const BlockArgs& a, int C);
+unsigned work_coarse(const CoarseArgs& a, int C);
+unsigned work_output(const OutputArgs& a);
+
+// Batched launches: `args` (device) holds n argument structs, `start` (device)
+// n + 1 offsets, `total` = start[n].  Every problem shares the kernel variant:
+// mode, precision, level0 (passes) and block side (block/coarse solves); the
+// channel count may differ between problems.
+hipError_t launch_stage_b(const StageArgs* args, const unsigned* start, int n, unsigned total,
+                          hipStream_t s);
+hipError_t launch_mask_b(const MaskArgs* args, const unsigned* start, int n, unsigned total,
+                         hipStream_t s);
+hipError_t launch_rhs_b(const RhsArgs* args, const unsigned* start, int n, unsigned total, int prec,
+                        int fine_f32, hipStream_t s);
+hipError_t launch_pass_b(int mode, const PassArgs* args, const unsigned* start, int n,
+                         unsigned total, int prec, int level0, hipStream_t s);
+hipError_t launch_restrict_b(const RestrictArgs* args, const unsigned* start, int n, unsigned total,
+                             int prec, int level0, hipStream_t s);
+hipError_t launch_block_b(const BlockArgs* args, const unsigned* start, int n, unsigned total,
+                          int prec, int level0, int B, hipStream_t s);
+hipError_t launch_coarse_b(const CoarseArgs* args, const unsigned* start, int n, unsigned total,
+                           int prec, int level0, int B, hipStream_t s);
+hipError_t launch_output_b(const OutputArgs* args, const unsigned* start, int n, unsigned total,
+                           hipStream_t s);
+
 // Launchers (all enqueue on `s`, return hipError_t of the launch).
 // Stage f and mask into level 0 (b = C f, c, and u = C f when u != nullptr),
 // check the input, and reduce ||b - A C f||^2 per channel into den.out.

@@ -140,32 +140,54 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned wg, unsigned n) {
   return xcd < rem ? xcd * (nper + 1) + idx : rem * (nper + 1) + (xcd - rem) * nper + idx;
 }
 
+// Problem owning global work item g of a batched launch: the largest p with
+// start[p] <= g (start[0] = 0, start[n] = total).
+__device__ __forceinline__ int find_problem(const unsigned* __restrict__ start, int n, unsigned g) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__host__ __device__ __forceinline__ unsigned px_groups(int W, int H) {
+  return (unsigned)((W + 63) / 64) * (unsigned)((H + 3) / 4);
+}
+
 // ---------------------------------------------------------------------------
 // staging and output
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_output(LevelView lv, const uint8_t* __restrict__ c,
-                                                const float* __restrict__ b, const float* u0,
-                                                const float* u1, const float* u2, const float* u3,
-                                                float* __restrict__ out, int Pout) {
-  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-  const int ch = blockIdx.z;
+__device__ __forceinline__ void output_body(const OutputArgs& a, unsigned lin) {
+  const LevelView& lv = a.lv;
+  const unsigned gxn = (unsigned)((lv.W + 63) / 64), per = px_groups(lv.W, lv.H);
+  const int ch = lin / per;
+  const unsigned q = lin - (unsigned)ch * per;
+  const int x = (int)(q % gxn) * 64 + (threadIdx.x & 63);
+  const int y = (int)(q / gxn) * 4 + (threadIdx.x >> 6);
   if (x >= lv.W || y >= lv.H) return;
-  const float* u = ch == 0 ? u0 : ch == 1 ? u1 : ch == 2 ? u2 : u3;
+  const float* u = a.u[ch];
   const size_t o = (size_t)y * lv.P + x;
   const size_t src = (size_t)ch * lv.plane + o;
-  out[(size_t)ch * Pout * lv.H + (size_t)y * Pout + x] = c[o] ? b[src] : u[src];
+  a.out[(size_t)ch * a.Pout * lv.H + (size_t)y * a.Pout + x] = a.c[o] ? a.b[src] : u[src];
 }
 
 // ---------------------------------------------------------------------------
 // coarse problems (Section 4.3)
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_mask_down(LevelView fl, const uint8_t* __restrict__ cf,
-                                                   LevelView cl, uint8_t* __restrict__ cc) {
-  const int X = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int Y = blockIdx.y * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void mask_body(const MaskArgs& a, unsigned lin) {
+  const LevelView& fl = a.fl;
+  const LevelView& cl = a.cl;
+  const uint8_t* __restrict__ cf = a.cf;
+  uint8_t* __restrict__ cc = a.cc;
+  const unsigned gxn = (unsigned)((cl.W + 63) / 64);
+  const int X = (int)(lin % gxn) * 64 + (threadIdx.x & 63);
+  const int Y = (int)(lin / gxn) * 4 + (threadIdx.x >> 6);
   if (X >= cl.W || Y >= cl.H) return;
   uint8_t m = 0;
   for (int dy = 0; dy < 2; ++dy)
@@ -182,12 +204,17 @@ __global__ void __launch_bounds__(256) k_mask_down(LevelView fl, const uint8_t* 
 // that cell's coarse mask; neighbours outside the image are not counted.  If
 // every weight is 0 the plain mean of the known children is used.
 template <class TF, class TC>
-__global__ void __launch_bounds__(256) k_rhs_down(LevelView fl, const uint8_t* __restrict__ cf,
-                                                  const TF* __restrict__ bf, LevelView cl,
-                                                  const uint8_t* __restrict__ cc,
-                                                  TC* __restrict__ bc, int C, int naive) {
-  const int X = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int Y = blockIdx.y * 4 + (threadIdx.x >> 6);
+__device__ __forceinline__ void rhs_body(const RhsArgs& a, unsigned lin) {
+  const LevelView& fl = a.fl;
+  const LevelView& cl = a.cl;
+  const uint8_t* __restrict__ cf = a.cf;
+  const uint8_t* __restrict__ cc = a.cc;
+  const TF* __restrict__ bf = (const TF*)a.bf;
+  TC* __restrict__ bc = (TC*)a.bc;
+  const int C = a.C, naive = a.naive;
+  const unsigned gxn = (unsigned)((cl.W + 63) / 64);
+  const int X = (int)(lin % gxn) * 64 + (threadIdx.x & 63);
+  const int Y = (int)(lin / gxn) * 4 + (threadIdx.x >> 6);
   if (X >= cl.W || Y >= cl.H) return;
   const size_t oc = (size_t)Y * cl.P + X;
   if (!cc[oc]) {
@@ -396,13 +423,18 @@ __global__ void k_fill(double* p, size_t n, double v) {
 // tile, input checks, and the residual of C f (the reference residual of the
 // relative residual):  at an unknown pixel it is the sum of the known
 // neighbours' values, at a known pixel 0.
-__global__ void __launch_bounds__(kPassThreads) k_stage(const float* __restrict__ f,
-                                                       const uint8_t* __restrict__ mask, int W,
-                                                       int H, int Pf, LevelView lv,
-                                                       uint8_t* __restrict__ c, float* __restrict__ b,
-                                                       float* __restrict__ u, int* __restrict__ status,
-                                                       NormOut den, unsigned tiles_x, unsigned ntiles) {
-  const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void stage_body(const StageArgs& a, unsigned lin) {
+  const float* __restrict__ f = a.f;
+  const uint8_t* __restrict__ mask = a.mask;
+  const int W = a.W, H = a.H, Pf = a.Pf;
+  const LevelView& lv = a.lv;
+  uint8_t* __restrict__ c = a.c;
+  float* __restrict__ b = a.b;
+  float* __restrict__ u = a.u;
+  int* __restrict__ status = a.status;
+  const NormOut& den = a.den;
+  const unsigned tiles_x = (unsigned)((lv.W + kTileW - 1) / kTileW);
+  const unsigned ntiles = tiles_x * (unsigned)((lv.H + kTileH - 1) / kTileH);
   const int ch = lin / ntiles;
   const unsigned tile = lin - (unsigned)ch * ntiles;
   const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
@@ -590,12 +622,12 @@ struct Former {
 //            r = b - (4u - (l + r + up + down)) elsewhere, in float64; write it
 //            (or keep it in LDS for the fused restriction); norm partial.
 template <int MODE, class TU, class TC>
-__global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tiles_x,
-                                                      unsigned ntiles) {
+__device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   constexpr int TW = kTileW + 2, TH = kTileH + 2;
   constexpr int NG = kPassThreads / kTileW;  // row groups
   constexpr int RJ = (TH + NG - 1) / NG;     // phase-1 rows per thread
-  const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
+  const unsigned tiles_x = (unsigned)((a.lv.W + kTileW - 1) / kTileW);
+  const unsigned ntiles = tiles_x * (unsigned)((a.lv.H + kTileH - 1) / kTileH);
   const int ch = lin / ntiles;
   const unsigned tile = lin - (unsigned)ch * ntiles;
   if (a.active && !a.active[ch]) return;
@@ -714,9 +746,9 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a, unsigned tile
 // ---------------------------------------------------------------------------
 
 template <class TF, class TC>
-__global__ void __launch_bounds__(kPassThreads) k_restrict(RestrictArgs a, unsigned tiles_x,
-                                                          unsigned ntiles) {
-  const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void restrict_body(const RestrictArgs& a, unsigned lin) {
+  const unsigned tiles_x = (unsigned)((a.cl.W + kTileW - 1) / kTileW);
+  const unsigned ntiles = tiles_x * (unsigned)((a.cl.H + kTileH - 1) / kTileH);
   const int ch = lin / ntiles;
   const unsigned tile = lin - (unsigned)ch * ntiles;
   if (a.active && !a.active[ch]) return;
@@ -862,8 +894,8 @@ __device__ __forceinline__ float pou_weight(int l, int nb, int k, int B, int o) 
 }
 
 template <int B, class TR, class TC>
-__global__ void __launch_bounds__(kWave) k_block_solve(BlockArgs a, unsigned nblk) {
-  const unsigned lin = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
+  const unsigned nblk = (unsigned)a.lv.nbx * (unsigned)a.lv.nby;
   const int ch = lin / nblk;
   const unsigned bi = lin - (unsigned)ch * nblk;
   if (a.active && !a.active[ch]) return;
@@ -904,8 +936,8 @@ __global__ void __launch_bounds__(kWave) k_block_solve(BlockArgs a, unsigned nbl
 // The coarsest grid is a single block.  Residual in float64 from u, then CG,
 // then u += v.  One wavefront per channel.
 template <int B, class T>
-__global__ void __launch_bounds__(kWave) k_coarse_solve(CoarseArgs a) {
-  const int ch = blockIdx.x;
+__device__ __forceinline__ void coarse_body(const CoarseArgs& a, unsigned lin) {
+  const int ch = (int)lin;
   if (a.active && !a.active[ch]) return;
   const LevelView& lv = a.lv;
   BlockCG<B> cg;
@@ -956,6 +988,98 @@ __global__ void __launch_bounds__(kWave) k_coarse_solve(CoarseArgs a) {
   (void)it;
 }
 
+// ---------------------------------------------------------------------------
+// kernels: one problem per launch (k_*) and batches of problems (k_*_b)
+// ---------------------------------------------------------------------------
+
+#define INPAINT_BATCH_LOOKUP(ARGS_T)                          \
+  const unsigned g = xcd_remap(blockIdx.x, gridDim.x);        \
+  const int p = find_problem(start, n, g);                    \
+  const ARGS_T a = args[p];                                   \
+  const unsigned lin = g - start[p];
+
+__global__ void __launch_bounds__(256) k_output(OutputArgs a) { output_body(a, xcd_remap(blockIdx.x, gridDim.x)); }
+__global__ void __launch_bounds__(256) k_output_b(const OutputArgs* __restrict__ args,
+                                                  const unsigned* __restrict__ start, int n) {
+  INPAINT_BATCH_LOOKUP(OutputArgs)
+  output_body(a, lin);
+}
+
+__global__ void __launch_bounds__(256) k_mask_down(MaskArgs a) { mask_body(a, xcd_remap(blockIdx.x, gridDim.x)); }
+__global__ void __launch_bounds__(256) k_mask_b(const MaskArgs* __restrict__ args,
+                                                const unsigned* __restrict__ start, int n) {
+  INPAINT_BATCH_LOOKUP(MaskArgs)
+  mask_body(a, lin);
+}
+
+template <class TF, class TC>
+__global__ void __launch_bounds__(256) k_rhs_down(RhsArgs a) {
+  rhs_body<TF, TC>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+template <class TF, class TC>
+__global__ void __launch_bounds__(256) k_rhs_b(const RhsArgs* __restrict__ args,
+                                               const unsigned* __restrict__ start, int n) {
+  INPAINT_BATCH_LOOKUP(RhsArgs)
+  rhs_body<TF, TC>(a, lin);
+}
+
+__global__ void __launch_bounds__(kPassThreads) k_stage(StageArgs a) {
+  stage_body(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+__global__ void __launch_bounds__(kPassThreads) k_stage_b(const StageArgs* __restrict__ args,
+                                                         const unsigned* __restrict__ start, int n) {
+  INPAINT_BATCH_LOOKUP(StageArgs)
+  stage_body(a, lin);
+}
+
+template <int MODE, class TU, class TC>
+__global__ void __launch_bounds__(kPassThreads) k_pass(PassArgs a) {
+  pass_body<MODE, TU, TC>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+template <int MODE, class TU, class TC>
+__global__ void __launch_bounds__(kPassThreads) k_pass_b(const PassArgs* __restrict__ args,
+                                                        const unsigned* __restrict__ start, int n) {
+  INPAINT_BATCH_LOOKUP(PassArgs)
+  pass_body<MODE, TU, TC>(a, lin);
+}
+
+template <class TF, class TC>
+__global__ void __launch_bounds__(kPassThreads) k_restrict(RestrictArgs a) {
+  restrict_body<TF, TC>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+template <class TF, class TC>
+__global__ void __launch_bounds__(kPassThreads) k_restrict_b(const RestrictArgs* __restrict__ args,
+                                                            const unsigned* __restrict__ start, int n) {
+  INPAINT_BATCH_LOOKUP(RestrictArgs)
+  restrict_body<TF, TC>(a, lin);
+}
+
+template <int B, class TR, class TC>
+__global__ void __launch_bounds__(kWave) k_block_solve(BlockArgs a) {
+  block_body<B, TR, TC>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+template <int B, class TR, class TC>
+__global__ void __launch_bounds__(kWave) k_block_b(const BlockArgs* __restrict__ args,
+                                                   const unsigned* __restrict__ start, int n) {
+  INPAINT_BATCH_LOOKUP(BlockArgs)
+  block_body<B, TR, TC>(a, lin);
+}
+
+template <int B, class T>
+__global__ void __launch_bounds__(kWave) k_coarse_solve(CoarseArgs a) {
+  coarse_body<B, T>(a, blockIdx.x);
+}
+template <int B, class T>
+__global__ void __launch_bounds__(kWave) k_coarse_b(const CoarseArgs* __restrict__ args,
+                                                    const unsigned* __restrict__ start, int n) {
+  const unsigned g = blockIdx.x;
+  const int p = find_problem(start, n, g);
+  const CoarseArgs a = args[p];
+  coarse_body<B, T>(a, g - start[p]);
+}
+
+#undef INPAINT_BATCH_LOOKUP
+
 dim3 px_grid(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
 
 }  // namespace
@@ -971,58 +1095,68 @@ hipError_t launch_fill(double* p, size_t n, double v, hipStream_t s) {
   return hipGetLastError();
 }
 
+size_t prec_bytes(int prec) { return prec == PREC_F32 ? 4 : 2; }
+
 size_t pass_tiles(const LevelView& lv) {
   return (size_t)((lv.W + kTileW - 1) / kTileW) * (size_t)((lv.H + kTileH - 1) / kTileH);
 }
 
+// ---------------------------------------------------------------------------
+// work counts (workgroups per problem)
+// ---------------------------------------------------------------------------
+
+unsigned work_stage(const StageArgs& a) { return (unsigned)pass_tiles(a.lv) * (unsigned)a.C; }
+unsigned work_mask(const MaskArgs& a) { return px_groups(a.cl.W, a.cl.H); }
+unsigned work_rhs(const RhsArgs& a) { return px_groups(a.cl.W, a.cl.H); }
+unsigned work_pass(const PassArgs& a, int C) { return (unsigned)pass_tiles(a.lv) * (unsigned)C; }
+unsigned work_restrict(const RestrictArgs& a, int C) { return (unsigned)pass_tiles(a.cl) * (unsigned)C; }
+unsigned work_block(const BlockArgs& a, int C) {
+  return (unsigned)a.lv.nbx * (unsigned)a.lv.nby * (unsigned)C;
+}
+unsigned work_coarse(const CoarseArgs&, int C) { return (unsigned)C; }
+unsigned work_output(const OutputArgs& a) { return px_groups(a.lv.W, a.lv.H) * (unsigned)a.C; }
+
+// ---------------------------------------------------------------------------
+// single-problem launchers
+// ---------------------------------------------------------------------------
+
 hipError_t launch_stage(const float* f, const uint8_t* mask, int W, int H, int C, int Pf,
                         LevelView lv, uint8_t* c, float* b, float* u, int* status, NormOut den,
                         hipStream_t s) {
-  const unsigned tx = (lv.W + kTileW - 1) / kTileW;
-  const unsigned nt = (unsigned)pass_tiles(lv);
-  hipLaunchKernelGGL(k_stage, dim3(nt * (unsigned)C), dim3(kPassThreads), 0, s, f, mask, W, H, Pf, lv,
-                     c, b, u, status, den, tx, nt);
+  const StageArgs a{f, mask, W, H, Pf, C, lv, c, b, u, status, den};
+  hipLaunchKernelGGL(k_stage, dim3(work_stage(a)), dim3(kPassThreads), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_mask_down(LevelView fine, const uint8_t* cf, LevelView coarse, uint8_t* cc,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_mask_down, px_grid(coarse.W, coarse.H), dim3(256), 0, s, fine, cf, coarse, cc);
+  const MaskArgs a{fine, coarse, cf, cc};
+  hipLaunchKernelGGL(k_mask_down, dim3(work_mask(a)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_rhs_down(LevelView fine, const uint8_t* cf, const void* bf, LevelView coarse,
                            const uint8_t* cc, void* bc, int C, int naive, int prec, int fine_f32,
                            hipStream_t s) {
+  const RhsArgs a{fine, coarse, cf, bf, cc, bc, C, naive};
   return with_types(prec, fine_f32, [&](auto tf, auto tc) {
     using TF = typename decltype(tf)::type;
     using TC = typename decltype(tc)::type;
-    hipLaunchKernelGGL((k_rhs_down<TF, TC>), px_grid(coarse.W, coarse.H), dim3(256), 0, s, fine, cf,
-                       (const TF*)bf, coarse, cc, (TC*)bc, C, naive);
+    hipLaunchKernelGGL((k_rhs_down<TF, TC>), dim3(work_rhs(a)), dim3(256), 0, s, a);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_pass(int mode, const PassArgs& a, int C, hipStream_t s) {
-  const unsigned tx = (a.lv.W + kTileW - 1) / kTileW;
-  const unsigned nt = (unsigned)pass_tiles(a.lv);
-  const dim3 grid(nt * (unsigned)C);
+  const dim3 grid(work_pass(a, C));
   return with_types(a.prec, a.level0, [&](auto tu, auto tc) {
     using TU = typename decltype(tu)::type;
     using TC = typename decltype(tc)::type;
     switch (mode) {
-      case PASS_RES:
-        hipLaunchKernelGGL((k_pass<PASS_RES, TU, TC>), grid, dim3(kPassThreads), 0, s, a, tx, nt);
-        break;
-      case PASS_UPD:
-        hipLaunchKernelGGL((k_pass<PASS_UPD, TU, TC>), grid, dim3(kPassThreads), 0, s, a, tx, nt);
-        break;
-      case PASS_PSOL:
-        hipLaunchKernelGGL((k_pass<PASS_PSOL, TU, TC>), grid, dim3(kPassThreads), 0, s, a, tx, nt);
-        break;
-      case PASS_PCORR:
-        hipLaunchKernelGGL((k_pass<PASS_PCORR, TU, TC>), grid, dim3(kPassThreads), 0, s, a, tx, nt);
-        break;
+      case PASS_RES: hipLaunchKernelGGL((k_pass<PASS_RES, TU, TC>), grid, dim3(kPassThreads), 0, s, a); break;
+      case PASS_UPD: hipLaunchKernelGGL((k_pass<PASS_UPD, TU, TC>), grid, dim3(kPassThreads), 0, s, a); break;
+      case PASS_PSOL: hipLaunchKernelGGL((k_pass<PASS_PSOL, TU, TC>), grid, dim3(kPassThreads), 0, s, a); break;
+      case PASS_PCORR: hipLaunchKernelGGL((k_pass<PASS_PCORR, TU, TC>), grid, dim3(kPassThreads), 0, s, a); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1030,26 +1164,23 @@ hipError_t launch_pass(int mode, const PassArgs& a, int C, hipStream_t s) {
 }
 
 hipError_t launch_restrict(const RestrictArgs& a, int C, hipStream_t s) {
-  const unsigned tx = (a.cl.W + kTileW - 1) / kTileW;
-  const unsigned nt = (unsigned)pass_tiles(a.cl);
   return with_types(a.prec, a.level0, [&](auto tf, auto tc) {
     using TF = typename decltype(tf)::type;
     using TC = typename decltype(tc)::type;
-    hipLaunchKernelGGL((k_restrict<TF, TC>), dim3(nt * (unsigned)C), dim3(kPassThreads), 0, s, a, tx, nt);
+    hipLaunchKernelGGL((k_restrict<TF, TC>), dim3(work_restrict(a, C)), dim3(kPassThreads), 0, s, a);
     return hipGetLastError();
   });
 }
 
 hipError_t launch_block_solve(const BlockArgs& a, int C, hipStream_t s) {
-  const unsigned nblk = (unsigned)a.lv.nbx * (unsigned)a.lv.nby;
-  const dim3 grid(nblk * (unsigned)C);
+  const dim3 grid(work_block(a, C));
   return with_types(a.prec, a.level0, [&](auto tr, auto tc) {
     using TR = typename decltype(tr)::type;
     using TC = typename decltype(tc)::type;
     if (a.lv.B == 32)
-      hipLaunchKernelGGL((k_block_solve<32, TR, TC>), grid, dim3(kWave), 0, s, a, nblk);
+      hipLaunchKernelGGL((k_block_solve<32, TR, TC>), grid, dim3(kWave), 0, s, a);
     else if (a.lv.B == 16)
-      hipLaunchKernelGGL((k_block_solve<16, TR, TC>), grid, dim3(kWave), 0, s, a, nblk);
+      hipLaunchKernelGGL((k_block_solve<16, TR, TC>), grid, dim3(kWave), 0, s, a);
     else
       return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1070,14 +1201,113 @@ hipError_t launch_coarse_solve(const CoarseArgs& a, int C, hipStream_t s) {
   });
 }
 
-size_t prec_bytes(int prec) { return prec == PREC_F32 ? 4 : 2; }
-
 hipError_t launch_output(LevelView lv, const uint8_t* c, const float* b, const float* const* u_sel,
                          float* out, int Pout, int C, hipStream_t s) {
-  dim3 g = px_grid(lv.W, lv.H);
-  g.z = C;
-  hipLaunchKernelGGL(k_output, g, dim3(256), 0, s, lv, c, b, u_sel[0], C > 1 ? u_sel[1] : u_sel[0],
-                     C > 2 ? u_sel[2] : u_sel[0], C > 3 ? u_sel[3] : u_sel[0], out, Pout);
+  OutputArgs a{};
+  a.lv = lv;
+  a.c = c;
+  a.b = b;
+  for (int ch = 0; ch < kMaxChannels; ++ch) a.u[ch] = u_sel[ch < C ? ch : 0];
+  a.out = out;
+  a.Pout = Pout;
+  a.C = C;
+  hipLaunchKernelGGL(k_output, dim3(work_output(a)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_stage_b(const StageArgs* args, const unsigned* start, int n, unsigned total,
+                          hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stage_b, dim3(total), dim3(kPassThreads), 0, s, args, start, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_b(const MaskArgs* args, const unsigned* start, int n, unsigned total,
+                         hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mask_b, dim3(total), dim3(256), 0, s, args, start, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_b(const RhsArgs* args, const unsigned* start, int n, unsigned total, int prec,
+                        int fine_f32, hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  return with_types(prec, fine_f32, [&](auto tf, auto tc) {
+    using TF = typename decltype(tf)::type;
+    using TC = typename decltype(tc)::type;
+    hipLaunchKernelGGL((k_rhs_b<TF, TC>), dim3(total), dim3(256), 0, s, args, start, n);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_pass_b(int mode, const PassArgs* args, const unsigned* start, int n,
+                         unsigned total, int prec, int level0, hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  const dim3 grid(total);
+  return with_types(prec, level0, [&](auto tu, auto tc) {
+    using TU = typename decltype(tu)::type;
+    using TC = typename decltype(tc)::type;
+    switch (mode) {
+      case PASS_RES: hipLaunchKernelGGL((k_pass_b<PASS_RES, TU, TC>), grid, dim3(kPassThreads), 0, s, args, start, n); break;
+      case PASS_UPD: hipLaunchKernelGGL((k_pass_b<PASS_UPD, TU, TC>), grid, dim3(kPassThreads), 0, s, args, start, n); break;
+      case PASS_PSOL: hipLaunchKernelGGL((k_pass_b<PASS_PSOL, TU, TC>), grid, dim3(kPassThreads), 0, s, args, start, n); break;
+      case PASS_PCORR: hipLaunchKernelGGL((k_pass_b<PASS_PCORR, TU, TC>), grid, dim3(kPassThreads), 0, s, args, start, n); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_restrict_b(const RestrictArgs* args, const unsigned* start, int n, unsigned total,
+                             int prec, int level0, hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  return with_types(prec, level0, [&](auto tf, auto tc) {
+    using TF = typename decltype(tf)::type;
+    using TC = typename decltype(tc)::type;
+    hipLaunchKernelGGL((k_restrict_b<TF, TC>), dim3(total), dim3(kPassThreads), 0, s, args, start, n);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_block_b(const BlockArgs* args, const unsigned* start, int n, unsigned total,
+                          int prec, int level0, int B, hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  return with_types(prec, level0, [&](auto tr, auto tc) {
+    using TR = typename decltype(tr)::type;
+    using TC = typename decltype(tc)::type;
+    if (B == 32)
+      hipLaunchKernelGGL((k_block_b<32, TR, TC>), dim3(total), dim3(kWave), 0, s, args, start, n);
+    else if (B == 16)
+      hipLaunchKernelGGL((k_block_b<16, TR, TC>), dim3(total), dim3(kWave), 0, s, args, start, n);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_coarse_b(const CoarseArgs* args, const unsigned* start, int n, unsigned total,
+                           int prec, int level0, int B, hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  return with_types(prec, level0, [&](auto tu, auto) {
+    using T = typename decltype(tu)::type;
+    if (B == 32)
+      hipLaunchKernelGGL((k_coarse_b<32, T>), dim3(total), dim3(kWave), 0, s, args, start, n);
+    else if (B == 16)
+      hipLaunchKernelGGL((k_coarse_b<16, T>), dim3(total), dim3(kWave), 0, s, args, start, n);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_output_b(const OutputArgs* args, const unsigned* start, int n, unsigned total,
+                           hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_output_b, dim3(total), dim3(256), 0, s, args, start, n);
   return hipGetLastError();
 }
 

@@ -49,4 +49,7 @@ def test_host_only_calls_without_gpu():
 def test_opts_struct_layout_matches_header():
     # 15 fields of 4 bytes each
     assert ctypes.sizeof(binding.InpaintOpts) == 15 * 4
-    assert ctypes.sizeof(binding.InpaintStats) == 8 + 3 * 4 + 4 + 8 + 4 + 4 + 8 + 8 + 8 + 9 * 4 + 9 * 4
+    # ... + status, padding, three serving times
+    assert ctypes.sizeof(binding.InpaintStats) == (8 + 3 * 4 + 4 + 8 + 4 + 4 + 8 + 8 + 8 + 9 * 4 + 9 * 4
+                                                   + 4 + 4 + 3 * 8)
+    assert ctypes.sizeof(binding.InpaintProblem) == 8 + 8 + 3 * 4 + 4 + 8

@@ -1,0 +1,165 @@
+"""Batched solve through the C ABI: every problem's result is bit-identical to
+the solve of that problem alone (same options), and meets the parity bar
+against the oracle (relative residual <= 1e-6, known pixels bit-exact, max abs
+error <= 0.5 grey levels)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_06744_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+def _mix(seed=0):
+    """Uneven sizes, 1-4 channels, a single-level problem, thin strips."""
+    spec = [(77, 53, 1, 0.05), (300, 17, 3, 0.05), (20, 24, 1, 0.2), (129, 257, 4, 0.02),
+            (1, 100, 1, 0.1), (511, 383, 3, 0.04), (33, 33, 2, 0.1), (640, 360, 1, 0.01)]
+    probs = []
+    for k, (W, H, C, d) in enumerate(spec):
+        probs.append((synth.frame_image(W, H, C, seed=seed + 10 * k + 1),
+                      synth.bernoulli_mask(W, H, d, seed=seed + 10 * k + 2)))
+    return probs
+
+
+def _solo(probs, **kw):
+    opts = binding.make_opts(**kw) if kw else None
+    return [binding.inpaint_solve_ex(f, m, TOL, opts=opts)[0] for f, m in probs]
+
+
+@pytest.mark.parametrize("kw", [
+    {}, {"schedule": binding.SCHED_FMG}, {"schedule": binding.SCHED_MULTILEVEL},
+    {"schedule": binding.SCHED_SINGLE}, {"pre_smooth": 2, "post_smooth": -1},
+    {"pre_smooth": -1, "post_smooth": 2}, {"block": 16, "overlap": 4},
+    {"precision": binding.PREC_FP16}, {"precision": binding.PREC_BF16},
+])
+def test_batched_equals_solo_bitwise(kw):
+    probs = _mix()
+    if kw.get("schedule") == binding.SCHED_SINGLE:
+        probs = [probs[0], probs[2], probs[4], probs[6]]
+    opts = binding.make_opts(**kw) if kw else None
+    outs, st, stats = binding.inpaint_solve_batched(probs, TOL, opts=opts)
+    assert st == binding.OK
+    solo = _solo(probs, **kw)
+    for k, (o, s) in enumerate(zip(outs, solo)):
+        assert stats[k]["status"] == binding.OK
+        assert np.array_equal(o, s), f"problem {k} differs from its solo solve"
+
+
+def test_batched_matches_oracle_and_reports_stats():
+    probs = _mix(seed=100)
+    outs, st, stats = binding.inpaint_solve_batched(probs, TOL)
+    assert st == binding.OK
+    for k, ((f, m), u) in enumerate(zip(probs, outs)):
+        kn = m != 0
+        for ch in range(f.shape[0]):
+            assert np.array_equal(u[ch][kn], f[ch][kn])
+        rr = oracle.rel_res(u.astype(np.float64), f.astype(np.float64), m)
+        assert np.all(rr <= TOL), (k, rr)
+        assert stats[k]["rel_res"] == pytest.approx(float(rr.max()), rel=1e-6, abs=1e-12)
+        ref = oracle.solve_pcg(f.astype(np.float64), m)
+        assert np.abs(u.astype(np.float64) - ref).max() <= 0.5
+        assert stats[k]["levels"] == binding.inpaint_hierarchy_size(f.shape[2], f.shape[1])[0]
+        assert stats[k]["gpu_ms"] > 0
+
+
+def test_batched_device_pointers_repeat_and_alias():
+    import torch
+    probs = _mix(seed=200)
+    ref, _, _ = binding.inpaint_solve_batched(probs, TOL)
+    dev = [(torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()) for f, m in probs]
+    for _ in range(2):  # the second call reuses the cached plans and graphs
+        outs, st, _ = binding.inpaint_solve_batched(dev, TOL)
+        torch.cuda.synchronize()
+        assert st == binding.OK
+        for o, r in zip(outs, ref):
+            assert np.array_equal(o.cpu().numpy(), r)
+    alias = [(f.clone(), m, None) for f, m in dev]
+    alias = [(f, m, f) for f, m, _ in alias]
+    binding.inpaint_solve_batched(alias, TOL)
+    torch.cuda.synchronize()
+    for (f, _, _), r in zip(alias, ref):
+        assert np.array_equal(f.cpu().numpy(), r)
+
+
+def test_batched_rejected_problems_leave_the_others_alone():
+    probs = _mix(seed=300)[:4]
+    empty = (probs[1][0], np.zeros_like(probs[1][1]))
+    g = probs[2][0].copy()
+    k = np.argwhere(probs[2][1])[0]
+    g[0, k[0], k[1]] = np.inf
+    bad = [probs[0], empty, (g, probs[2][1]), probs[3]]
+    outs, st, stats = binding.inpaint_solve_batched(bad, TOL, raise_on_error=False)
+    assert st == binding.E_EMPTY_MASK
+    assert [s["status"] for s in stats] == [binding.OK, binding.E_EMPTY_MASK, binding.E_INVALID,
+                                            binding.OK]
+    solo = _solo([probs[0], probs[3]])
+    assert np.array_equal(outs[0], solo[0]) and np.array_equal(outs[3], solo[1])
+    # the same workspaces with every problem valid again (plans are rebuilt)
+    outs2, st2, _ = binding.inpaint_solve_batched(probs, TOL)
+    assert st2 == binding.OK
+    for o, s in zip(outs2, _solo(probs)):
+        assert np.array_equal(o, s)
+
+
+def test_batched_argument_errors():
+    probs = _mix()[:2]
+    with pytest.raises(binding.InpaintError) as e:
+        binding.inpaint_solve_batched([], TOL)
+    assert e.value.code == binding.E_INVALID
+    f, m = probs[0]
+    with pytest.raises(binding.InpaintError) as e:
+        binding.inpaint_solve_batched([probs[0], (np.zeros((5, 8, 8), np.float32),
+                                                  np.ones((8, 8), np.uint8))], TOL)
+    assert e.value.code == binding.E_INVALID
+    shared = np.empty_like(f)
+    with pytest.raises(binding.InpaintError) as e:
+        binding.inpaint_solve_batched([(f, m, shared), (f, m, shared)], TOL)
+    assert e.value.code == binding.E_INVALID
+    with pytest.raises(binding.InpaintError) as e:
+        binding.inpaint_solve_batched(probs, TOL, opts=binding.make_opts(block=24))
+    assert e.value.code == binding.E_INVALID
+
+
+def test_batched_not_converged_is_per_problem():
+    probs = _mix(seed=400)[:3]
+    outs, st, stats = binding.inpaint_solve_batched(probs, 1e-14,
+                                                    opts=binding.make_opts(max_cycles=2),
+                                                    raise_on_error=False)
+    assert st == binding.NOT_CONVERGED
+    for (f, m), u, s in zip(probs, outs, stats):
+        assert s["status"] == binding.NOT_CONVERGED and s["cycles"] == 2
+        assert np.array_equal(u[:, m != 0], f[:, m != 0])
+
+
+@pytest.mark.timeout(900)
+def test_batched_64_uneven_problems():
+    """The 64-problem workload (uneven sizes up to 1920x1080, 1 or 3 channels,
+    1-10 % masks) in the launch configuration the benchmark times: every
+    problem to 1e-6 with known pixels exact; the two smallest also against the
+    oracle's solution and a handful bit-for-bit against their solo solves."""
+    import torch
+    probs = synth.batched_problems()
+    dev = [(torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()) for f, m in probs]
+    outs, st, stats = binding.inpaint_solve_batched(dev, TOL)
+    torch.cuda.synchronize()
+    assert st == binding.OK
+    host = [o.cpu().numpy() for o in outs]
+    for k, ((f, m), u) in enumerate(zip(probs, host)):
+        kn = m != 0
+        assert np.array_equal(u[:, kn], f[:, kn]), k
+        rr = oracle.rel_res(u.astype(np.float64), f.astype(np.float64), m)
+        assert np.all(rr <= TOL), (k, rr)
+    order = sorted(range(len(probs)), key=lambda k: probs[k][0].size)
+    for k in order[:2]:
+        f, m = probs[k]
+        ref = oracle.solve_pcg(f.astype(np.float64), m)
+        assert np.abs(host[k].astype(np.float64) - ref).max() <= 0.5
+    for k in order[::16]:
+        solo, _, _ = binding.inpaint_solve_ex(dev[k][0], dev[k][1], TOL)
+        torch.cuda.synchronize()
+        assert np.array_equal(solo.cpu().numpy(), host[k]), k
+    print(f"64-problem batch: {stats[0]['gpu_ms']:.2f} ms, cycles "
+          f"{sorted(set(s['cycles'] for s in stats))}", flush=True)
