@@ -46,6 +46,7 @@ extern "C" {
 typedef enum inpaint_status {
   INPAINT_OK = 0,
   INPAINT_NOT_CONVERGED = 1, /* cycle cap reached; out holds the last iterate */
+  INPAINT_PENDING = 2,       /* inpaint_server_poll: the request has not finished yet */
   INPAINT_E_INVALID = -1,    /* bad argument, overlapping buffers, non-finite f at a known pixel */
   INPAINT_E_EMPTY_MASK = -2, /* no known pixel: the system is singular (any constant solves it) */
   INPAINT_E_NOMEM = -3,      /* device or pinned host allocation failed */
@@ -207,6 +208,55 @@ typedef struct inpaint_problem {
  */
 int inpaint_solve_batched(const inpaint_problem* problems, int n, double tol,
                           const inpaint_opts* opts, void* stream, inpaint_stats* stats);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching on one device.
+ *
+ * Requests are admitted in submission order while a batch slot is free and
+ * their hierarchy (plus staging for host buffers) fits the server's HBM
+ * budget; idle hierarchies of other sizes are freed to make room, and a
+ * request that does not fit waits in the queue.  Admitted requests join the
+ * running batch at the next V-cycle boundary and leave it when they converge,
+ * so requests that arrive while others are on the device share every batched
+ * launch with them.  Hierarchies stay on the device between requests of the
+ * same size.  Each request runs the same arithmetic as a solve of it alone, so
+ * its result is bit-identical to inpaint_solve_ex with the server's options,
+ * whatever else is in the batch.
+ * ------------------------------------------------------------------------- */
+
+typedef struct inpaint_server inpaint_server; /* opaque */
+
+typedef struct inpaint_server_cfg {
+  int struct_size;   /* sizeof(inpaint_server_cfg) */
+  int max_batch;     /* requests in the running batch at most, 1..1024 (0 = 64) */
+  size_t hbm_budget; /* device bytes for the requests' hierarchies and staging
+                        (0 = 80 % of the device memory free at creation) */
+  inpaint_opts opts; /* options of every request (opts.struct_size == 0: all
+                        defaults; opts.profile is ignored) */
+} inpaint_server_cfg;
+
+/* Start a server on the calling thread's current device (cfg NULL = defaults).
+   The server runs its own thread and its own HIP stream. */
+int inpaint_server_create(const inpaint_server_cfg* cfg, inpaint_server** srv);
+
+/* Queue one problem with its tolerance; returns at once with a ticket.  The
+   caller keeps f, mask and out valid and unchanged until the ticket has been
+   collected.  Bad arguments: E_INVALID; a hierarchy larger than the whole
+   budget: E_NOMEM (nothing queued). */
+int inpaint_server_submit(inpaint_server* srv, const inpaint_problem* p, double tol,
+                          uint64_t* ticket);
+
+/* INPAINT_PENDING while the request runs; afterwards its inpaint_status, with
+   its statistics in *st (may be NULL) including t_submit_ms, t_start_ms and
+   t_done_ms, and the ticket is collected (a later call on it is E_INVALID). */
+int inpaint_server_poll(inpaint_server* srv, uint64_t ticket, inpaint_stats* st);
+
+/* As inpaint_server_poll, but blocks until the request has finished. */
+int inpaint_server_wait(inpaint_server* srv, uint64_t ticket, inpaint_stats* st);
+
+/* Finish every submitted request, stop the loop and free the server's device
+   memory.  Tickets not collected before are lost. */
+void inpaint_server_destroy(inpaint_server* srv);
 
 /* Message for the last error on the calling thread ("" if none). */
 const char* inpaint_last_error(void);

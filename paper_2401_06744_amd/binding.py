@@ -18,7 +18,8 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "li
 _lib = None
 _lock = threading.Lock()
 
-OK, NOT_CONVERGED, E_INVALID, E_EMPTY_MASK, E_NOMEM, E_DEVICE, E_DIVERGED = 0, 1, -1, -2, -3, -4, -5
+OK, NOT_CONVERGED, PENDING = 0, 1, 2
+E_INVALID, E_EMPTY_MASK, E_NOMEM, E_DEVICE, E_DIVERGED = -1, -2, -3, -4, -5
 KERNELS = ["stage", "pyramid", "block_solve", "update", "prolong", "restrict", "coarse",
            "residual", "output"]
 SCHED_RFMG, SCHED_FMG, SCHED_MULTILEVEL, SCHED_SINGLE = 0, 1, 2, 3
@@ -29,7 +30,8 @@ EXPORTED = [
     "inpaint_solve", "inpaint_solve_ex", "inpaint_rel_res", "inpaint_last_error",
     "inpaint_version", "inpaint_hierarchy_size", "inpaint_debug_pyramid",
     "inpaint_debug_oras_step", "inpaint_debug_restrict", "inpaint_debug_prolong",
-    "inpaint_solve_batched",
+    "inpaint_solve_batched", "inpaint_server_create", "inpaint_server_submit",
+    "inpaint_server_poll", "inpaint_server_wait", "inpaint_server_destroy",
 ]
 
 
@@ -67,6 +69,11 @@ class InpaintProblem(ct.Structure):
                 ("channels", ct.c_int), ("out", ct.c_void_p)]
 
 
+class InpaintServerCfg(ct.Structure):
+    _fields_ = [("struct_size", ct.c_int), ("max_batch", ct.c_int), ("hbm_budget", ct.c_size_t),
+                ("opts", InpaintOpts)]
+
+
 class InpaintError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"inpaint error {code}: {msg}")
@@ -100,9 +107,16 @@ def lib() -> ct.CDLL:
         L.inpaint_debug_prolong.argtypes = [vp, i, i, vp, vp, vp, i, vp]
         L.inpaint_solve_batched.argtypes = [ct.POINTER(InpaintProblem), i, d,
                                             ct.POINTER(InpaintOpts), vp, ct.POINTER(InpaintStats)]
+        L.inpaint_server_create.argtypes = [ct.POINTER(InpaintServerCfg), ct.POINTER(vp)]
+        L.inpaint_server_submit.argtypes = [vp, ct.POINTER(InpaintProblem), d,
+                                            ct.POINTER(ct.c_uint64)]
+        L.inpaint_server_poll.argtypes = [vp, ct.c_uint64, ct.POINTER(InpaintStats)]
+        L.inpaint_server_wait.argtypes = [vp, ct.c_uint64, ct.POINTER(InpaintStats)]
+        L.inpaint_server_destroy.argtypes = [vp]
+        L.inpaint_server_destroy.restype = None
         for name in EXPORTED:
             fn = getattr(L, name)
-            if fn.restype is ct.c_int or fn.restype is None:
+            if name != "inpaint_server_destroy" and (fn.restype is ct.c_int or fn.restype is None):
                 fn.restype = ct.c_int
         L.inpaint_last_error.restype = ct.c_char_p
         L.inpaint_version.restype = ct.c_char_p
@@ -220,6 +234,66 @@ def inpaint_solve_batched(problems, tol: float = 1e-6, opts: InpaintOpts | None 
     if raise_on_error:
         _check(st)
     return outs, st, [stats[k].as_dict() for k in range(len(problems))]
+
+
+class ServerHandle:
+    """A running server: the C handle plus references to the buffers of every
+    uncollected ticket, so that they stay alive while the device uses them."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        self.buffers = {}
+
+
+def inpaint_server_create(max_batch: int = 0, hbm_budget: int = 0,
+                          opts: InpaintOpts | None = None) -> ServerHandle:
+    cfg = InpaintServerCfg()
+    cfg.struct_size = ct.sizeof(InpaintServerCfg)
+    cfg.max_batch = max_batch
+    cfg.hbm_budget = hbm_budget
+    if opts is not None:
+        cfg.opts = opts
+    h = ct.c_void_p()
+    _check(lib().inpaint_server_create(ct.byref(cfg), ct.byref(h)))
+    return ServerHandle(h)
+
+
+def inpaint_server_submit(srv: ServerHandle, f, mask, out=None, tol: float = 1e-6) -> int:
+    """Queue (f, mask); returns the ticket.  The output buffer is returned by
+    inpaint_server_wait / inpaint_server_poll."""
+    arr, outs = _problems([(f, mask, out)])
+    t = ct.c_uint64(0)
+    _check(lib().inpaint_server_submit(srv.handle, arr, tol, ct.byref(t)))
+    srv.buffers[t.value] = (f, mask, outs[0])
+    return t.value
+
+
+def _collect(srv: ServerHandle, ticket: int, fn, raise_on_error: bool):
+    st = InpaintStats()
+    code = fn(srv.handle, ticket, ct.byref(st))
+    if code == PENDING:
+        return None
+    bufs = srv.buffers.pop(ticket, (None, None, None))
+    if raise_on_error:
+        _check(code)
+    return bufs[2], code, st.as_dict()
+
+
+def inpaint_server_poll(srv: ServerHandle, ticket: int, raise_on_error: bool = True):
+    """None while the request runs, else (out, status, stats dict)."""
+    return _collect(srv, ticket, lib().inpaint_server_poll, raise_on_error)
+
+
+def inpaint_server_wait(srv: ServerHandle, ticket: int, raise_on_error: bool = True):
+    """Block until the request has finished; returns (out, status, stats dict)."""
+    return _collect(srv, ticket, lib().inpaint_server_wait, raise_on_error)
+
+
+def inpaint_server_destroy(srv: ServerHandle) -> None:
+    if srv.handle:
+        lib().inpaint_server_destroy(srv.handle)
+        srv.handle = None
+        srv.buffers.clear()
 
 
 def inpaint_rel_res(u, f, mask) -> np.ndarray:

@@ -95,6 +95,57 @@ struct Member {
   int Lc() const { return ws->L - 1; }
 };
 
+// Plan builders.  Each walks the members in lockstep by level and calls their
+// Run's argument builders in the order a solve of that member alone launches.
+// Prepare: reset flags, stage (f, mask) into level 0 with the reference
+// residual, coarse masks and known values level by level, gather the flags.
+void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* flags_dev);
+// The coarse-to-fine initial guess (Section 4.2).
+void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o);
+// One V-cycle on the finest grid (one finest ORAS iteration for the
+// multilevel and single-level schedules).
+void build_cycle(Plan& P, const std::vector<Member*>& ms, const Opts& o);
+void build_output(Plan& P, const std::vector<Member*>& ms);
+// Copy of each member's flag block to flags_dev + 16 * member.slot.
+void add_gather(Plan& P, const std::vector<Member*>& ms, int* flags_dev);
+
+// Build a plan with `body` and record, per member, what one run of it adds to
+// the member's counters and which level-0 buffer holds the iterate afterwards.
+template <class Body>
+void build(Plan& P, const std::vector<Member*>& ms, Body&& body) {
+  std::vector<std::array<long long, 3>> before;
+  for (Member* m : ms) before.push_back({m->R->oras_iters, m->R->block_solves, m->R->finest_block_solves});
+  body();
+  P.delta.clear();
+  P.cur0.clear();
+  for (size_t i = 0; i < ms.size(); ++i) {
+    const Run& R = *ms[i]->R;
+    P.delta.push_back({R.oras_iters - before[i][0], R.block_solves - before[i][1],
+                       R.finest_block_solves - before[i][2]});
+    P.cur0.push_back(ms[i]->ws->lv[0].cur);
+  }
+}
+
+// Copy the plans' argument arrays into one device buffer owned by `*buf`
+// (grown as needed) and point each plan at its part.
+void upload(std::vector<Plan*> plans, unsigned char** buf, size_t* cap, hipStream_t s);
+
+// Set up member m for problem p on workspace ws: stage host inputs, pick the
+// output buffer.  m.idx and m.slot are set by the caller.
+void init_member(Member& m, const inpaint_problem& p, Workspace* ws, const Opts& o, double tol,
+                 hipStream_t s);
+// Throws Fail (E_INVALID) for a bad problem; i >= 0 names it in the message.
+void validate_problem(const inpaint_problem& p, int i);
+// Input checks read back after a prepare plan; sets m->status on rejection.
+void check_prepared(const int* flags_host, Member* m);
+// Apply gathered flags after plan P ran over ms; returns true when all are done.
+bool apply_flags(const int* flags_host, const std::vector<Member*>& ms, const Plan& P);
+// Add one run of P to the counters of the members still running.
+void account(const std::vector<Member*>& ms, const Plan& P);
+// After the last plan: final buffers of unfinished channels and the status.
+void finish_member(Member* m, int last_cur0);
+void fill_stats(const Member* m, inpaint_stats& st);
+
 // Device resources of a batch, cached across calls with the same workspaces,
 // options and tolerance.
 struct BatchCtx {

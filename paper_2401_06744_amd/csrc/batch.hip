@@ -220,6 +220,8 @@ void build_vcycle(Plan& P, const std::vector<Member*>& ms, int l0, const Opts& o
   }
 }
 
+}  // namespace
+
 // The coarse-to-fine initial guess (Section 4.2) of every member.
 void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
   if (o.schedule == INPAINT_SCHED_SINGLE) {
@@ -265,22 +267,7 @@ void add_gather(Plan& P, const std::vector<Member*>& ms, int* flags_dev) {
   P.end();
 }
 
-// Build a plan with `body` and record, per member, what one run of it adds to
-// the member's counters and which level-0 buffer holds the iterate afterwards.
-template <class Body>
-void build(Plan& P, const std::vector<Member*>& ms, Body&& body) {
-  std::vector<std::array<long long, 3>> before;
-  for (Member* m : ms) before.push_back({m->R->oras_iters, m->R->block_solves, m->R->finest_block_solves});
-  body();
-  P.delta.clear();
-  P.cur0.clear();
-  for (size_t i = 0; i < ms.size(); ++i) {
-    const Run& R = *ms[i]->R;
-    P.delta.push_back({R.oras_iters - before[i][0], R.block_solves - before[i][1],
-                       R.finest_block_solves - before[i][2]});
-    P.cur0.push_back(ms[i]->ws->lv[0].cur);
-  }
-}
+namespace {
 
 std::vector<int> level_state(const std::vector<Member*>& ms) {
   std::vector<int> s;
@@ -356,8 +343,8 @@ std::shared_ptr<BatchCtx> batch_ctx(int dev, const std::vector<Member*>& ms, con
   return c;
 }
 
-// Copy the plans' argument arrays into one device buffer owned by `*buf`
-// (grown as needed) and point each plan at its part.
+}  // namespace
+
 void upload(std::vector<Plan*> plans, unsigned char** buf, size_t* cap, hipStream_t s) {
   size_t need = 0;
   for (Plan* p : plans) need += round_up(p->host.size(), 256);
@@ -380,6 +367,8 @@ void upload(std::vector<Plan*> plans, unsigned char** buf, size_t* cap, hipStrea
   }
 }
 
+namespace {
+
 void capture(Plan& P, BatchCtx& c, int prec, int B) {
   HIPCHK(hipStreamBeginCapture(c.cap, hipStreamCaptureModeThreadLocal));
   const hipError_t e = issue(P, prec, B, c.cap);
@@ -398,14 +387,19 @@ void run_plan(const Plan& P, int prec, int B, hipStream_t s) {
     HIPCHK(issue(P, prec, B, s));
 }
 
-// Read the gathered flags of every member; returns true when all are done.
 bool poll_members(BatchCtx& c, const std::vector<Member*>& ms, const Plan& P, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)c.n * 64, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  return apply_flags(c.flags_host, ms, P);
+}
+
+}  // namespace
+
+bool apply_flags(const int* flags_host, const std::vector<Member*>& ms, const Plan& P) {
   bool all = true;
   for (size_t i = 0; i < ms.size(); ++i) {
     Member* m = ms[i];
-    const int* blk = c.flags_host + 16 * m->slot;
+    const int* blk = flags_host + 16 * m->slot;
     const double* rr = (const double*)blk;
     const int* act = blk + 8;
     const int* st = blk + 12;
@@ -435,20 +429,71 @@ void account(const std::vector<Member*>& ms, const Plan& P) {
   }
 }
 
-}  // namespace
+void finish_member(Member* m, int last_cur0) {
+  bool diverged = false;
+  for (int ch = 0; ch < m->C; ++ch) {
+    if (m->final_cur[ch] < 0) m->final_cur[ch] = last_cur0;
+    if (!std::isfinite(m->rel[ch])) diverged = true;
+  }
+  if (diverged) {
+    m->status = INPAINT_E_DIVERGED;
+    m->msg = "the residual became non-finite";
+  } else if (!m->done) {
+    m->status = INPAINT_NOT_CONVERGED;
+    m->msg = "cycle cap reached before the tolerance";
+  }
+}
+
+void fill_stats(const Member* m, inpaint_stats& st) {
+  std::memset(&st, 0, sizeof st);
+  st.status = m->status;
+  st.levels = m->ws ? m->ws->L : 0;
+  if (m->status == INPAINT_OK || m->status == INPAINT_NOT_CONVERGED ||
+      m->status == INPAINT_E_DIVERGED) {
+    double r = 0.0;
+    for (int ch = 0; ch < m->C; ++ch) r = std::max(r, m->rel[ch]);
+    st.rel_res = m->status == INPAINT_E_DIVERGED ? NAN : r;
+    st.cycles = m->cycles;
+    st.oras_iters = (int)(m->oras * m->C);
+    st.finest_block_solves = m->finest_blocks;
+  }
+}
+
+// Reads the flag block written by the prepare plan: input checks of f and the mask.
+void check_prepared(const int* flags_host, Member* m) {
+  const int st = flags_host[16 * m->slot + 12];
+  if (st & 1) {
+    m->status = INPAINT_E_INVALID;
+    m->msg = "f is not finite at a known pixel";
+  } else if (!(st & 2)) {
+    m->status = INPAINT_E_EMPTY_MASK;
+    m->msg = "mask has no known pixel: the system is singular";
+  }
+}
+
+void validate_problem(const inpaint_problem& p, int i) {
+  try {
+    check_dims(p.f, p.mask, p.W, p.H, p.channels);
+    if (!p.out) fail(INPAINT_E_INVALID, "NULL pointer argument");
+    const size_t nf = (size_t)p.W * p.H * p.channels * sizeof(float);
+    if (p.out != p.f && overlap(p.out, nf, p.f, nf)) fail(INPAINT_E_INVALID, "out partially overlaps f");
+    if (overlap(p.out, nf, p.mask, (size_t)p.W * p.H)) fail(INPAINT_E_INVALID, "out overlaps mask");
+  } catch (const Fail&) {
+    if (i >= 0) g_err = "problem " + std::to_string(i) + ": " + g_err;
+    throw;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // the batched solve
 // ---------------------------------------------------------------------------
 
-void init_member(Member& m, const inpaint_problem& p, int idx, const Opts& o, double tol,
+void init_member(Member& m, const inpaint_problem& p, Workspace* ws, const Opts& o, double tol,
                  hipStream_t s) {
-  m.idx = m.slot = idx;
   m.W = p.W;
   m.H = p.H;
   m.C = p.channels;
-  acquire(m.lease, m.W, m.H, m.C, o.B, o.o, o.B, o.prec);
-  m.ws = m.lease.ws;
+  m.ws = ws;
   m.R.reset(new Run{m.ws, o, s, m.C, tol});
   const bool fd = is_device_ptr(p.f), md = is_device_ptr(p.mask), od = is_device_ptr(p.out);
   if (!fd || !md || !od) ensure_staging(m.ws);
@@ -544,19 +589,7 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
   if (!(tol > 0.0 && tol < 1.0)) fail(INPAINT_E_INVALID, "tol must lie in (0, 1)");
   Opts o = resolve(opts);
   o.profile = 0;
-  for (int i = 0; i < n; ++i) {
-    const inpaint_problem& p = probs[i];
-    try {
-      check_dims(p.f, p.mask, p.W, p.H, p.channels);
-      if (!p.out) fail(INPAINT_E_INVALID, "NULL pointer argument");
-      const size_t nf = (size_t)p.W * p.H * p.channels * sizeof(float);
-      if (p.out != p.f && overlap(p.out, nf, p.f, nf)) fail(INPAINT_E_INVALID, "out partially overlaps f");
-      if (overlap(p.out, nf, p.mask, (size_t)p.W * p.H)) fail(INPAINT_E_INVALID, "out overlaps mask");
-    } catch (const Fail& e) {
-      g_err = "problem " + std::to_string(i) + ": " + g_err;
-      throw;
-    }
-  }
+  for (int i = 0; i < n; ++i) validate_problem(probs[i], i);
   {
     std::vector<std::pair<const char*, const char*>> spans;
     for (int i = 0; i < n; ++i) {
@@ -575,7 +608,10 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
   std::vector<Member*> all;
   for (int i = 0; i < n; ++i) {
     own.emplace_back(new Member());
-    init_member(*own.back(), probs[i], i, o, tol, s);
+    Member& m = *own.back();
+    m.idx = m.slot = i;
+    acquire(m.lease, probs[i].W, probs[i].H, probs[i].channels, o.B, o.o, o.B, o.prec);
+    init_member(m, probs[i], m.lease.ws, o, tol, s);
     all.push_back(own.back().get());
   }
   auto ctx = batch_ctx(dev, all, o, tol, n);
@@ -593,14 +629,7 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
   std::vector<Member*> live;
   std::string live_key;
   for (Member* m : all) {
-    const int st = c.flags_host[16 * m->slot + 12];
-    if (st & 1) {
-      m->status = INPAINT_E_INVALID;
-      m->msg = "f is not finite at a known pixel";
-    } else if (!(st & 2)) {
-      m->status = INPAINT_E_EMPTY_MASK;
-      m->msg = "mask has no known pixel: the system is singular";
-    }
+    check_prepared(c.flags_host, m);
     live_key.push_back(m->status == INPAINT_OK ? 1 : 0);
     if (m->status == INPAINT_OK) live.push_back(m);
   }
@@ -645,21 +674,7 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
       done = poll_members(c, live, P, s);
     }
     const Plan& last = cycles == 0 ? c.cascade : c.cycle[(cycles - 1) % c.ncycle];
-    for (size_t i = 0; i < live.size(); ++i) {
-      Member* m = live[i];
-      bool diverged = false;
-      for (int ch = 0; ch < m->C; ++ch) {
-        if (m->final_cur[ch] < 0) m->final_cur[ch] = last.cur0[i];
-        if (!std::isfinite(m->rel[ch])) diverged = true;
-      }
-      if (diverged) {
-        m->status = INPAINT_E_DIVERGED;
-        m->msg = "the residual became non-finite";
-      } else if (!m->done) {
-        m->status = INPAINT_NOT_CONVERGED;
-        m->msg = "cycle cap reached before the tolerance";
-      }
-    }
+    for (size_t i = 0; i < live.size(); ++i) finish_member(live[i], last.cur0[i]);
     Plan out;
     build_output(out, live);
     upload({&out}, &c.call_dev, &c.call_cap, s);
@@ -683,20 +698,8 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
       }
     }
     if (stats) {
-      inpaint_stats& st = stats[m->idx];
-      std::memset(&st, 0, sizeof st);
-      st.status = m->status;
-      st.levels = m->ws->L;
-      st.gpu_ms = ms;
-      if (m->status == INPAINT_OK || m->status == INPAINT_NOT_CONVERGED ||
-          m->status == INPAINT_E_DIVERGED) {
-        double r = 0.0;
-        for (int ch = 0; ch < m->C; ++ch) r = std::max(r, m->rel[ch]);
-        st.rel_res = m->status == INPAINT_E_DIVERGED ? NAN : r;
-        st.cycles = m->cycles;
-        st.oras_iters = (int)(m->oras * m->C);
-        st.finest_block_solves = m->finest_blocks;
-      }
+      fill_stats(m, stats[m->idx]);
+      stats[m->idx].gpu_ms = ms;
     }
   }
   g_err = msg;

@@ -79,6 +79,7 @@ struct Level {
 
 struct Key {
   int dev, W, H, C, B, o, coarsest, prec;
+  bool operator==(const Key& k) const { return !(*this < k) && !(k < *this); }
   bool operator<(const Key& k) const {
     return std::tie(dev, W, H, C, B, o, coarsest, prec) <
            std::tie(k.dev, k.W, k.H, k.C, k.B, k.o, k.coarsest, k.prec);
@@ -124,6 +125,12 @@ struct Lease {
   Lease& operator=(const Lease&) = delete;
   ~Lease();
 };
+
+// A workspace for key k: the grid hierarchy and all per-problem device state
+// in one allocation (alloc = false: sizes only, nothing allocated).
+std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc = true);
+// Device bytes of create_workspace(k).
+size_t workspace_bytes(const Key& k);
 
 // Lease a free workspace for (device, sizes, channels, block, overlap,
 // coarsest side, precision), creating it on first use.  Workspaces are kept

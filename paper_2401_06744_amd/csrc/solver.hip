@@ -78,9 +78,7 @@ std::vector<std::pair<int, int>> level_sizes(int W, int H, int coarsest) {
   return s;
 }
 
-namespace {
-
-std::unique_ptr<Workspace> create_workspace(const Key& k) {
+std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
   auto ws = std::make_unique<Workspace>();
   ws->key = k;
   const auto sizes = level_sizes(k.W, k.H, k.coarsest);
@@ -129,6 +127,7 @@ std::unique_ptr<Workspace> create_workspace(const Key& k) {
   const size_t o_flags = take(64);
   const size_t o_cg = take((size_t)kMaxLevels * C * 3 * sizeof(unsigned long long));
   ws->bytes = off;
+  if (!alloc) return ws;
   HIPCHK(hipMalloc(&ws->base, off));
   char* base = (char*)ws->base;
   for (int l = 0; l < ws->L; ++l) {
@@ -159,6 +158,10 @@ std::unique_ptr<Workspace> create_workspace(const Key& k) {
   HIPCHK(hipEventCreate(&ws->ev1));
   return ws;
 }
+
+size_t workspace_bytes(const Key& k) { return create_workspace(k, false)->bytes; }
+
+namespace {
 
 std::mutex g_mu;
 std::map<Key, std::vector<std::unique_ptr<Workspace>>> g_cache;

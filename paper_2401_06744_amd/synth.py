@@ -107,50 +107,42 @@ def bernoulli_mask(W: int, H: int, density: float, seed: int) -> np.ndarray:
     return m
 
 
-def _poisson_disk(rng: np.random.Generator, W: int, H: int, radius: float, k: int = 30) -> np.ndarray:
-    """Bridson's Poisson-disk sampling on a background grid; returns an (n, 2) array."""
+def _poisson_disk(rng: np.random.Generator, W: int, H: int, radius: float, rounds: int = 24) -> np.ndarray:
+    """Poisson-disk sampling by phased dart throwing on a background grid of
+    cells of side radius/sqrt(2) (each holds at most one point); returns an
+    (n, 2) array of (x, y).
+
+    Every round visits the 9 cell phases (x mod 3, y mod 3) in random order and
+    throws one dart into each empty cell of the phase; a dart is kept when no
+    point of the 5x5 cell neighbourhood lies closer than the radius.  Cells of
+    one phase are at least two cells (1.41 radii) apart, so their darts never
+    conflict and a whole phase is processed at once."""
     cell = radius / np.sqrt(2.0)
     gw, gh = int(np.ceil(W / cell)), int(np.ceil(H / cell))
-    grid = -np.ones((gh, gw), dtype=np.int64)
-    pts = []
-    active = []
-    p0 = np.array([rng.uniform(0, W), rng.uniform(0, H)])
-    pts.append(p0)
-    grid[int(p0[1] / cell), int(p0[0] / cell)] = 0
-    active.append(0)
+    px = np.full((gh + 4, gw + 4), np.nan)
+    py = np.full((gh + 4, gw + 4), np.nan)
+    gy, gx = np.mgrid[0:gh, 0:gw]
+    phase_of = (gy % 3) * 3 + (gx % 3)
     r2 = radius * radius
-    while active:
-        ai = rng.integers(len(active))
-        base = pts[active[ai]]
-        ang = rng.uniform(0, 2 * np.pi, k)
-        rad = radius * np.sqrt(rng.uniform(1.0, 4.0, k))
-        cand = base[None, :] + np.stack([rad * np.cos(ang), rad * np.sin(ang)], axis=1)
-        placed = False
-        for c in cand:
-            if not (0 <= c[0] < W and 0 <= c[1] < H):
+    for _ in range(rounds):
+        for phase in rng.permutation(9):
+            sel = (phase_of == phase) & np.isnan(px[2:-2, 2:-2])
+            cy, cx = gy[sel], gx[sel]
+            if cy.size == 0:
                 continue
-            gx, gy = int(c[0] / cell), int(c[1] / cell)
-            ok = True
-            for yy in range(max(0, gy - 2), min(gh, gy + 3)):
-                for xx in range(max(0, gx - 2), min(gw, gx + 3)):
-                    j = grid[yy, xx]
-                    if j >= 0:
-                        d = pts[j] - c
-                        if d[0] * d[0] + d[1] * d[1] < r2:
-                            ok = False
-                            break
-                if not ok:
-                    break
-            if ok:
-                pts.append(c)
-                grid[gy, gx] = len(pts) - 1
-                active.append(len(pts) - 1)
-                placed = True
-                break
-        if not placed:
-            active[ai] = active[-1]
-            active.pop()
-    return np.array(pts)
+            x = (cx + rng.random(cx.size)) * cell
+            y = (cy + rng.random(cy.size)) * cell
+            ok = (x < W) & (y < H)
+            for dy in range(-2, 3):
+                for dx in range(-2, 3):
+                    qx = px[cy + 2 + dy, cx + 2 + dx]
+                    qy = py[cy + 2 + dy, cx + 2 + dx]
+                    ok &= ~((qx - x) ** 2 + (qy - y) ** 2 < r2)
+            px[cy[ok] + 2, cx[ok] + 2] = x[ok]
+            py[cy[ok] + 2, cx[ok] + 2] = y[ok]
+    inner_x, inner_y = px[2:-2, 2:-2], py[2:-2, 2:-2]
+    keep = ~np.isnan(inner_x)
+    return np.stack([inner_x[keep], inner_y[keep]], axis=1)
 
 
 def blue_noise_mask(W: int, H: int, density: float, seed: int, iters: int = 12) -> tuple[np.ndarray, float]:

@@ -53,3 +53,4 @@ def test_opts_struct_layout_matches_header():
     assert ctypes.sizeof(binding.InpaintStats) == (8 + 3 * 4 + 4 + 8 + 4 + 4 + 8 + 8 + 8 + 9 * 4 + 9 * 4
                                                    + 4 + 4 + 3 * 8)
     assert ctypes.sizeof(binding.InpaintProblem) == 8 + 8 + 3 * 4 + 4 + 8
+    assert ctypes.sizeof(binding.InpaintServerCfg) == 4 + 4 + 8 + 15 * 4 + 4

@@ -1,0 +1,130 @@
+"""Serving through the C ABI: requests of mixed sizes submitted while others
+run are each solved exactly as alone (bit-identical to inpaint_solve_ex with
+the server's options), under HBM-footprint admission."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_06744_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+
+
+def _reqs(n, seed=0, sizes=((160, 90), (320, 180), (77, 53), (33, 200))):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        W, H = sizes[k % len(sizes)]
+        C = 3 if k % 3 else 1
+        d = float(rng.uniform(0.005, 0.10))
+        out.append((synth.frame_image(W, H, C, seed=seed + 7 * k + 1),
+                    synth.bernoulli_mask(W, H, d, seed=seed + 7 * k + 2)))
+    return out
+
+
+@pytest.mark.parametrize("prec", [binding.PREC_FP32, binding.PREC_FP16])
+def test_served_results_equal_solo_results(prec):
+    opts = binding.make_opts(precision=prec)
+    reqs = _reqs(12, seed=1)
+    srv = binding.inpaint_server_create(max_batch=5, opts=opts)
+    try:
+        tickets = []
+        for k, (f, m) in enumerate(reqs):
+            tickets.append(binding.inpaint_server_submit(srv, f, m, tol=TOL))
+            if k % 4 == 3:
+                time.sleep(0.002)  # let some requests start before the next ones arrive
+        results = [binding.inpaint_server_wait(srv, t) for t in tickets]
+    finally:
+        binding.inpaint_server_destroy(srv)
+    for (f, m), (out, st, stats) in zip(reqs, results):
+        assert st == binding.OK and stats["status"] == binding.OK
+        solo, _, _ = binding.inpaint_solve_ex(f, m, TOL, opts=opts)
+        assert np.array_equal(out, solo)
+        assert 0 <= stats["t_submit_ms"] <= stats["t_start_ms"] <= stats["t_done_ms"]
+        assert stats["rel_res"] <= TOL
+
+
+def test_alone_equals_in_the_mix_and_oracle():
+    probe = _reqs(1, seed=50, sizes=((257, 129),))[0]
+    srv = binding.inpaint_server_create()
+    try:
+        alone, st, _ = binding.inpaint_server_wait(srv, binding.inpaint_server_submit(srv, *probe))
+        assert st == binding.OK
+        others = _reqs(9, seed=60)
+        ts = [binding.inpaint_server_submit(srv, f, m) for f, m in others[:5]]
+        tp = binding.inpaint_server_submit(srv, *probe)
+        ts += [binding.inpaint_server_submit(srv, f, m) for f, m in others[5:]]
+        mixed, st2, _ = binding.inpaint_server_wait(srv, tp)
+        for t in ts:
+            assert binding.inpaint_server_wait(srv, t)[1] == binding.OK
+    finally:
+        binding.inpaint_server_destroy(srv)
+    assert st2 == binding.OK
+    assert np.array_equal(alone, mixed)
+    f, m = probe
+    ref = oracle.solve_pcg(f.astype(np.float64), m)
+    assert np.abs(mixed.astype(np.float64) - ref).max() <= 0.5
+    assert np.array_equal(mixed[:, m != 0], f[:, m != 0])
+
+
+def test_tiny_budget_queues_requests_and_device_buffers():
+    import torch
+    reqs = _reqs(6, seed=80)
+    dev = [(torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()) for f, m in reqs]
+    # a budget that holds the largest single hierarchy only: requests run one
+    # or two at a time and idle hierarchies of other sizes are freed
+    srv = binding.inpaint_server_create(hbm_budget=12 << 20)
+    try:
+        ts = [binding.inpaint_server_submit(srv, f, m) for f, m in dev]
+        res = [binding.inpaint_server_wait(srv, t) for t in ts]
+        torch.cuda.synchronize()
+    finally:
+        binding.inpaint_server_destroy(srv)
+    for (f, m), (out, st, _) in zip(reqs, res):
+        assert st == binding.OK
+        solo, _, _ = binding.inpaint_solve_ex(f, m, TOL)
+        assert np.array_equal(out.cpu().numpy(), solo)
+
+
+def test_server_errors_and_rejections():
+    f, m = _reqs(1, seed=90)[0]
+    srv = binding.inpaint_server_create(hbm_budget=1 << 20)
+    try:
+        big = synth.frame_image(1024, 1024, 3, seed=1)
+        with pytest.raises(binding.InpaintError) as e:
+            binding.inpaint_server_submit(srv, big, np.ones((1024, 1024), np.uint8))
+        assert e.value.code == binding.E_NOMEM
+        with pytest.raises(binding.InpaintError) as e:
+            binding.inpaint_server_submit(srv, f, m, tol=2.0)
+        assert e.value.code == binding.E_INVALID
+        t_bad = binding.inpaint_server_submit(srv, f, np.zeros_like(m))
+        t_ok = binding.inpaint_server_submit(srv, f, m)
+        out, st, stats = binding.inpaint_server_wait(srv, t_bad, raise_on_error=False)
+        assert st == binding.E_EMPTY_MASK and stats["status"] == binding.E_EMPTY_MASK
+        while True:
+            r = binding.inpaint_server_poll(srv, t_ok)
+            if r is not None:
+                break
+            time.sleep(0.001)
+        assert r[1] == binding.OK
+        with pytest.raises(binding.InpaintError) as e:
+            binding.inpaint_server_poll(srv, t_ok)
+        assert e.value.code == binding.E_INVALID
+    finally:
+        binding.inpaint_server_destroy(srv)
+
+
+def test_destroy_finishes_submitted_requests():
+    reqs = _reqs(4, seed=100)
+    outs = [np.zeros_like(f) for f, _ in reqs]
+    srv = binding.inpaint_server_create()
+    for (f, m), o in zip(reqs, outs):
+        binding.inpaint_server_submit(srv, f, m, out=o)
+    binding.inpaint_server_destroy(srv)
+    for (f, m), o in zip(reqs, outs):
+        solo, _, _ = binding.inpaint_solve_ex(f, m, TOL)
+        assert np.array_equal(o, solo)
