@@ -209,6 +209,24 @@ typedef struct inpaint_problem {
 int inpaint_solve_batched(const inpaint_problem* problems, int n, double tol,
                           const inpaint_opts* opts, void* stream, inpaint_stats* stats);
 
+/*
+ * Autotuner of the batched solve: picks the ORAS block side (16, 32), overlap
+ * (2, 4, 6, 8, at most half the block), Robin weight gamma (0.3, 0.5, 0.7),
+ * local CG tolerance tau (0.002, 0.005, 0.01) and cycle schedule (RFMG, FMG)
+ * for these problems by timing batched solves of them: one coordinate-descent
+ * sweep from `base` (NULL = defaults), each candidate timed as the median of
+ * three solves after a warm-up; a candidate counts only if every problem
+ * converges.  The problems' outputs are overwritten.  The choice is cached in
+ * memory per workload signature (sorted sizes and channel counts, precision,
+ * tolerance, smoothing counts) and, when the environment variable
+ * INPAINT_AUTOTUNE_CACHE names a file, appended to and read from that file.
+ *   best     receives base with the five chosen fields set
+ *   best_ms  NULL or receives the chosen configuration's time per batch (ms)
+ */
+int inpaint_autotune(const inpaint_problem* problems, int n, double tol,
+                     const inpaint_opts* base, void* stream, inpaint_opts* best,
+                     double* best_ms);
+
 /* ---------------------------------------------------------------------------
  * Serving: a request loop with continuous batching on one device.
  *

@@ -31,7 +31,7 @@ EXPORTED = [
     "inpaint_version", "inpaint_hierarchy_size", "inpaint_debug_pyramid",
     "inpaint_debug_oras_step", "inpaint_debug_restrict", "inpaint_debug_prolong",
     "inpaint_solve_batched", "inpaint_server_create", "inpaint_server_submit",
-    "inpaint_server_poll", "inpaint_server_wait", "inpaint_server_destroy",
+    "inpaint_server_poll", "inpaint_server_wait", "inpaint_server_destroy", "inpaint_autotune",
 ]
 
 
@@ -107,6 +107,8 @@ def lib() -> ct.CDLL:
         L.inpaint_debug_prolong.argtypes = [vp, i, i, vp, vp, vp, i, vp]
         L.inpaint_solve_batched.argtypes = [ct.POINTER(InpaintProblem), i, d,
                                             ct.POINTER(InpaintOpts), vp, ct.POINTER(InpaintStats)]
+        L.inpaint_autotune.argtypes = [ct.POINTER(InpaintProblem), i, d, ct.POINTER(InpaintOpts),
+                                       vp, ct.POINTER(InpaintOpts), ct.POINTER(ct.c_double)]
         L.inpaint_server_create.argtypes = [ct.POINTER(InpaintServerCfg), ct.POINTER(vp)]
         L.inpaint_server_submit.argtypes = [vp, ct.POINTER(InpaintProblem), d,
                                             ct.POINTER(ct.c_uint64)]
@@ -234,6 +236,16 @@ def inpaint_solve_batched(problems, tol: float = 1e-6, opts: InpaintOpts | None 
     if raise_on_error:
         _check(st)
     return outs, st, [stats[k].as_dict() for k in range(len(problems))]
+
+
+def inpaint_autotune(problems, tol: float = 1e-6, base: InpaintOpts | None = None, stream=None):
+    """Tune the batched solve's options on these problems; returns (opts, ms per batch)."""
+    arr, _ = _problems(problems)
+    best = InpaintOpts()
+    ms = ct.c_double(0.0)
+    _check(lib().inpaint_autotune(arr, len(problems), tol, ct.byref(base) if base is not None else None,
+                                  _stream_handle(stream), ct.byref(best), ct.byref(ms)))
+    return best, ms.value
 
 
 class ServerHandle:

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libinpaint.so")
-SOURCES = ["kernels.hip", "solver.hip", "batch.hip", "server.hip"]
+SOURCES = ["kernels.hip", "solver.hip", "batch.hip", "server.hip", "autotune.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -170,7 +170,9 @@ __device__ __forceinline__ void output_body(const OutputArgs& a, unsigned lin) {
   const int x = (int)(q % gxn) * 64 + (threadIdx.x & 63);
   const int y = (int)(q / gxn) * 4 + (threadIdx.x >> 6);
   if (x >= lv.W || y >= lv.H) return;
-  const float* u = a.u[ch];
+  // select without indexing the argument array dynamically (that would place
+  // the arguments in scratch memory)
+  const float* u = ch == 0 ? a.u[0] : ch == 1 ? a.u[1] : ch == 2 ? a.u[2] : a.u[3];
   const size_t o = (size_t)y * lv.P + x;
   const size_t src = (size_t)ch * lv.plane + o;
   a.out[(size_t)ch * a.Pout * lv.H + (size_t)y * a.Pout + x] = a.c[o] ? a.b[src] : u[src];
@@ -1001,8 +1003,11 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs& a, unsigned lin) {
 __global__ void __launch_bounds__(256) k_output(OutputArgs a) { output_body(a, xcd_remap(blockIdx.x, gridDim.x)); }
 __global__ void __launch_bounds__(256) k_output_b(const OutputArgs* __restrict__ args,
                                                   const unsigned* __restrict__ start, int n) {
-  INPAINT_BATCH_LOOKUP(OutputArgs)
-  output_body(a, lin);
+  // the arguments are read in place: a private copy of this struct (with its
+  // pointer array) would live in scratch memory
+  const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
+  const int p = find_problem(start, n, g);
+  output_body(args[p], g - start[p]);
 }
 
 __global__ void __launch_bounds__(256) k_mask_down(MaskArgs a) { mask_body(a, xcd_remap(blockIdx.x, gridDim.x)); }

@@ -2,6 +2,8 @@
 the solve of that problem alone (same options), and meets the parity bar
 against the oracle (relative residual <= 1e-6, known pixels bit-exact, max abs
 error <= 0.5 grey levels)."""
+import time
+
 import numpy as np
 import pytest
 
@@ -163,3 +165,25 @@ def test_batched_64_uneven_problems():
         assert np.array_equal(solo.cpu().numpy(), host[k]), k
     print(f"64-problem batch: {stats[0]['gpu_ms']:.2f} ms, cycles "
           f"{sorted(set(s['cycles'] for s in stats))}", flush=True)
+
+
+def test_autotune_picks_a_converging_configuration_and_caches_it(tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("INPAINT_AUTOTUNE_CACHE", str(cache))
+    probs = _mix(seed=500)[:5]
+    t0 = time.perf_counter()
+    best, ms = binding.inpaint_autotune(probs, TOL)
+    first = time.perf_counter() - t0
+    assert best.block in (16, 32) and 2 <= best.overlap <= best.block // 2
+    assert best.schedule in (binding.SCHED_RFMG, binding.SCHED_FMG)
+    assert ms > 0
+    t0 = time.perf_counter()
+    again, ms2 = binding.inpaint_autotune(probs, TOL)
+    assert time.perf_counter() - t0 < first
+    assert (again.block, again.overlap, again.schedule, ms2) == (best.block, best.overlap, best.schedule, ms)
+    assert cache.exists() and cache.read_text().count("\n") >= 1
+    outs, st, _ = binding.inpaint_solve_batched(probs, TOL, opts=best)
+    assert st == binding.OK
+    for (f, m), u in zip(probs, outs):
+        rr = oracle.rel_res(u.astype(np.float64), f.astype(np.float64), m)
+        assert np.all(rr <= TOL)
