@@ -805,7 +805,7 @@ struct BlockCG {
   int lane, lx, g;
   float hasL, hasR;  // the lane to the left / right belongs to the same row group
   float dg[R];       // diagonal of A_i, 0 at known and outside pixels
-  float nm[R];       // 1 at unknown pixels of the block, else 0
+  bool nm[R];        // unknown pixel of the block (held as lane masks in scalar registers)
 
   __device__ void apply(const float (&x)[R], float (&q)[R]) const {
     float fa = __shfl(x[R - 1], (lane - B) & 63);
@@ -818,7 +818,7 @@ struct BlockCG {
       const float r = lane_from_right(x[k]) * hasR;
       const float up = k > 0 ? x[k - 1] : fa;
       const float dn = k < R - 1 ? x[k + 1] : fb;
-      q[k] = dg[k] * x[k] - nm[k] * ((l + r) + (up + dn));
+      q[k] = nm[k] ? dg[k] * x[k] - ((l + r) + (up + dn)) : 0.0f;
     }
   }
 
@@ -842,7 +842,7 @@ struct BlockCG {
       const bool unknown = ok && c[(size_t)(y0 + ly) * P + x0 + lx] == 0;
       const float du = ly > 0 ? 1.0f : (y0 > 0 ? gamma : 0.0f);
       const float dd = ly < bh - 1 ? 1.0f : (y0 + bh < H ? gamma : 0.0f);
-      nm[k] = unknown ? 1.0f : 0.0f;
+      nm[k] = unknown;
       dg[k] = unknown ? (dl + dr) + (du + dd) : 0.0f;
     }
   }
@@ -854,7 +854,7 @@ struct BlockCG {
     float rr = 0.0f;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      rho[k] *= nm[k];
+      rho[k] = nm[k] ? rho[k] : 0.0f;
       v[k] = 0.0f;
       p[k] = rho[k];
       rr += rho[k] * rho[k];
@@ -973,7 +973,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs& a, unsigned lin) {
       const double upv = k > 0 ? u[k - 1] : fa;
       const double dn = k < R - 1 ? u[k + 1] : fb;
       const double res = (double)bb[k] - ((double)cg.dg[k] * (double)u[k] - ((l + r) + (upv + dn)));
-      rho[k] = (float)(res * (double)cg.nm[k]);
+      rho[k] = cg.nm[k] ? (float)res : 0.0f;
     }
   }
   float rr0 = 0.0f;
