@@ -26,9 +26,11 @@ enum StepKind : int {
 };
 
 // One batched launch: n argument structs and n + 1 work offsets, stored at
-// byte offsets `args` and `start` of the plan's buffer.
+// byte offsets `args` and `start` of the plan's buffer.  `f32` selects the
+// kernel variant whose level fields are float32 (the finest grid's solution
+// fields); `level` is the grid level the launch works on (-1: none).
 struct Step {
-  int kind, mode, level0, n;
+  int kind, mode, f32, level, n;
   unsigned total;
   size_t args, start;
 };
@@ -46,14 +48,30 @@ struct Plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 
-  void begin(int kind, int mode = 0, int level0 = 0);
+  void begin(int kind, int mode = 0, int level = -1);
+  // Append one problem's arguments; f32 (if >= 0) is the field type of its
+  // launch variant, which every problem of a launch must share.
   template <class T>
-  void add(const T& a, unsigned work) {
+  void add(const T& a, unsigned work, int f32 = -1) {
+    if (f32 >= 0) {
+      if (open.f32 < 0)
+        open.f32 = f32;
+      else if (open.f32 != f32)
+        fail(INPAINT_E_DEVICE, "problems of one batched launch need different kernel variants");
+    }
     const size_t at = pend.size();
     pend.resize(at + sizeof(T));
     std::memcpy(pend.data() + at, &a, sizeof(T));
     open.n += 1;
     pstart.push_back(pstart.back() + work);
+  }
+  // A pass launch: the problems must also share the pass mode.
+  void add_pass(const PassArgs& a, unsigned work) {
+    if (open.mode < 0)
+      open.mode = a.mode;
+    else if (open.mode != a.mode)
+      fail(INPAINT_E_DEVICE, "problems of one batched launch need different pass modes");
+    add(a, work, a.level0);
   }
   void end();
   void clear();
@@ -69,8 +87,21 @@ struct Plan {
   std::vector<unsigned> pstart;
 };
 
+// Per-launch timing of the finest-grid launches (single solves with
+// opts.profile): HIP events recorded around each such launch on its stream.
+struct Prof {
+  std::vector<hipEvent_t>* pool = nullptr;  // reused events (owned by the workspace)
+  size_t next = 0;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  hipEvent_t event();
+};
+
 // Enqueue every launch of a plan (plan.dev must be set).
-hipError_t issue(const Plan& P, int prec, int B, hipStream_t s);
+hipError_t issue(const Plan& P, int prec, int B, hipStream_t s, Prof* prof = nullptr);
 
 // One problem of a batch.
 struct Member {
@@ -145,6 +176,14 @@ void account(const std::vector<Member*>& ms, const Plan& P);
 // After the last plan: final buffers of unfinished channels and the status.
 void finish_member(Member* m, int last_cur0);
 void fill_stats(const Member* m, inpaint_stats& st);
+
+// Solve the members together (prepare, cascade, V-cycles, output), on the
+// stream s, and return after every result is in place; statuses, iteration
+// state and statistics are left in the members.  With prof (single solves
+// with opts.profile) every finest-grid launch is timed and nothing is replayed
+// from a graph.  Returns the device time in ms.
+float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipStream_t s,
+                Prof* prof);
 
 // Device resources of a batch, cached across calls with the same workspaces,
 // options and tolerance.

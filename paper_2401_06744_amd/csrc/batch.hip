@@ -55,14 +55,16 @@ __global__ void __launch_bounds__(64) k_gather(const GatherArgs* __restrict__ ar
 // plans
 // ---------------------------------------------------------------------------
 
-void Plan::begin(int kind, int mode, int level0) {
-  open = Step{kind, mode, level0, 0, 0, 0, 0};
+void Plan::begin(int kind, int mode, int level) {
+  open = Step{kind, mode, -1, level, 0, 0, 0, 0};
   pend.clear();
   pstart.assign(1, 0u);
 }
 
 void Plan::end() {
   if (open.n == 0) return;
+  if (open.f32 < 0) open.f32 = 0;
+  if (open.mode < 0) open.mode = 0;
   open.total = pstart.back();
   open.args = append(pend.data(), pend.size());
   open.start = append(pstart.data(), pstart.size() * sizeof(unsigned));
@@ -91,10 +93,64 @@ void Plan::clear() {
 
 Plan::~Plan() { clear(); }
 
-hipError_t issue(const Plan& P, int prec, int B, hipStream_t s) {
+hipEvent_t Prof::event() {
+  if (next == pool->size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    pool->push_back(e);
+  }
+  return (*pool)[next++];
+}
+
+namespace {
+
+// inpaint_kernel class of a finest-grid launch, -1 for launches not timed
+int kernel_class(const Step& st) {
+  if (st.level != 0) return -1;
+  switch (st.kind) {
+    case S_STAGE: return INPAINT_K_STAGE;
+    case S_MASK:
+    case S_RHS: return INPAINT_K_PYRAMID;
+    case S_BLOCK: return INPAINT_K_BLOCK_SOLVE;
+    case S_RESTRICT: return INPAINT_K_RESTRICT;
+    case S_COARSE: return INPAINT_K_COARSE;
+    case S_OUTPUT: return INPAINT_K_OUTPUT;
+    case S_PASS:
+      return st.mode == PASS_UPD ? INPAINT_K_UPDATE
+             : st.mode == PASS_RES ? INPAINT_K_RESIDUAL
+                                   : INPAINT_K_PROLONG;
+    default: return -1;
+  }
+}
+
+hipError_t issue_step(const Step& st, const unsigned char* dev, int prec, int B, hipStream_t s);
+
+}  // namespace
+
+hipError_t issue(const Plan& P, int prec, int B, hipStream_t s, Prof* prof) {
   for (const Step& st : P.steps) {
-    const void* a = P.dev + st.args;
-    const unsigned* start = (const unsigned*)(P.dev + st.start);
+    const int cls = prof ? kernel_class(st) : -1;
+    if (cls < 0) {
+      const hipError_t e = issue_step(st, P.dev, prec, B, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    hipEvent_t a = prof->event(), b = prof->event();
+    hipError_t e = hipEventRecord(a, s);
+    if (e == hipSuccess) e = issue_step(st, P.dev, prec, B, s);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e != hipSuccess) return e;
+    prof->recs.push_back({cls, a, b});
+  }
+  return hipSuccess;
+}
+
+namespace {
+
+hipError_t issue_step(const Step& st, const unsigned char* dev, int prec, int B, hipStream_t s) {
+  {
+    const void* a = dev + st.args;
+    const unsigned* start = (const unsigned*)(dev + st.start);
     hipError_t e = hipSuccess;
     switch (st.kind) {
       case S_RESET:
@@ -108,27 +164,28 @@ hipError_t issue(const Plan& P, int prec, int B, hipStream_t s) {
       case S_STAGE: e = launch_stage_b((const StageArgs*)a, start, st.n, st.total, s); break;
       case S_MASK: e = launch_mask_b((const MaskArgs*)a, start, st.n, st.total, s); break;
       case S_RHS:
-        e = launch_rhs_b((const RhsArgs*)a, start, st.n, st.total, prec, st.level0, s);
+        e = launch_rhs_b((const RhsArgs*)a, start, st.n, st.total, prec, st.f32, s);
         break;
       case S_PASS:
-        e = launch_pass_b(st.mode, (const PassArgs*)a, start, st.n, st.total, prec, st.level0, s);
+        e = launch_pass_b(st.mode, (const PassArgs*)a, start, st.n, st.total, prec, st.f32, s);
         break;
       case S_RESTRICT:
-        e = launch_restrict_b((const RestrictArgs*)a, start, st.n, st.total, prec, st.level0, s);
+        e = launch_restrict_b((const RestrictArgs*)a, start, st.n, st.total, prec, st.f32, s);
         break;
       case S_BLOCK:
-        e = launch_block_b((const BlockArgs*)a, start, st.n, st.total, prec, st.level0, B, s);
+        e = launch_block_b((const BlockArgs*)a, start, st.n, st.total, prec, st.f32, B, s);
         break;
       case S_COARSE:
-        e = launch_coarse_b((const CoarseArgs*)a, start, st.n, st.total, prec, st.level0, B, s);
+        e = launch_coarse_b((const CoarseArgs*)a, start, st.n, st.total, prec, st.f32, B, s);
         break;
       case S_OUTPUT: e = launch_output_b((const OutputArgs*)a, start, st.n, st.total, s); break;
       default: e = hipErrorInvalidValue;
     }
-    if (e != hipSuccess) return e;
+    return e;
   }
-  return hipSuccess;
 }
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // plan builders: each walks the members in lockstep and calls their Run's
@@ -151,27 +208,56 @@ int max_coarsest(const std::vector<Member*>& ms) {
   return v;
 }
 
-// One ORAS iteration on level l of every member in ms.
-void step_oras(Plan& P, const std::vector<Member*>& ms, int l, bool check, bool rest) {
-  P.begin(S_BLOCK, 0, l == 0);
+bool corr0(const Member* m) { return m->R->corr0(); }
+
+void step_block(Plan& P, const std::vector<Member*>& ms, int l) {
+  P.begin(S_BLOCK, 0, l);
   for (Member* m : ms) {
     const BlockArgs a = m->R->make_block(l);
-    P.add(a, work_block(a, m->C));
-  }
-  P.end();
-  P.begin(S_PASS, PASS_UPD, l == 0);
-  for (Member* m : ms) {
-    const PassArgs a = m->R->make_update(l, check, rest);
-    P.add(a, work_pass(a, m->C));
+    P.add(a, work_block(a, m->C), a.level0);
   }
   P.end();
 }
 
+// The precision form's last update of a cycle on the finest grid (see
+// Run::make_final).
+void step_final(Plan& P, const std::vector<Member*>& ms, bool blocks) {
+  P.begin(S_PASS, -1, 0);
+  for (Member* m : ms) {
+    const PassArgs a = m->R->make_final(true, blocks);
+    P.add_pass(a, work_pass(a, m->C));
+  }
+  P.end();
+}
+
+// One ORAS iteration on level l of every member in ms.
+void step_oras(Plan& P, const std::vector<Member*>& ms, int l, bool check, bool rest) {
+  step_block(P, ms, l);
+  P.begin(S_PASS, -1, l);
+  for (Member* m : ms) {
+    const PassArgs a = m->R->make_update(l, check, rest);
+    P.add_pass(a, work_pass(a, m->C));
+  }
+  P.end();
+}
+
+// One ORAS iteration on the finest grid ending in the convergence test: in
+// the precision form its update is the final update of the correction.
+void step_oras_checked(Plan& P, const std::vector<Member*>& ms) {
+  const auto corr = subset(ms, corr0);
+  const auto plain = subset(ms, [](Member* m) { return !corr0(m); });
+  if (!plain.empty()) step_oras(P, plain, 0, true, false);
+  if (!corr.empty()) {
+    step_block(P, corr, 0);
+    step_final(P, corr, true);
+  }
+}
+
 void step_residual(Plan& P, const std::vector<Member*>& ms) {
-  P.begin(S_PASS, PASS_RES, 1);
+  P.begin(S_PASS, -1, 0);
   for (Member* m : ms) {
     const PassArgs a = m->R->make_residual(0, true);
-    P.add(a, work_pass(a, m->C));
+    P.add_pass(a, work_pass(a, m->C));
   }
   P.end();
 }
@@ -185,38 +271,52 @@ void build_vcycle(Plan& P, const std::vector<Member*>& ms, int l0, const Opts& o
     const auto part = subset(ms, [&](Member* m) { return l < m->Lc(); });
     for (int i = 0; i < o.pre; ++i) step_oras(P, part, l, false, i == o.pre - 1);
     if (o.pre == 0) {
-      P.begin(S_RESTRICT, 0, l == 0);
+      P.begin(S_RESTRICT, 0, l);
       for (Member* m : part) {
         const RestrictArgs a = m->R->make_restrict(l);
-        P.add(a, work_restrict(a, m->C));
+        P.add(a, work_restrict(a, m->C), a.level0);
       }
       P.end();
     }
   }
-  P.begin(S_COARSE, 0, 0);
+  P.begin(S_COARSE, 0, maxLc);
   for (Member* m : ms)
     if (m->Lc() > 0) {
       const CoarseArgs a = m->R->make_coarse(m->Lc(), true);
-      P.add(a, work_coarse(a, m->C));
+      P.add(a, work_coarse(a, m->C), a.level0);
     }
   P.end();
   const auto flat = subset(ms, [](Member* m) { return m->Lc() == 0; });
-  P.begin(S_COARSE, 0, 1);
+  P.begin(S_COARSE, 0, 0);
   for (Member* m : flat) {
     const CoarseArgs a = m->R->make_coarse(0, false);
-    P.add(a, work_coarse(a, m->C));
+    P.add(a, work_coarse(a, m->C), a.level0);
   }
   P.end();
   step_residual(P, flat);
   for (int l = maxLc - 1; l >= l0; --l) {
     const auto part = subset(ms, [&](Member* m) { return l < m->Lc(); });
-    P.begin(S_PASS, PASS_PCORR, l == 0);
-    for (Member* m : part) {
+    const auto corr = subset(part, [&](Member* m) { return l == 0 && corr0(m); });
+    const auto plain = subset(part, [&](Member* m) { return !(l == 0 && corr0(m)); });
+    P.begin(S_PASS, -1, l);
+    for (Member* m : plain) {
       const PassArgs a = m->R->make_prolong(l, PASS_PCORR, l == 0 && o.post == 0);
-      P.add(a, work_pass(a, m->C));
+      P.add_pass(a, work_pass(a, m->C));
     }
     P.end();
-    for (int i = 0; i < o.post; ++i) step_oras(P, part, l, l == 0 && i == o.post - 1, false);
+    for (int i = 0; i < o.post; ++i) step_oras(P, plain, l, l == 0 && i == o.post - 1, false);
+    if (corr.empty()) continue;
+    // precision form: the correction e of the float32 iterate gets the coarse
+    // correction and the post-smoothing; the last update adds e to u and tests
+    P.begin(S_PASS, -1, 0);
+    for (Member* m : corr) {
+      const PassArgs a = m->R->make_prolong(0, PASS_PCORR, false);
+      P.add_pass(a, work_pass(a, m->C));
+    }
+    P.end();
+    for (int i = 0; i + 1 < o.post; ++i) step_oras(P, corr, 0, false, false);
+    if (o.post > 0) step_block(P, corr, 0);
+    step_final(P, corr, o.post > 0);
   }
 }
 
@@ -230,20 +330,20 @@ void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
   }
   step_residual(P, subset(ms, [](Member* m) { return m->Lc() == 0; }));
   const auto deep = subset(ms, [](Member* m) { return m->Lc() > 0; });
-  P.begin(S_COARSE, 0, 0);
+  P.begin(S_COARSE, 0, max_coarsest(deep));
   for (Member* m : deep) {
     m->R->top = m->Lc();
     const CoarseArgs a = m->R->make_coarse(m->Lc(), true);
-    P.add(a, work_coarse(a, m->C));
+    P.add(a, work_coarse(a, m->C), a.level0);
   }
   P.end();
   for (int l = max_coarsest(deep) - 1; l >= 0; --l) {
     const auto part = subset(deep, [&](Member* m) { return l < m->Lc(); });
-    P.begin(S_PASS, PASS_PSOL, l == 0);
+    P.begin(S_PASS, -1, l);
     for (Member* m : part) {
       m->R->top = l;
       const PassArgs a = m->R->make_prolong(l, PASS_PSOL, l == 0);
-      P.add(a, work_pass(a, m->C));
+      P.add_pass(a, work_pass(a, m->C));
     }
     P.end();
     if (l == 0) break;
@@ -258,7 +358,7 @@ void build_cycle(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
   if (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG)
     build_vcycle(P, ms, 0, o);
   else
-    step_oras(P, ms, 0, true, false);
+    step_oras_checked(P, ms);
 }
 
 void add_gather(Plan& P, const std::vector<Member*>& ms, int* flags_dev) {
@@ -271,8 +371,11 @@ namespace {
 
 std::vector<int> level_state(const std::vector<Member*>& ms) {
   std::vector<int> s;
-  for (Member* m : ms)
+  for (Member* m : ms) {
     for (int l = 0; l < m->ws->L; ++l) s.push_back(m->ws->lv[l].cur);
+    s.push_back(m->ws->lv[0].ecur);
+    s.push_back(m->ws->lv[0].ezero);
+  }
   return s;
 }
 
@@ -303,7 +406,7 @@ namespace {
 
 std::mutex g_bmu;
 std::list<std::shared_ptr<BatchCtx>> g_bcache;  // most recently used first
-constexpr size_t kBatchCacheSize = 8;
+constexpr size_t kBatchCacheSize = 32;
 
 std::string ctx_key(int dev, const std::vector<Member*>& ms, const Opts& o, double tol) {
   std::string k;
@@ -524,11 +627,13 @@ void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* 
   P.begin(S_RESET);
   for (Member* m : ms) P.add(ResetArgs{m->ws->active, m->ws->status, m->ws->cgstat, m->C}, 1u);
   P.end();
-  P.begin(S_STAGE);
+  P.begin(S_STAGE, 0, 0);
   for (Member* m : ms) {
     Workspace* ws = m->ws;
     Level& L0 = ws->lv[0];
     L0.cur = 0;
+    L0.ecur = 0;
+    L0.ezero = true;
     NormOut den = m->R->norm(0, false);
     den.out = ws->den;
     den.rho = ws->rho;
@@ -543,7 +648,7 @@ void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* 
     for (Member* m : ms) maxL = std::max(maxL, m->ws->L);
     for (int l = 0; l + 1 < maxL; ++l) {
       const auto part = subset(ms, [&](Member* m) { return l + 1 < m->ws->L; });
-      P.begin(S_MASK);
+      P.begin(S_MASK, 0, l);
       for (Member* m : part) {
         Level& F = m->ws->lv[l];
         Level& Cl = m->ws->lv[l + 1];
@@ -552,12 +657,12 @@ void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* 
         P.add(a, work_mask(a));
       }
       P.end();
-      P.begin(S_RHS, 0, l == 0);
+      P.begin(S_RHS, 0, l);
       for (Member* m : part) {
         Level& F = m->ws->lv[l];
         Level& Cl = m->ws->lv[l + 1];
         const RhsArgs a{F.v, Cl.v, F.c, F.b, Cl.c, Cl.b, m->C, o.rhs == INPAINT_RHS_NAIVE ? 1 : 0};
-        P.add(a, work_rhs(a));
+        P.add(a, work_rhs(a), l == 0 ? 1 : 0);
       }
       P.end();
     }
@@ -566,7 +671,7 @@ void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* 
 }
 
 void build_output(Plan& P, const std::vector<Member*>& ms) {
-  P.begin(S_OUTPUT);
+  P.begin(S_OUTPUT, 0, 0);
   for (Member* m : ms) {
     const Level& L0 = m->ws->lv[0];
     OutputArgs a{};
@@ -602,8 +707,6 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
         fail(INPAINT_E_INVALID, "the outputs of two problems overlap");
   }
   hipStream_t s = (hipStream_t)stream;
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
   std::vector<std::unique_ptr<Member>> own;
   std::vector<Member*> all;
   for (int i = 0; i < n; ++i) {
@@ -614,6 +717,30 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
     init_member(m, probs[i], m.lease.ws, o, tol, s);
     all.push_back(own.back().get());
   }
+  const float ms = run_batch(all, o, tol, s, nullptr);
+  int ret = INPAINT_OK;
+  std::string msg;
+  for (Member* m : all) {
+    if (ret == INPAINT_OK || (ret == INPAINT_NOT_CONVERGED && m->status < 0)) {
+      if (m->status != INPAINT_OK) {
+        ret = m->status;
+        msg = "problem " + std::to_string(m->idx) + ": " + m->msg;
+      }
+    }
+    if (stats) {
+      fill_stats(m, stats[m->idx]);
+      stats[m->idx].gpu_ms = ms;
+    }
+  }
+  g_err = msg;
+  return ret;
+}
+
+float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipStream_t s,
+                Prof* prof) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  const int n = (int)all.size();
   auto ctx = batch_ctx(dev, all, o, tol, n);
   BatchCtx& c = *ctx;
   const int prec = o.prec, B = o.B;
@@ -623,7 +750,7 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
   Plan prep;
   build(prep, all, [&] { build_prepare(prep, all, o, c.flags_dev); });
   upload({&prep}, &c.call_dev, &c.call_cap, s);
-  HIPCHK(issue(prep, prec, B, s));
+  HIPCHK(issue(prep, prec, B, s, prof));
   HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)n * 64, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   std::vector<Member*> live;
@@ -658,9 +785,10 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
       if (level_state(live) != s0) fail(INPAINT_E_DEVICE, "cycle plans do not return to their start state");
       upload({&c.cascade, &c.cycle[0], &c.cycle[1]}, &c.plan_dev, &c.plan_cap, s);
       HIPCHK(hipStreamSynchronize(s));
-      for (int k = 0; k < c.ncycle; ++k) capture(c.cycle[k], c, prec, B);
+      if (!prof)
+        for (int k = 0; k < c.ncycle; ++k) capture(c.cycle[k], c, prec, B);
     }
-    run_plan(c.cascade, prec, B, s);
+    HIPCHK(issue(c.cascade, prec, B, s, prof));
     account(live, c.cascade);
     bool done = poll_members(c, live, c.cascade, s);
     int cycles = 0;
@@ -669,7 +797,10 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
       for (Member* m : live)
         if (!m->done) ++m->cycles;
       account(live, P);
-      run_plan(P, prec, B, s);
+      if (prof)
+        HIPCHK(issue(P, prec, B, s, prof));
+      else
+        run_plan(P, prec, B, s);
       ++cycles;
       done = poll_members(c, live, P, s);
     }
@@ -678,7 +809,7 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
     Plan out;
     build_output(out, live);
     upload({&out}, &c.call_dev, &c.call_cap, s);
-    HIPCHK(issue(out, prec, B, s));
+    HIPCHK(issue(out, prec, B, s, prof));
   }
   HIPCHK(hipEventRecord(c.ev1, s));
   for (Member* m : live)
@@ -688,22 +819,7 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
   HIPCHK(hipStreamSynchronize(s));
   float ms = 0.0f;
   HIPCHK(hipEventElapsedTime(&ms, c.ev0, c.ev1));
-  int ret = INPAINT_OK;
-  std::string msg;
-  for (Member* m : all) {
-    if (ret == INPAINT_OK || (ret == INPAINT_NOT_CONVERGED && m->status < 0)) {
-      if (m->status != INPAINT_OK) {
-        ret = m->status;
-        msg = "problem " + std::to_string(m->idx) + ": " + m->msg;
-      }
-    }
-    if (stats) {
-      fill_stats(m, stats[m->idx]);
-      stats[m->idx].gpu_ms = ms;
-    }
-  }
-  g_err = msg;
-  return ret;
+  return ms;
 }
 
 }  // namespace inpaint

@@ -75,6 +75,14 @@ struct Level {
   int* itot = nullptr;  // [C][nblk] local CG iterations per block, summed over a solve
   int* imax = nullptr;  // [C][nblk] their maximum (itot and imax are contiguous)
   int cur = 0;
+  // Precision form, finest grid only: the V-cycle solves for a correction e of
+  // the float32 iterate with 16-bit fields: e (double-buffered), its
+  // right-hand side d (the float64 residual of u, rounded) and its residual rh.
+  void* e[2] = {nullptr, nullptr};
+  void* d = nullptr;
+  void* rh = nullptr;
+  int ecur = 0;
+  bool ezero = true;  // e is zero (at the start of every V-cycle)
 };
 
 struct Key {
@@ -205,6 +213,30 @@ struct Run {
   static Sc sc_err() { return Sc{kErr, 1}; }
   static Sc sc_one() { return Sc{1.0f, 0}; }
   int prec() const { return ws->key.prec; }
+  // The finest grid runs the correction form (16-bit e on a float32 u): the
+  // precision form on a hierarchy of more than one level.
+  bool corr0() const { return ws->key.prec != PREC_F32 && ws->L > 1; }
+
+  // Arguments of a pass over the finest grid's correction problem: iterate e,
+  // right-hand side d, residual rh, all of the correction type.  The pass runs
+  // `mode`, or `mode0` while e is still zero.
+  PassArgs corr_args(int mode, int mode0) {
+    Level& L = ws->lv[0];
+    PassArgs a = pass_args(0);
+    a.mode = L.ezero ? mode0 : mode;
+    a.level0 = 0;
+    a.solution = 0;
+    a.s_u = sc_err();
+    a.s_b = sc_res(0);
+    a.s_r = sc_res(0);
+    a.b = L.d;
+    a.u_in = L.e[L.ecur];
+    a.u_out = L.e[L.ecur ^ 1];
+    a.r = L.rh;
+    L.ecur ^= 1;
+    L.ezero = false;
+    return a;
+  }
 
   PassArgs pass_args(int l) const {
     const Level& L = ws->lv[l];
@@ -235,8 +267,15 @@ struct Run {
 
   PassArgs make_residual(int l, bool check) {
     PassArgs a = pass_args(l);
+    a.mode = PASS_RES;
     a.u_out = nullptr;
     a.norm = norm(l, check);
+    if (l == 0 && corr0()) {
+      // the residual of u is the right-hand side of the next correction problem
+      a.r = ws->lv[0].d;
+      a.r_tc = 1;
+      ws->lv[0].ezero = true;
+    }
     return a;
   }
 
@@ -251,6 +290,10 @@ struct Run {
     b.s_contrib = sc_err();
     b.c = L.c;
     b.r = L.r;
+    if (l == 0 && corr0()) {
+      b.level0 = 0;
+      b.r = L.ezero ? L.d : L.rh;  // while e = 0 its residual is d
+    }
     b.snorm = ws->snorm + (size_t)l * C;
     b.contrib = L.contrib;
     b.gamma = o.gamma;
@@ -266,7 +309,10 @@ struct Run {
   // new residual to level l + 1 (the last pre-smoothing of a V-cycle).
   PassArgs make_update(int l, bool check, bool rest) {
     Level& L = ws->lv[l];
-    PassArgs a = pass_args(l);
+    const bool corr = l == 0 && corr0();
+    if (corr && check) fail(INPAINT_E_DEVICE, "a correction update cannot test convergence");
+    PassArgs a = corr ? corr_args(PASS_UPD, PASS_UPD0) : pass_args(l);
+    if (!corr) a.mode = PASS_UPD;
     a.norm = norm(l, check);
     if (rest) {
       Level& Cl = ws->lv[l + 1];
@@ -278,7 +324,7 @@ struct Run {
       a.rc = Cl.r;
       a.norm = norm(l + 1, false);
     }
-    L.cur ^= 1;
+    if (!corr) L.cur ^= 1;
     ++oras_iters;
     block_solves += (long)L.v.nbx * L.v.nby * C;
     if (l == 0) finest_block_solves += (long long)L.v.nbx * L.v.nby * C;
@@ -288,7 +334,15 @@ struct Run {
   PassArgs make_prolong(int l, int mode, bool check) {
     Level& L = ws->lv[l];
     const Level& Lc = ws->lv[l + 1];
-    PassArgs a = pass_args(l);
+    const bool corr = l == 0 && corr0() && mode == PASS_PCORR;
+    if (corr && check) fail(INPAINT_E_DEVICE, "a correction pass cannot test convergence");
+    PassArgs a = corr ? corr_args(PASS_PCORR, PASS_PCORR0) : pass_args(l);
+    if (!corr) a.mode = mode;
+    if (l == 0 && corr0() && mode == PASS_PSOL) {
+      a.r = L.d;
+      a.r_tc = 1;
+      L.ezero = true;
+    }
     a.uc = Lc.u[Lc.cur];
     // the coarse field is a solution in the cascade and a correction in a V-cycle
     a.s_uc = mode == PASS_PSOL ? sc_one() : sc_err();
@@ -297,7 +351,31 @@ struct Run {
     a.Pc = Lc.v.P;
     a.planec = Lc.v.plane;
     a.norm = norm(l, check);
+    if (!corr) L.cur ^= 1;
+    return a;
+  }
+
+  // Precision form, finest grid: u += e (+ the block corrections of the ORAS
+  // iteration whose block solves just ran, when `blocks`), then the float64
+  // residual of the new u, its norm and the convergence test; the residual,
+  // rounded, is the right-hand side d of the next correction problem.
+  PassArgs make_final(bool check, bool blocks) {
+    Level& L = ws->lv[0];
+    PassArgs a = pass_args(0);
+    a.mode = blocks ? PASS_FIN : PASS_FIN0;
+    a.e_add = L.ezero ? nullptr : L.e[L.ecur];
+    a.s_e = sc_err();
+    if (!blocks) a.contrib = nullptr;
+    a.r = L.d;
+    a.r_tc = 1;
+    a.norm = norm(0, check);
     L.cur ^= 1;
+    L.ezero = true;
+    if (blocks) {
+      ++oras_iters;
+      block_solves += (long)L.v.nbx * L.v.nby * C;
+      finest_block_solves += (long long)L.v.nbx * L.v.nby * C;
+    }
     return a;
   }
 
@@ -310,6 +388,11 @@ struct Run {
     a.prec = prec();
     a.level0 = l == 0;
     a.rf = F.r;
+    if (l == 0 && corr0()) {
+      // pre-smoothing is off: e = 0, so the residual to restrict is d
+      a.level0 = 0;
+      a.rf = F.d;
+    }
     a.cc = Cl.c;
     a.bc = Cl.b;
     a.uc = Cl.u[Cl.cur];
@@ -346,19 +429,19 @@ struct Run {
 
   void residual(int l, bool check) {
     const PassArgs a = make_residual(l, check);
-    timed(INPAINT_K_RESIDUAL, l, [&] { return launch_pass(PASS_RES, a, C, s); });
+    timed(INPAINT_K_RESIDUAL, l, [&] { return launch_pass(a.mode, a, C, s); });
   }
 
   void oras(int l, bool check, bool rest = false) {
     const BlockArgs b = make_block(l);
     timed(INPAINT_K_BLOCK_SOLVE, l, [&] { return launch_block_solve(b, C, s); });
     const PassArgs a = make_update(l, check, rest);
-    timed(INPAINT_K_UPDATE, l, [&] { return launch_pass(PASS_UPD, a, C, s); });
+    timed(INPAINT_K_UPDATE, l, [&] { return launch_pass(a.mode, a, C, s); });
   }
 
   void prolong(int l, int mode, bool check) {
     const PassArgs a = make_prolong(l, mode, check);
-    timed(INPAINT_K_PROLONG, l, [&] { return launch_pass(mode, a, C, s); });
+    timed(INPAINT_K_PROLONG, l, [&] { return launch_pass(a.mode, a, C, s); });
   }
 
   void restrict_to(int l) {
@@ -370,58 +453,12 @@ struct Run {
     const CoarseArgs a = make_coarse(l, init);
     timed(INPAINT_K_COARSE, l, [&] { return launch_coarse_solve(a, C, s); });
   }
-
-  // One V-cycle on level l for the problem held in (b_l, u_l).  On return
-  // (l > 0) u_l holds the correction; at l == 0 the residual of the finest
-  // grid and its norm are current.
-  void vcycle(int l) {
-    const int Lc = ws->L - 1;
-    if (l == Lc) {
-      coarse(l, l != 0);
-      if (l == 0) residual(0, true);
-      return;
-    }
-    for (int i = 0; i < o.pre; ++i) oras(l, false, i == o.pre - 1);
-    if (o.pre == 0) restrict_to(l);
-    vcycle(l + 1);
-    prolong(l, PASS_PCORR, l == 0 && o.post == 0);
-    for (int i = 0; i < o.post; ++i) oras(l, l == 0 && i == o.post - 1);
-  }
-
-  // Coarse-to-fine initial guess (Section 4.2): exact-ish solve on the
-  // coarsest grid, then on every finer level prolongate the solution, reset
-  // the known pixels and smooth with one ORAS iteration (reduced FMG) or a
-  // V-cycle (full FMG); the finest level is left to the V-cycles.
-  void cascade() {
-    const int Lc = ws->L - 1;
-    if (Lc == 0) {
-      residual(0, true);
-      return;
-    }
-    top = Lc;
-    coarse(Lc, true);
-    for (int l = Lc - 1; l >= 0; --l) {
-      top = l;
-      prolong(l, PASS_PSOL, l == 0);
-      if (l == 0) break;
-      if (o.schedule == INPAINT_SCHED_FMG)
-        vcycle(l);
-      else
-        oras(l, false);
-    }
-  }
 };
 
-struct SolveResult {
-  int status = INPAINT_OK;
-  double rel = 0.0;
-  int cycles = 0;
-};
 
 // Stage (f, mask) into level 0 and build the hierarchy; returns after the
 // input checks have been read back.
 void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy, bool write_u);
-SolveResult run_solve(Run& R, float* out_d);
 void check_dims(const void* a, const void* b, int W, int H, int C);
 bool overlap(const void* a, size_t na, const void* b, size_t nb);
 

@@ -62,16 +62,22 @@ struct NormOut {
 };
 
 enum PassMode : int {
-  PASS_RES = 0,    // u_new = u_in (residual only; u_out unused)
-  PASS_UPD = 1,    // u_new = u_in + sum of weighted block corrections
-  PASS_PSOL = 2,   // u_new = mask ? b : P u_c   (cascade prolongation)
-  PASS_PCORR = 3,  // u_new = u_in + (mask ? 0 : P u_c)   (coarse-grid correction)
+  PASS_RES = 0,     // u_new = u_in (residual only; u_out unused)
+  PASS_UPD = 1,     // u_new = u_in + sum of weighted block corrections
+  PASS_PSOL = 2,    // u_new = mask ? b : P u_c   (cascade prolongation)
+  PASS_PCORR = 3,   // u_new = u_in + (mask ? 0 : P u_c)   (coarse-grid correction)
+  // the precision form's finest grid (a 16-bit correction e of a float32 u):
+  PASS_UPD0 = 4,    // as PASS_UPD with u_in = 0 (not read)
+  PASS_FIN = 5,     // u_new = u_in + (e + sum of weighted block corrections), r of type prec
+  PASS_FIN0 = 6,    // u_new = u_in + e, r of type prec
+  PASS_PCORR0 = 7,  // as PASS_PCORR with u_in = 0 (not read)
 };
+constexpr int kPassModes = 8;
 
-// The level's own iterate, known values / right-hand side and residual are
-// float32 on the finest grid (level0 = 1) and of the correction type `prec`
-// elsewhere; corrections, the coarse field and the fused restriction's outputs
-// are always of type `prec`.
+// The launch's own iterate, known values / right-hand side and residual are
+// float32 when level0 = 1 (the finest grid's solution fields) and of the
+// correction type `prec` otherwise; corrections, the coarse field and the fused
+// restriction's outputs are always of type `prec`.
 struct PassArgs {
   LevelView lv;
   int prec, level0;
@@ -83,7 +89,7 @@ struct PassArgs {
   const void* u_in;
   void* u_out;
   void* r;
-  const void* contrib;   // PASS_UPD: [C][nby*nbx][B][B]
+  const void* contrib;   // PASS_UPD, UPD0, FIN: [C][nby*nbx][B][B]
   const void* uc;        // PASS_PSOL/PCORR: coarse field [C][Hc][Pc]
   int Wc, Hc, Pc;
   size_t planec;
@@ -100,6 +106,10 @@ struct PassArgs {
   void* rc;
   const float* rho;      // [C]
   Sc s_u, s_b, s_r, s_contrib, s_uc, s_cr;  // s_cr: coarse b and r of the restriction
+  int mode;              // the PassMode this launch runs (all problems of a launch share it)
+  const void* e_add;     // PASS_FIN, PASS_FIN0: the correction e (type prec, scale s_e)
+  Sc s_e;
+  int r_tc;              // PASS_PSOL, PASS_RES: the residual r is stored with type prec
 };
 
 struct BlockArgs {

@@ -54,7 +54,7 @@ struct Fld {
   T* p;
   float s, inv;
   __device__ __forceinline__ Fld(const void* base, size_t chan_off, Sc sc, const float* rho, int ch) {
-    p = (T*)base + chan_off;
+    p = base ? (T*)base + chan_off : nullptr;  // optional fields may be absent
     if constexpr (is_f32<T>()) {
       s = inv = 1.0f;
     } else {
@@ -540,11 +540,24 @@ __device__ __forceinline__ double bilinear(double a, double b, double c, double 
 // New iterate at (gx, gy) (inside the image) for one pass mode.  Column data
 // is computed once per thread, row data per row.  TU: element type of this
 // level's iterate and known values; TC: corrections and the coarse field.
+// what a pass mode reads and writes
+__host__ __device__ constexpr bool mode_upd(int m) {
+  return m == PASS_UPD || m == PASS_UPD0 || m == PASS_FIN || m == PASS_FIN0;
+}
+__host__ __device__ constexpr bool mode_contrib(int m) {
+  return m == PASS_UPD || m == PASS_UPD0 || m == PASS_FIN;
+}
+__host__ __device__ constexpr bool mode_pcorr(int m) { return m == PASS_PCORR || m == PASS_PCORR0; }
+__host__ __device__ constexpr bool mode_zero(int m) { return m == PASS_UPD0 || m == PASS_PCORR0; }
+__host__ __device__ constexpr bool mode_fin(int m) { return m == PASS_FIN || m == PASS_FIN0; }
+__host__ __device__ constexpr bool mode_rest(int m) { return m == PASS_UPD || m == PASS_UPD0; }
+
 template <int MODE, class TU, class TC>
 struct Former {
   const PassArgs& a;
   Fld<TU> uin, bb;
   Fld<TC> cb, uc;   // corrections of this channel (UPD); coarse field (PSOL, PCORR)
+  Fld<TC> ea;       // added correction (UPD with e_add)
   int S, o, B, nbx, nby;
   float rS;
 
@@ -554,7 +567,8 @@ struct Former {
         bb(a_.b, (size_t)ch * a_.lv.plane, a_.s_b, a_.rho, ch),
         cb(a_.contrib, (size_t)ch * ((size_t)a_.lv.nbx * a_.lv.nby * a_.lv.B * a_.lv.B), a_.s_contrib,
            a_.rho, ch),
-        uc(a_.uc, (size_t)ch * a_.planec, a_.s_uc, a_.rho, ch) {
+        uc(a_.uc, (size_t)ch * a_.planec, a_.s_uc, a_.rho, ch),
+        ea(a_.e_add, (size_t)ch * a_.lv.plane, a_.s_e, a_.rho, ch) {
     const LevelView& lv = a.lv;
     B = lv.B;
     S = lv.B - lv.o;
@@ -573,13 +587,13 @@ struct Former {
   __device__ Col col(int gx) const {
     Col c;
     c.gx = gx;
-    if constexpr (MODE == PASS_UPD) {
+    if constexpr (mode_contrib(MODE)) {
       const BlockAxis ax = block_axis(gx, S, rS, o, nbx);
       c.cx1 = ax.b1 * B * B + ax.l1;
       c.cx0 = (ax.b1 - 1) * B * B + ax.l1 + S;
       c.h0 = ax.h0;
     }
-    if constexpr (MODE == PASS_PSOL || MODE == PASS_PCORR) prolong_axis(gx, a.Wc, c.xn, c.xf);
+    if constexpr (MODE == PASS_PSOL || mode_pcorr(MODE)) prolong_axis(gx, a.Wc, c.xn, c.xf);
     return c;
   }
 
@@ -588,18 +602,24 @@ struct Former {
     const int off = gy * lv.P + c.gx;
     if constexpr (MODE == PASS_RES) {
       return uin.ld(off);
-    } else if constexpr (MODE == PASS_UPD) {
-      const BlockAxis ay = block_axis(gy, S, rS, o, nby);
-      const int ry1 = ay.b1 * nbx * B * B + ay.l1 * B;
-      const int ry0 = (ay.b1 - 1) * nbx * B * B + (ay.l1 + S) * B;
+    } else if constexpr (mode_upd(MODE)) {
       float d = 0.0f;
-      if (ay.h0) {
-        if (c.h0) d += cb.ld(ry0 + c.cx0);
-        d += cb.ld(ry0 + c.cx1);
+      if constexpr (mode_contrib(MODE)) {
+        const BlockAxis ay = block_axis(gy, S, rS, o, nby);
+        const int ry1 = ay.b1 * nbx * B * B + ay.l1 * B;
+        const int ry0 = (ay.b1 - 1) * nbx * B * B + (ay.l1 + S) * B;
+        if (ay.h0) {
+          if (c.h0) d += cb.ld(ry0 + c.cx0);
+          d += cb.ld(ry0 + c.cx1);
+        }
+        if (c.h0) d += cb.ld(ry1 + c.cx0);
+        d += cb.ld(ry1 + c.cx1);
       }
-      if (c.h0) d += cb.ld(ry1 + c.cx0);
-      d += cb.ld(ry1 + c.cx1);
-      return uin.ld(off) + d;
+      if constexpr (mode_fin(MODE)) d = ea.ld(off) + d;
+      if constexpr (mode_zero(MODE))
+        return d;
+      else
+        return uin.ld(off) + d;
     } else {
       const bool known = a.c[off] != 0;
       int yn, yf;
@@ -609,7 +629,7 @@ struct Former {
       if constexpr (MODE == PASS_PSOL) {
         return known ? bb.ld(off) : (float)p;
       } else {
-        const float u = uin.ld(off);
+        const float u = mode_zero(MODE) ? 0.0f : uin.ld(off);
         return known ? u : (float)((double)u + p);
       }
     }
@@ -664,10 +684,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   constexpr int RK = kTileH / NG;  // phase-2 rows per thread
   const int gx = x0 + c;
   const bool colin = gx < lv.W;
-  const bool rest = MODE == PASS_UPD && a.rest;
-  __shared__ float rt[MODE == PASS_UPD ? kTileH : 1][MODE == PASS_UPD ? kTileW : 1];
+  const bool rest = mode_rest(MODE) && a.rest;
+  __shared__ float rt[mode_rest(MODE) ? kTileH : 1][mode_rest(MODE) ? kTileW : 1];
   const Fld<TU> uo(a.u_out, (size_t)ch * lv.plane, a.s_u, a.rho, ch);
   const Fld<TU> ro(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);
+  const Fld<TC> rlo(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);  // r_tc
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < RK; ++k) {
@@ -693,17 +714,20 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
         r = known ? 0.0 : bv - fma(4.0, ud, -nb);
       }
       const float rf = (float)r;
-      if constexpr (MODE == PASS_UPD) {
+      if constexpr (mode_rest(MODE)) {
         if (rest) {
           rt[ty][c] = rf;
           continue;
         }
       }
-      ro.st(off, rf);
+      if (mode_fin(MODE) || ((MODE == PASS_PSOL || MODE == PASS_RES) && a.r_tc))
+        rlo.st(off, rf);
+      else
+        ro.st(off, rf);
       acc += r * r;
     }
   }
-  if constexpr (MODE == PASS_UPD) {
+  if constexpr (mode_rest(MODE)) {
     if (rest) {
       // The tile's coarse cells have all their children inside the tile.
       __syncthreads();
@@ -1059,12 +1083,16 @@ __global__ void __launch_bounds__(kPassThreads) k_restrict_b(const RestrictArgs*
   restrict_body<TF, TC>(a, lin);
 }
 
+// Five wavefronts per SIMD (at most 96 registers) hide the latency of the
+// cross-lane operations better than the four a free register allocation gives.
 template <int B, class TR, class TC>
-__global__ void __launch_bounds__(kWave) k_block_solve(BlockArgs a) {
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(5, 8)))
+k_block_solve(BlockArgs a) {
   block_body<B, TR, TC>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 template <int B, class TR, class TC>
-__global__ void __launch_bounds__(kWave) k_block_b(const BlockArgs* __restrict__ args,
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(5, 8)))
+k_block_b(const BlockArgs* __restrict__ args,
                                                    const unsigned* __restrict__ start, int n) {
   INPAINT_BATCH_LOOKUP(BlockArgs)
   block_body<B, TR, TC>(a, lin);
@@ -1158,10 +1186,17 @@ hipError_t launch_pass(int mode, const PassArgs& a, int C, hipStream_t s) {
     using TU = typename decltype(tu)::type;
     using TC = typename decltype(tc)::type;
     switch (mode) {
-      case PASS_RES: hipLaunchKernelGGL((k_pass<PASS_RES, TU, TC>), grid, dim3(kPassThreads), 0, s, a); break;
-      case PASS_UPD: hipLaunchKernelGGL((k_pass<PASS_UPD, TU, TC>), grid, dim3(kPassThreads), 0, s, a); break;
-      case PASS_PSOL: hipLaunchKernelGGL((k_pass<PASS_PSOL, TU, TC>), grid, dim3(kPassThreads), 0, s, a); break;
-      case PASS_PCORR: hipLaunchKernelGGL((k_pass<PASS_PCORR, TU, TC>), grid, dim3(kPassThreads), 0, s, a); break;
+#define INPAINT_PASS_CASE(M) \
+  case M: hipLaunchKernelGGL((k_pass<M, TU, TC>), grid, dim3(kPassThreads), 0, s, a); break;
+      INPAINT_PASS_CASE(PASS_RES)
+      INPAINT_PASS_CASE(PASS_UPD)
+      INPAINT_PASS_CASE(PASS_PSOL)
+      INPAINT_PASS_CASE(PASS_PCORR)
+      INPAINT_PASS_CASE(PASS_UPD0)
+      INPAINT_PASS_CASE(PASS_FIN)
+      INPAINT_PASS_CASE(PASS_FIN0)
+      INPAINT_PASS_CASE(PASS_PCORR0)
+#undef INPAINT_PASS_CASE
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1257,10 +1292,19 @@ hipError_t launch_pass_b(int mode, const PassArgs* args, const unsigned* start, 
     using TU = typename decltype(tu)::type;
     using TC = typename decltype(tc)::type;
     switch (mode) {
-      case PASS_RES: hipLaunchKernelGGL((k_pass_b<PASS_RES, TU, TC>), grid, dim3(kPassThreads), 0, s, args, start, n); break;
-      case PASS_UPD: hipLaunchKernelGGL((k_pass_b<PASS_UPD, TU, TC>), grid, dim3(kPassThreads), 0, s, args, start, n); break;
-      case PASS_PSOL: hipLaunchKernelGGL((k_pass_b<PASS_PSOL, TU, TC>), grid, dim3(kPassThreads), 0, s, args, start, n); break;
-      case PASS_PCORR: hipLaunchKernelGGL((k_pass_b<PASS_PCORR, TU, TC>), grid, dim3(kPassThreads), 0, s, args, start, n); break;
+#define INPAINT_PASS_CASE(M)                                                                \
+  case M:                                                                                   \
+    hipLaunchKernelGGL((k_pass_b<M, TU, TC>), grid, dim3(kPassThreads), 0, s, args, start, n); \
+    break;
+      INPAINT_PASS_CASE(PASS_RES)
+      INPAINT_PASS_CASE(PASS_UPD)
+      INPAINT_PASS_CASE(PASS_PSOL)
+      INPAINT_PASS_CASE(PASS_PCORR)
+      INPAINT_PASS_CASE(PASS_UPD0)
+      INPAINT_PASS_CASE(PASS_FIN)
+      INPAINT_PASS_CASE(PASS_FIN0)
+      INPAINT_PASS_CASE(PASS_PCORR0)
+#undef INPAINT_PASS_CASE
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <map>
 
+#include "batch.h"
 #include "driver.h"
 
 namespace inpaint {
@@ -91,7 +92,7 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
     off = round_up(off + n, 256);
     return at;
   };
-  struct Offs { size_t c, b, u0, u1, r, contrib, it; };
+  struct Offs { size_t c, b, u0, u1, r, contrib, it, e0, e1, d, rh; };
   std::vector<Offs> lo(ws->L);
   size_t maxtiles = 1;
   for (int l = 0; l < ws->L; ++l) {
@@ -112,7 +113,17 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
     lo[l].b = take(f);
     lo[l].u0 = take(f);
     lo[l].u1 = take(f);
-    lo[l].r = take(f);
+    // the precision form's finest grid keeps its residual in 16 bits (d, rh)
+    // beside the correction e; the float32 residual is not needed there
+    const bool corr = l == 0 && k.prec != PREC_F32 && ws->L > 1;
+    lo[l].r = corr ? 0 : take(f);
+    if (corr) {
+      const size_t fe = (size_t)C * v.plane * es;
+      lo[l].e0 = take(fe);
+      lo[l].e1 = take(fe);
+      lo[l].d = take(fe);
+      lo[l].rh = take(fe);
+    }
     lo[l].contrib = take((size_t)C * v.nbx * v.nby * k.B * k.B * es);
     lo[l].it = take((size_t)2 * C * v.nbx * v.nby * sizeof(int));
     maxtiles = std::max(maxtiles, pass_tiles(v));
@@ -136,7 +147,14 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
     L.b = (float*)(base + lo[l].b);
     L.u[0] = (float*)(base + lo[l].u0);
     L.u[1] = (float*)(base + lo[l].u1);
-    L.r = (float*)(base + lo[l].r);
+    const bool corr = l == 0 && k.prec != PREC_F32 && ws->L > 1;
+    L.r = corr ? nullptr : (float*)(base + lo[l].r);
+    if (corr) {
+      L.e[0] = base + lo[l].e0;
+      L.e[1] = base + lo[l].e1;
+      L.d = base + lo[l].d;
+      L.rh = base + lo[l].rh;
+    }
     L.contrib = (float*)(base + lo[l].contrib);
     L.itot = (int*)(base + lo[l].it);
     L.imax = L.itot + (size_t)C * L.v.nbx * L.v.nby;
@@ -270,76 +288,6 @@ void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy, bool 
   if (!(h[0] & 2)) fail(INPAINT_E_EMPTY_MASK, "mask has no known pixel: the system is singular");
 }
 
-// Read back the per-channel flags; returns true when every channel is done.
-bool poll(Run& R, std::vector<int>& final_cur, std::vector<double>& rel) {
-  Workspace* ws = R.ws;
-  const int C = R.C;
-  char* h = (char*)ws->host;
-  HIPCHK(hipMemcpyAsync(h, ws->relres, 64, hipMemcpyDeviceToHost, R.s));
-  HIPCHK(hipStreamSynchronize(R.s));
-  const double* rr = (const double*)h;
-  const int* act = (const int*)(h + 32);
-  const int* st = (const int*)(h + 48);
-  if (st[0] & 4) fail(INPAINT_E_DEVICE, "a norm partial never arrived (spin budget exhausted)");
-  bool all = true;
-  for (int ch = 0; ch < C; ++ch) {
-    if (final_cur[ch] < 0) {
-      rel[ch] = rr[ch];
-      if (!act[ch] || !std::isfinite(rr[ch])) final_cur[ch] = ws->lv[0].cur;
-    }
-    all = all && final_cur[ch] >= 0;
-  }
-  return all;
-}
-
-SolveResult run_solve(Run& R, float* out_d) {
-  Workspace* ws = R.ws;
-  const int C = R.C;
-  std::vector<int> final_cur(C, -1);
-  std::vector<double> rel(C, 0.0);
-  SolveResult res;
-  const int sched = R.o.schedule;
-  if (sched == INPAINT_SCHED_SINGLE) {
-    R.residual(0, true);
-  } else {
-    R.cascade();
-  }
-  bool done = poll(R, final_cur, rel);
-  int cycles = 0;
-  while (!done && cycles < R.o.max_cycles) {
-    if (sched == INPAINT_SCHED_RFMG || sched == INPAINT_SCHED_FMG)
-      R.vcycle(0);
-    else
-      R.oras(0, true);
-    ++cycles;
-    done = poll(R, final_cur, rel);
-  }
-  bool diverged = false;
-  for (int ch = 0; ch < C; ++ch) {
-    if (final_cur[ch] < 0) final_cur[ch] = ws->lv[0].cur;
-    if (!std::isfinite(rel[ch])) diverged = true;
-  }
-  const float* sel[kMaxChannels];
-  for (int ch = 0; ch < C; ++ch) sel[ch] = ws->lv[0].u[final_cur[ch]];
-  R.timed(INPAINT_K_OUTPUT, 0, [&] {
-    return launch_output(ws->lv[0].v, ws->lv[0].c, ws->lv[0].b, sel, out_d, ws->key.W, C, R.s);
-  });
-  if (R.o.profile)
-    for (int l = 0; l < ws->L; ++l)
-      HIPCHK(launch_cg_stats(ws->lv[l].v, ws->lv[l].itot, ws->lv[l].imax, C,
-                             ws->cgstat + (size_t)l * C * 3, R.s));
-  res.cycles = cycles;
-  res.rel = 0.0;
-  for (int ch = 0; ch < C; ++ch) res.rel = std::max(res.rel, rel[ch]);
-  if (diverged) {
-    res.status = INPAINT_E_DIVERGED;
-    res.rel = NAN;
-  } else if (!done) {
-    res.status = INPAINT_NOT_CONVERGED;
-  }
-  return res;
-}
-
 void check_dims(const void* a, const void* b, int W, int H, int C) {
   if (!a || !b) fail(INPAINT_E_INVALID, "NULL pointer argument");
   if (W < 1 || H < 1) fail(INPAINT_E_INVALID, "W and H must be >= 1");
@@ -363,69 +311,57 @@ int solve_impl(const float* f, const uint8_t* mask, int W, int H, int C, double 
   if (out != f && overlap(out, nf, f, nf)) fail(INPAINT_E_INVALID, "out partially overlaps f");
   if (overlap(out, nf, mask, (size_t)W * H)) fail(INPAINT_E_INVALID, "out overlaps mask");
   hipStream_t s = (hipStream_t)stream;
-  Lease lease;
-  acquire(lease, W, H, C, o.B, o.o, o.B, o.prec);
-  Workspace* ws = lease.ws;
-  const bool fd = is_device_ptr(f), md = is_device_ptr(mask), od = is_device_ptr(out);
-  if (!fd || !md || !od) ensure_staging(ws);
-  const float* f_d = f;
-  const uint8_t* m_d = mask;
-  float* o_d = out;
-  if (!fd) {
-    HIPCHK(hipMemcpyAsync(ws->f_dev, f, nf, hipMemcpyHostToDevice, s));
-    f_d = ws->f_dev;
-  }
-  if (!md) {
-    HIPCHK(hipMemcpyAsync(ws->m_dev, mask, (size_t)W * H, hipMemcpyHostToDevice, s));
-    m_d = ws->m_dev;
-  }
-  if (!od) o_d = ws->o_dev;
-  Run R{ws, o, s, C, tol};
-  HIPCHK(hipEventRecord(ws->ev0, s));
-  prepare(R, f_d, m_d, o.schedule != INPAINT_SCHED_SINGLE, o.schedule == INPAINT_SCHED_SINGLE);
-  const SolveResult res = run_solve(R, o_d);
-  HIPCHK(hipEventRecord(ws->ev1, s));
-  if (!od) HIPCHK(hipMemcpyAsync(out, ws->o_dev, nf, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (stats) {
-    std::memset(stats, 0, sizeof(*stats));
-    stats->rel_res = res.rel;
-    stats->cycles = res.cycles;
-    stats->levels = ws->L;
-    stats->oras_iters = (int)(R.oras_iters * C);
-    std::vector<unsigned long long> cg((size_t)3 * C * ws->L, 0);
-    HIPCHK(hipMemcpy(cg.data(), ws->cgstat, cg.size() * sizeof(unsigned long long),
-                     hipMemcpyDeviceToHost));
-    unsigned long long tot = 0, mx = 0, fin = 0, finpx = 0;
-    for (int l = 0; l < ws->L; ++l)
-      for (int ch = 0; ch < C; ++ch) {
-        const unsigned long long* c3 = &cg[((size_t)l * C + ch) * 3];
-        tot += c3[0];
-        mx = std::max(mx, c3[1]);
-        if (l == 0) {
-          fin += c3[0];
-          finpx += c3[2];
-        }
-      }
-    stats->local_cg_mean = R.block_solves ? (double)tot / (double)R.block_solves : 0.0;
-    stats->local_cg_max = (int)mx;
-    stats->local_cg_finest = (double)fin;
-    stats->finest_block_solves = R.finest_block_solves;
-    stats->finest_cg_pixel_iters = (double)finpx;
-    for (const auto& rc : R.recs) {
-      float kms = 0.0f;
-      HIPCHK(hipEventElapsedTime(&kms, rc.a, rc.b));
-      stats->kernel_ms[rc.cls] += kms;
-      stats->kernel_calls[rc.cls] += 1;
+  Member m;
+  acquire(m.lease, W, H, C, o.B, o.o, o.B, o.prec);
+  const inpaint_problem p{f, mask, W, H, C, out};
+  init_member(m, p, m.lease.ws, o, tol, s);
+  Workspace* ws = m.ws;
+  Prof prof;
+  prof.pool = &ws->evpool;
+  if (o.profile)
+    for (int l = 0; l < ws->L; ++l) {
+      const Level& L = ws->lv[l];
+      // two int arrays of C*nblk entries = C*nblk doubles of zero bits
+      HIPCHK(launch_fill((double*)L.itot, (size_t)C * L.v.nbx * L.v.nby, 0.0, s));
     }
-    float ms = 0.0f;
-    HIPCHK(hipEventElapsedTime(&ms, ws->ev0, ws->ev1));
+  const float ms = run_batch({&m}, o, tol, s, o.profile ? &prof : nullptr);
+  if (m.status == INPAINT_E_INVALID || m.status == INPAINT_E_EMPTY_MASK) fail(m.status, m.msg);
+  if (stats) {
+    fill_stats(&m, *stats);
     stats->gpu_ms = ms;
-    stats->status = res.status;
+    if (o.profile) {
+      for (int l = 0; l < ws->L; ++l)
+        HIPCHK(launch_cg_stats(ws->lv[l].v, ws->lv[l].itot, ws->lv[l].imax, C,
+                               ws->cgstat + (size_t)l * C * 3, s));
+      std::vector<unsigned long long> cg((size_t)3 * C * ws->L, 0);
+      HIPCHK(hipMemcpyAsync(cg.data(), ws->cgstat, cg.size() * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      unsigned long long tot = 0, mx = 0, fin = 0, finpx = 0;
+      for (int l = 0; l < ws->L; ++l)
+        for (int ch = 0; ch < C; ++ch) {
+          const unsigned long long* c3 = &cg[((size_t)l * C + ch) * 3];
+          tot += c3[0];
+          mx = std::max(mx, c3[1]);
+          if (l == 0) {
+            fin += c3[0];
+            finpx += c3[2];
+          }
+        }
+      stats->local_cg_mean = m.blocks ? (double)tot / (double)m.blocks : 0.0;
+      stats->local_cg_max = (int)mx;
+      stats->local_cg_finest = (double)fin;
+      stats->finest_cg_pixel_iters = (double)finpx;
+      for (const auto& rc : prof.recs) {
+        float kms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&kms, rc.a, rc.b));
+        stats->kernel_ms[rc.cls] += kms;
+        stats->kernel_calls[rc.cls] += 1;
+      }
+    }
   }
-  if (res.status == INPAINT_E_DIVERGED) g_err = "the residual became non-finite";
-  else if (res.status == INPAINT_NOT_CONVERGED) g_err = "cycle cap reached before the tolerance";
-  return res.status;
+  g_err = m.status == INPAINT_OK ? "" : m.msg;
+  return m.status;
 }
 
 // Copy a host [C][H][W] array into a pitched level field.
