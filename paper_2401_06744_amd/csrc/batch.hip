@@ -230,12 +230,14 @@ void step_final(Plan& P, const std::vector<Member*>& ms, bool blocks) {
   P.end();
 }
 
-// One ORAS iteration on level l of every member in ms.
-void step_oras(Plan& P, const std::vector<Member*>& ms, int l, bool check, bool rest) {
+// One ORAS iteration on level l of every member in ms (need: a later launch
+// reads the norm its update writes).
+void step_oras(Plan& P, const std::vector<Member*>& ms, int l, bool check, bool rest,
+               bool need = true) {
   step_block(P, ms, l);
   P.begin(S_PASS, -1, l);
   for (Member* m : ms) {
-    const PassArgs a = m->R->make_update(l, check, rest);
+    const PassArgs a = m->R->make_update(l, check, rest, need);
     P.add_pass(a, work_pass(a, m->C));
   }
   P.end();
@@ -300,17 +302,19 @@ void build_vcycle(Plan& P, const std::vector<Member*>& ms, int l0, const Opts& o
     const auto plain = subset(part, [&](Member* m) { return !(l == 0 && corr0(m)); });
     P.begin(S_PASS, -1, l);
     for (Member* m : plain) {
-      const PassArgs a = m->R->make_prolong(l, PASS_PCORR, l == 0 && o.post == 0);
+      const PassArgs a = m->R->make_prolong(l, PASS_PCORR, l == 0 && o.post == 0, o.post > 0);
       P.add_pass(a, work_pass(a, m->C));
     }
     P.end();
-    for (int i = 0; i < o.post; ++i) step_oras(P, plain, l, l == 0 && i == o.post - 1, false);
+    // on coarser levels the last post-smoothing's norm is not read
+    for (int i = 0; i < o.post; ++i)
+      step_oras(P, plain, l, l == 0 && i == o.post - 1, false, l == 0 || i + 1 < o.post);
     if (corr.empty()) continue;
     // precision form: the correction e of the float32 iterate gets the coarse
     // correction and the post-smoothing; the last update adds e to u and tests
     P.begin(S_PASS, -1, 0);
     for (Member* m : corr) {
-      const PassArgs a = m->R->make_prolong(0, PASS_PCORR, false);
+      const PassArgs a = m->R->make_prolong(0, PASS_PCORR, false, o.post > 0);
       P.add_pass(a, work_pass(a, m->C));
     }
     P.end();
@@ -350,7 +354,7 @@ void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
     if (o.schedule == INPAINT_SCHED_FMG)
       build_vcycle(P, part, l, o);
     else
-      step_oras(P, part, l, false, false);
+      step_oras(P, part, l, false, false, false);
   }
 }
 
@@ -635,6 +639,7 @@ void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* 
     L0.ecur = 0;
     L0.ezero = true;
     NormOut den = m->R->norm(0, false);
+    den.mode = NORM_FULL;
     den.out = ws->den;
     den.rho = ws->rho;
     den.inv_n = 1.0 / ((double)m->W * (double)m->H);

@@ -83,6 +83,12 @@ struct Level {
   void* rh = nullptr;
   int ecur = 0;
   bool ezero = true;  // e is zero (at the start of every V-cycle)
+  // Deferred norm partials of this level's residual ([C][dstride]; dstride 0:
+  // the level's norms are always reduced in the pass) and the number of
+  // partials its latest writer left (0: the norm is in the workspace's snorm).
+  double* dpart = nullptr;
+  int dstride = 0;
+  int npart = 0;
 };
 
 struct Key {
@@ -190,8 +196,30 @@ struct Run {
     recs.push_back({cls, a, b});
   }
 
-  NormOut norm(int l, bool check) const {
+  // Largest number of workgroup partials a block solve adds itself.
+  static constexpr size_t kDeferMax = 256;
+
+  // Norm of level l's residual written by a pass of writer_tiles workgroups.
+  // The convergence test needs the full in-pass reduction; a norm that no
+  // launch reads is skipped; on small grids the partials are left for the
+  // block solve that reads the norm.
+  NormOut norm(int l, bool check, size_t writer_tiles = (size_t)-1, bool need = true) {
     NormOut n{};
+    Level& L = ws->lv[l];
+    if (check) {
+      n.mode = NORM_FULL;
+      L.npart = 0;
+    } else if (!need) {
+      n.mode = NORM_NONE;
+    } else if (L.dstride > 0 && writer_tiles <= (size_t)L.dstride) {
+      n.mode = NORM_DEFER;
+      n.dpart = L.dpart;
+      n.dstride = L.dstride;
+      L.npart = (int)writer_tiles;
+    } else {
+      n.mode = NORM_FULL;
+      L.npart = 0;
+    }
     n.partials = ws->partials;
     n.counter = ws->counters;
     n.status = ws->status;
@@ -269,7 +297,7 @@ struct Run {
     PassArgs a = pass_args(l);
     a.mode = PASS_RES;
     a.u_out = nullptr;
-    a.norm = norm(l, check);
+    a.norm = norm(l, check, pass_tiles(ws->lv[l].v));
     if (l == 0 && corr0()) {
       // the residual of u is the right-hand side of the next correction problem
       a.r = ws->lv[0].d;
@@ -294,7 +322,9 @@ struct Run {
       b.level0 = 0;
       b.r = L.ezero ? L.d : L.rh;  // while e = 0 its residual is d
     }
-    b.snorm = ws->snorm + (size_t)l * C;
+    b.snorm = L.npart ? L.dpart : ws->snorm + (size_t)l * C;
+    b.npart = L.npart;
+    b.pstride = L.dstride;
     b.contrib = L.contrib;
     b.gamma = o.gamma;
     b.tau = o.tau;
@@ -306,14 +336,16 @@ struct Run {
   }
 
   // The update half of an ORAS iteration.  With rest, it also restricts the
-  // new residual to level l + 1 (the last pre-smoothing of a V-cycle).
-  PassArgs make_update(int l, bool check, bool rest) {
+  // new residual to level l + 1 (the last pre-smoothing of a V-cycle).  need:
+  // some later launch reads the norm this pass writes.
+  PassArgs make_update(int l, bool check, bool rest, bool need = true) {
     Level& L = ws->lv[l];
     const bool corr = l == 0 && corr0();
     if (corr && check) fail(INPAINT_E_DEVICE, "a correction update cannot test convergence");
     PassArgs a = corr ? corr_args(PASS_UPD, PASS_UPD0) : pass_args(l);
     if (!corr) a.mode = PASS_UPD;
-    a.norm = norm(l, check);
+    const size_t tiles = pass_tiles(L.v);
+    if (!rest) a.norm = norm(l, check, tiles, need);
     if (rest) {
       Level& Cl = ws->lv[l + 1];
       a.rest = 1;
@@ -322,7 +354,8 @@ struct Run {
       a.bc = Cl.b;
       a.uc0 = Cl.u[Cl.cur];
       a.rc = Cl.r;
-      a.norm = norm(l + 1, false);
+      // the coarsest grid's solve does not read the norm
+      a.norm = norm(l + 1, false, tiles, need && l + 1 < ws->L - 1);
     }
     if (!corr) L.cur ^= 1;
     ++oras_iters;
@@ -331,7 +364,7 @@ struct Run {
     return a;
   }
 
-  PassArgs make_prolong(int l, int mode, bool check) {
+  PassArgs make_prolong(int l, int mode, bool check, bool need = true) {
     Level& L = ws->lv[l];
     const Level& Lc = ws->lv[l + 1];
     const bool corr = l == 0 && corr0() && mode == PASS_PCORR;
@@ -350,7 +383,7 @@ struct Run {
     a.Hc = Lc.v.H;
     a.Pc = Lc.v.P;
     a.planec = Lc.v.plane;
-    a.norm = norm(l, check);
+    a.norm = norm(l, check, pass_tiles(L.v), need);
     if (!corr) L.cur ^= 1;
     return a;
   }
@@ -397,7 +430,7 @@ struct Run {
     a.bc = Cl.b;
     a.uc = Cl.u[Cl.cur];
     a.rc = Cl.r;
-    a.norm = norm(l + 1, false);
+    a.norm = norm(l + 1, false, pass_tiles(Cl.v), l + 1 < ws->L - 1);
     a.active = ws->active;
     a.rho = ws->rho;
     a.s_rf = sc_res(l);

@@ -40,10 +40,22 @@ struct Sc {
   int rel;
 };
 
-// Per-channel norm reduction of a grid pass.  Every workgroup publishes its
-// partial sum and bumps a per-channel counter; the workgroup that arrives last
-// adds all partials in a fixed order (see reduce_norm in kernels.hip).
+// Per-channel norm reduction of a grid pass.
+//   NORM_FULL:  every workgroup publishes its partial sum and bumps a
+//               per-channel counter; the workgroup that arrives last adds all
+//               partials in a fixed order and writes the norm (and the
+//               convergence test) - needed on large grids and for the test.
+//   NORM_DEFER: every workgroup stores its partial sum at dpart[ch * dstride +
+//               tile] and nothing more; the block solve that consumes the norm
+//               adds the partials itself (cheap on small grids, and it saves
+//               the pass the latency of the cross-workgroup reduction).
+//   NORM_NONE:  nobody reads this norm.
+enum NormMode : int { NORM_FULL = 0, NORM_DEFER = 1, NORM_NONE = 2 };
+
 struct NormOut {
+  int mode;
+  double* dpart;      // NORM_DEFER: [C][dstride]
+  int dstride;
   double* partials;   // [C][ntiles], every entry < 0 (unset) between passes
   unsigned* counter;  // [C][kCounterLines][32]: 64 group counters + 1 total, one
                       // 128-byte line each, all 0 between passes
@@ -117,7 +129,8 @@ struct BlockArgs {
   int prec, level0;
   const uint8_t* c;
   const void* r;          // residual [C][H][P] (float32 on the finest grid)
-  const double* snorm;    // [C] squared global residual norm
+  const double* snorm;    // [C] squared global residual norm, or (npart > 0) the sum of
+  int npart, pstride;     // its npart partials at snorm[ch * pstride + i]
   void* contrib;          // [C][nby*nbx][B][B] weighted corrections D_i v_i (type prec)
   float gamma, tau;
   int maxit;

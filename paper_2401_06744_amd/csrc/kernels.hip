@@ -286,10 +286,19 @@ __device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, 
   constexpr int NW = kPassThreads / kWave;
   __shared__ double red[NW];
   __shared__ int last;
+  if (no.mode == NORM_NONE) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   acc = wave_sum_d(acc);
   if (lane == 0) red[wave] = acc;
   __syncthreads();
+  if (no.mode == NORM_DEFER) {
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NW; ++w) s += red[w];
+      no.dpart[(size_t)ch * no.dstride + tile] = s;
+    }
+    return;
+  }
   double* part = no.partials + (size_t)ch * ntiles;
   unsigned* cnt = no.counter + (size_t)ch * kCounterLines * 32;
   if (threadIdx.x == 0) {
@@ -942,7 +951,18 @@ __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
     rho[k] = (colok && ly < bh) ? r.ld((y0 + ly) * lv.P + x0 + cg.lx) : 0.0f;
   }
   const double frac = (double)bw * (double)bh / ((double)lv.W * (double)lv.H);
-  const float thr = (float)((double)a.tau * a.snorm[ch] * frac);
+  double sn;
+  if (a.npart > 0) {
+    // the norm's partials, one per workgroup of the pass that wrote r, added
+    // in a fixed order
+    const double* p = a.snorm + (size_t)ch * a.pstride;
+    double v = 0.0;
+    for (int i = cg.lane; i < a.npart; i += kWave) v += p[i];
+    sn = wave_sum_d(v);
+  } else {
+    sn = a.snorm[ch];
+  }
+  const float thr = (float)((double)a.tau * sn * frac);
   const int it = cg.solve(rho, v, thr, a.maxit);
   const Fld<TC> out(a.contrib, (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B,
                     a.s_contrib, a.rho, ch);

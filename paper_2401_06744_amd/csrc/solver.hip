@@ -92,7 +92,7 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
     off = round_up(off + n, 256);
     return at;
   };
-  struct Offs { size_t c, b, u0, u1, r, contrib, it, e0, e1, d, rh; };
+  struct Offs { size_t c, b, u0, u1, r, contrib, it, e0, e1, d, rh, dp; };
   std::vector<Offs> lo(ws->L);
   size_t maxtiles = 1;
   for (int l = 0; l < ws->L; ++l) {
@@ -126,6 +126,11 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
     }
     lo[l].contrib = take((size_t)C * v.nbx * v.nby * k.B * k.B * es);
     lo[l].it = take((size_t)2 * C * v.nbx * v.nby * sizeof(int));
+    // deferred norm partials: written by passes over this level or, for the
+    // fused restriction, over the next finer one
+    const size_t wt = std::max(pass_tiles(v), l > 0 ? pass_tiles(ws->lv[l - 1].v) : (size_t)0);
+    ws->lv[l].dstride = wt <= Run::kDeferMax ? (int)wt : 0;
+    lo[l].dp = ws->lv[l].dstride ? take((size_t)C * wt * sizeof(double)) : 0;
     maxtiles = std::max(maxtiles, pass_tiles(v));
   }
   const size_t o_part = take((size_t)C * maxtiles * sizeof(double));
@@ -157,6 +162,7 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
     }
     L.contrib = (float*)(base + lo[l].contrib);
     L.itot = (int*)(base + lo[l].it);
+    L.dpart = L.dstride ? (double*)(base + lo[l].dp) : nullptr;
     L.imax = L.itot + (size_t)C * L.v.nbx * L.v.nby;
   }
   ws->partials = (double*)(base + o_part);
@@ -262,6 +268,7 @@ void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy, bool 
   // staging, input checks and the reference residual ||b - A C f|| (denominator
   // of the relative residual)
   NormOut den = R.norm(0, false);
+  den.mode = NORM_FULL;
   den.out = ws->den;
   den.rho = ws->rho;
   den.inv_n = 1.0 / ((double)ws->key.W * (double)ws->key.H);
@@ -431,7 +438,7 @@ INPAINT_EXPORT int inpaint_rel_res(const float* u, const float* f, const uint8_t
                               u + (size_t)ch * W * H, (size_t)W * sizeof(float),
                               (size_t)W * sizeof(float), H, kind, s));
     L0.cur = 1;
-    R.residual(0, false);
+    R.residual(0, true);  // the full in-pass reduction writes the norm read below
     std::vector<double> sn(channels), den(channels);
     HIPCHK(hipMemcpyAsync(sn.data(), ws->snorm, channels * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(den.data(), ws->den, channels * sizeof(double), hipMemcpyDeviceToHost, s));
