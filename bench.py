@@ -96,7 +96,7 @@ def algorithmic_bytes(cls: str, W: int, H: int, C: int) -> float:
         "prolong": 3 * f4 + f4 / 4 + N,       # read u, mask, coarse e (N/4); write u, r
         "restrict": f4 + 3 * f4 / 4 + N / 4,  # read r, coarse mask; write coarse b, u, r
         "residual": 2 * f4 + N,               # read u, mask; write r
-        "stage": 3 * f4 + 2 * N,              # read f, mask; write b, u, mask (per stage launch)
+        "stage": 2 * f4 + 2 * N,              # read f, mask; write b, mask
         "pyramid": N + f4 + 1.25 * N / 4 + f4 / 4,
         "output": 3 * f4 + N,                 # read u, b, mask; write out
         "coarse": 3 * f4 + N,

@@ -116,9 +116,14 @@ int kernel_class(const Step& st) {
     case S_COARSE: return INPAINT_K_COARSE;
     case S_OUTPUT: return INPAINT_K_OUTPUT;
     case S_PASS:
-      return st.mode == PASS_UPD ? INPAINT_K_UPDATE
-             : st.mode == PASS_RES ? INPAINT_K_RESIDUAL
-                                   : INPAINT_K_PROLONG;
+      switch (st.mode) {
+        case PASS_RES: return INPAINT_K_RESIDUAL;
+        case PASS_UPD:
+        case PASS_UPD0:
+        case PASS_FIN:
+        case PASS_FIN0: return INPAINT_K_UPDATE;
+        default: return INPAINT_K_PROLONG;  // PSOL, PCORR, PCORR0
+      }
     default: return -1;
   }
 }
