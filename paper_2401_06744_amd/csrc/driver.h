@@ -242,8 +242,12 @@ struct Run {
   static Sc sc_one() { return Sc{1.0f, 0}; }
   int prec() const { return ws->key.prec; }
   // The finest grid runs the correction form (16-bit e on a float32 u): the
-  // precision form on a hierarchy of more than one level.
-  bool corr0() const { return ws->key.prec != PREC_F32 && ws->L > 1; }
+  // float16 form on a hierarchy of more than one level.  bfloat16's 8-bit
+  // significand would bound each refinement step's contraction at ~4e-3 (a
+  // third V-cycle at 4 % masks, measured), so in the bfloat16 form the finest
+  // grid keeps float32 fields and only the coarser levels and the block
+  // corrections are 16-bit.
+  bool corr0() const { return ws->key.prec == PREC_F16 && ws->L > 1; }
 
   // Arguments of a pass over the finest grid's correction problem: iterate e,
   // right-hand side d, residual rh, all of the correction type.  The pass runs

@@ -901,7 +901,7 @@ struct BlockCG {
       for (int k = 0; k < R; ++k) pq += p[k] * q[k];
       pq = wave_sum(pq);
       if (!(pq > 0.0f)) break;
-      const float alpha = rr / pq;
+      const float alpha = __fdividef(rr, pq);  // reciprocal + multiply: CG needs no IEEE division
       float rn = 0.0f;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
@@ -910,12 +910,119 @@ struct BlockCG {
         rn += rho[k] * rho[k];
       }
       rn = wave_sum(rn);
-      const float beta = rn / rr;
+      const float beta = __fdividef(rn, rr);
       rr = rn;
 #pragma unroll
       for (int k = 0; k < R; ++k) p[k] = rho[k] + beta * p[k];
       ++it;
     }
+    return it;
+  }
+};
+
+// The same local CG in packed float16 arithmetic, for the 16-bit forms and
+// B = 32: each lane's 16 rows are held as 8 pairs (rows 2j, 2j + 1) in
+// half2 registers, so that one packed instruction works on two pixels.  The
+// right-hand side is normalised to unit norm first (all values then lie well
+// inside the float16 range); dot products accumulate in float32 (dot2), and
+// the solution accumulates in float32.
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ unsigned h2_bits(half2_t v) { return __builtin_bit_cast(unsigned, v); }
+__device__ __forceinline__ half2_t bits_h2(unsigned v) { return __builtin_bit_cast(half2_t, v); }
+
+struct BlockCGh {
+  static constexpr int B = 32, R = 16, J = 8;
+  int lane, g;
+  half2_t hL, hR;   // 1 where the left / right lane belongs to the same block row
+  half2_t dg[J];    // diagonal of A_i (0 at known and outside pixels)
+  half2_t nm[J];    // 1 at unknown pixels of the block, else 0
+
+  __device__ void from(const BlockCG<32>& c) {
+    lane = c.lane;
+    g = c.g;
+    hL = half2_t{(_Float16)c.hasL, (_Float16)c.hasL};
+    hR = half2_t{(_Float16)c.hasR, (_Float16)c.hasR};
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      dg[j] = half2_t{(_Float16)c.dg[2 * j], (_Float16)c.dg[2 * j + 1]};
+      nm[j] = half2_t{(_Float16)(c.nm[2 * j] ? 1.0f : 0.0f), (_Float16)(c.nm[2 * j + 1] ? 1.0f : 0.0f)};
+    }
+  }
+
+  __device__ void apply(const half2_t (&x)[J], half2_t (&q)[J]) const {
+    // the last row of the row group above (high half of x[J-1] of lane - B),
+    // the first row of the one below (low half of x[0] of lane + B)
+    unsigned fa = (unsigned)__shfl((int)h2_bits(x[J - 1]), (lane - B) & 63);
+    unsigned fb = (unsigned)__shfl((int)h2_bits(x[0]), (lane + B) & 63);
+    fa = g > 0 ? fa : 0u;
+    fb = g < 1 ? fb : 0u;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const unsigned xb = h2_bits(x[j]);
+      const half2_t l = bits_h2((unsigned)__builtin_amdgcn_update_dpp(0, (int)xb, 0x138, 0xf, 0xf, true)) * hL;
+      const half2_t r = bits_h2((unsigned)__builtin_amdgcn_update_dpp(0, (int)xb, 0x130, 0xf, 0xf, true)) * hR;
+      // up = (row 2j - 1, row 2j), down = (row 2j + 1, row 2j + 2)
+      const half2_t up = bits_h2(__builtin_amdgcn_alignbit(xb, j > 0 ? h2_bits(x[j - 1]) : fa, 16));
+      const half2_t dn = bits_h2(__builtin_amdgcn_alignbit(j < J - 1 ? h2_bits(x[j + 1]) : fb, xb, 16));
+      q[j] = (dg[j] * x[j] - ((l + r) + (up + dn))) * nm[j];
+    }
+  }
+
+  __device__ static float dot(const half2_t (&a)[J], const half2_t (&b)[J]) {
+    float s = 0.0f;
+#pragma unroll
+    for (int j = 0; j < J; ++j) s = __builtin_amdgcn_fdot2(a[j], b[j], s, false);
+    return wave_sum(s);
+  }
+
+  // CG from v = 0 on A_i v = rho (rho: the block's residual, 0 at known
+  // pixels), stopping when ||rho||^2 <= thr or after maxit iterations; v in
+  // float32.
+  __device__ int solve(const float (&rho)[R], float (&v)[R], float thr, int maxit) const {
+    float rr0 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      v[k] = 0.0f;
+      rr0 += rho[k] * rho[k];
+    }
+    rr0 = wave_sum(rr0);
+    if (!(rr0 > thr) || maxit <= 0) return 0;
+    const float sc = 1.0f / sqrtf(rr0);  // normalise: ||r|| = 1
+    half2_t r[J], p[J], q[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      r[j] = half2_t{(_Float16)(rho[2 * j] * sc), (_Float16)(rho[2 * j + 1] * sc)} * nm[j];
+      p[j] = r[j];
+    }
+    float rr = dot(r, r);
+    const float t = thr * sc * sc;
+    int it = 0;
+    while (it < maxit && rr > t) {
+      apply(p, q);
+      const float pq = dot(p, q);
+      if (!(pq > 0.0f)) break;
+      const float alpha = __fdividef(rr, pq);  // reciprocal + multiply: CG needs no IEEE division
+      const _Float16 ah = (_Float16)alpha;
+      const half2_t a2 = half2_t{ah, ah};
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        v[2 * j] += alpha * (float)p[j].x;
+        v[2 * j + 1] += alpha * (float)p[j].y;
+        r[j] = r[j] - a2 * q[j];
+      }
+      const float rn = dot(r, r);
+      const float beta = __fdividef(rn, rr);
+      rr = rn;
+      const _Float16 bh = (_Float16)beta;
+      const half2_t b2 = half2_t{bh, bh};
+#pragma unroll
+      for (int j = 0; j < J; ++j) p[j] = r[j] + b2 * p[j];
+      ++it;
+    }
+    const float un = 1.0f / sc;
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] *= un;
     return it;
   }
 };
@@ -963,7 +1070,15 @@ __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
     sn = a.snorm[ch];
   }
   const float thr = (float)((double)a.tau * sn * frac);
-  const int it = cg.solve(rho, v, thr, a.maxit);
+  int it;
+  if constexpr (B == 32 && !is_f32<TR>()) {
+    // 16-bit forms: the local solve in packed float16 arithmetic
+    BlockCGh h;
+    h.from(cg);
+    it = h.solve(rho, v, thr, a.maxit);
+  } else {
+    it = cg.solve(rho, v, thr, a.maxit);
+  }
   const Fld<TC> out(a.contrib, (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B,
                     a.s_contrib, a.rho, ch);
   const float wx = pou_weight(cg.lx, lv.nbx, bx, B, lv.o);

@@ -115,7 +115,7 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
     lo[l].u1 = take(f);
     // the precision form's finest grid keeps its residual in 16 bits (d, rh)
     // beside the correction e; the float32 residual is not needed there
-    const bool corr = l == 0 && k.prec != PREC_F32 && ws->L > 1;
+    const bool corr = l == 0 && k.prec == PREC_F16 && ws->L > 1;
     lo[l].r = corr ? 0 : take(f);
     if (corr) {
       const size_t fe = (size_t)C * v.plane * es;
@@ -152,7 +152,7 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
     L.b = (float*)(base + lo[l].b);
     L.u[0] = (float*)(base + lo[l].u0);
     L.u[1] = (float*)(base + lo[l].u1);
-    const bool corr = l == 0 && k.prec != PREC_F32 && ws->L > 1;
+    const bool corr = l == 0 && k.prec == PREC_F16 && ws->L > 1;
     L.r = corr ? nullptr : (float*)(base + lo[l].r);
     if (corr) {
       L.e[0] = base + lo[l].e0;
