@@ -332,6 +332,8 @@ struct Run {
     b.contrib = L.contrib;
     b.gamma = o.gamma;
     b.tau = o.tau;
+    b.inv_o1 = 1.0f / (float)(L.v.o - 1);
+    b.inv_area = 1.0 / ((double)L.v.W * (double)L.v.H);
     b.maxit = o.maxit;
     b.active = ws->active;
     b.itot = o.profile ? L.itot : nullptr;

@@ -139,6 +139,8 @@ struct BlockArgs {
   int* imax;              // and the running maximum; both nullptr to skip
   const float* rho;
   Sc s_r, s_contrib;
+  float inv_o1;           // 1 / (overlap - 1): slope of the partition-of-unity weights
+  double inv_area;        // 1 / (W * H) of the level
 };
 
 struct CoarseArgs {

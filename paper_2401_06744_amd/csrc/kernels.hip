@@ -59,7 +59,7 @@ struct Fld {
       s = inv = 1.0f;
     } else {
       s = scale_of(sc, rho, ch);
-      inv = 1.0f / s;
+      inv = __builtin_amdgcn_rcpf(s);  // the 16-bit value is rounded anyway
     }
   }
   __device__ __forceinline__ float ld(int i) const {
@@ -614,15 +614,17 @@ struct Former {
     } else if constexpr (mode_upd(MODE)) {
       float d = 0.0f;
       if constexpr (mode_contrib(MODE)) {
+        // the (up to) four blocks covering the pixel: all four slots are read,
+        // absent ones at a valid stand-in address and then dropped, so that
+        // the loads issue together rather than behind per-pixel branches
         const BlockAxis ay = block_axis(gy, S, rS, o, nby);
         const int ry1 = ay.b1 * nbx * B * B + ay.l1 * B;
-        const int ry0 = (ay.b1 - 1) * nbx * B * B + (ay.l1 + S) * B;
-        if (ay.h0) {
-          if (c.h0) d += cb.ld(ry0 + c.cx0);
-          d += cb.ld(ry0 + c.cx1);
-        }
-        if (c.h0) d += cb.ld(ry1 + c.cx0);
-        d += cb.ld(ry1 + c.cx1);
+        const int ry0 = ay.h0 ? (ay.b1 - 1) * nbx * B * B + (ay.l1 + S) * B : ry1;
+        const int cx0 = c.h0 ? c.cx0 : c.cx1;
+        const float d00 = cb.ld(ry0 + cx0), d01 = cb.ld(ry0 + c.cx1);
+        const float d10 = cb.ld(ry1 + cx0), d11 = cb.ld(ry1 + c.cx1);
+        // the same additions, in the same order, as adding only the present ones
+        d = (((ay.h0 && c.h0 ? d00 : 0.0f) + (ay.h0 ? d01 : 0.0f)) + (c.h0 ? d10 : 0.0f)) + d11;
       }
       if constexpr (mode_fin(MODE)) d = ea.ld(off) + d;
       if constexpr (mode_zero(MODE))
@@ -636,7 +638,8 @@ struct Former {
       const double p = bilinear(uc.ld(yn * a.Pc + c.xn), uc.ld(yn * a.Pc + c.xf),
                                 uc.ld(yf * a.Pc + c.xn), uc.ld(yf * a.Pc + c.xf));
       if constexpr (MODE == PASS_PSOL) {
-        return known ? bb.ld(off) : (float)p;
+        const float bk = bb.ld(off);  // read unconditionally: no branch around the load
+        return known ? bk : (float)p;
       } else {
         const float u = mode_zero(MODE) ? 0.0f : uin.ld(off);
         return known ? u : (float)((double)u + p);
@@ -672,9 +675,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
     float v[RJ];
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
-      const int ty = g + NG * j;
+      // rows past the halo repeat a valid row (their value is not stored)
+      const int ty = min(g + NG * j, TH - 1);
       const int gy = min(max(y0 - 1 + ty, 0), lv.H - 1);
-      v[j] = ty < TH ? F.value(col, gy) : 0.0f;
+      v[j] = F.value(col, gy);
     }
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
@@ -699,6 +703,22 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   const Fld<TU> ro(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);
   const Fld<TC> rlo(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);  // r_tc
   double acc = 0.0;
+  // masks (and right-hand sides) of this thread's rows, loaded up front from
+  // clamped addresses so that the loads issue together
+  uint8_t mk[RK];
+  float bvv[RK];
+  {
+    const int gxc = min(gx, lv.W - 1);
+#pragma unroll
+    for (int k = 0; k < RK; ++k) mk[k] = a.c[min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc];
+    if (MODE == PASS_RES || !a.solution) {
+#pragma unroll
+      for (int k = 0; k < RK; ++k) bvv[k] = F.bb.ld(min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc);
+    } else {
+#pragma unroll
+      for (int k = 0; k < RK; ++k) bvv[k] = 0.0f;
+    }
+  }
 #pragma unroll
   for (int k = 0; k < RK; ++k) {
     const int ty = g * RK + k;
@@ -710,16 +730,15 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
       const double ud = u;
       const double nb = ((double)t[ty + 1][c] + (double)t[ty + 1][c + 2]) +
                         ((double)t[ty][c + 1] + (double)t[ty + 2][c + 1]);
-      const bool known = a.c[off] != 0;
+      const bool known = mk[k] != 0;
+      const double bv = bvv[k];
       double r;
       if constexpr (MODE == PASS_RES) {
-        const double bv = F.bb.ld(off);
         r = known ? bv - ud : bv - fma(4.0, ud, -nb);
       } else {
         // Every pass but the residual-only one leaves u == b at known pixels, so
         // the residual there is exactly 0; and b is 0 at the unknown pixels of a
         // solution problem, so it is read only for correction problems.
-        const double bv = a.solution ? 0.0 : (double)F.bb.ld(off);
         r = known ? 0.0 : bv - fma(4.0, ud, -nb);
       }
       const float rf = (float)r;
@@ -868,11 +887,17 @@ struct BlockCG {
     const bool colok = lx < bw;
     const float dl = lx > 0 ? 1.0f : (x0 > 0 ? gamma : 0.0f);
     const float dr = lx < bw - 1 ? 1.0f : (x0 + bw < W ? gamma : 0.0f);
+    // every lane loads, from a clamped in-block address, so that the loads
+    // issue together instead of one branch (and one wait) per row
+    const int cx = x0 + min(lx, bw - 1);
+    uint8_t cm[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) cm[k] = c[(size_t)(y0 + min(g * R + k, bh - 1)) * P + cx];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int ly = g * R + k;
       const bool ok = colok && ly < bh;
-      const bool unknown = ok && c[(size_t)(y0 + ly) * P + x0 + lx] == 0;
+      const bool unknown = ok && cm[k] == 0;
       const float du = ly > 0 ? 1.0f : (y0 > 0 ? gamma : 0.0f);
       const float dd = ly < bh - 1 ? 1.0f : (y0 + bh < H ? gamma : 0.0f);
       nm[k] = unknown;
@@ -988,7 +1013,7 @@ struct BlockCGh {
     }
     rr0 = wave_sum(rr0);
     if (!(rr0 > thr) || maxit <= 0) return 0;
-    const float sc = 1.0f / sqrtf(rr0);  // normalise: ||r|| = 1
+    const float sc = __builtin_amdgcn_rsqf(rr0);  // normalise: ||r|| = 1
     half2_t r[J], p[J], q[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -1020,18 +1045,18 @@ struct BlockCGh {
       for (int j = 0; j < J; ++j) p[j] = r[j] + b2 * p[j];
       ++it;
     }
-    const float un = 1.0f / sc;
+    const float un = rr0 * sc;  // ||rho||
 #pragma unroll
     for (int k = 0; k < R; ++k) v[k] *= un;
     return it;
   }
 };
 
-__device__ __forceinline__ float pou_weight(int l, int nb, int k, int B, int o) {
+__device__ __forceinline__ float pou_weight(int l, int nb, int k, int B, int o, float inv_o1) {
   // 1-D partition of unity (Section 3.1): 0 at the outermost overlap pixel,
   // 1 at the innermost, linear in between; 1 away from overlaps.
-  if (k > 0 && l < o) return (float)l / (float)(o - 1);
-  if (k < nb - 1 && l >= B - o) return (float)(B - 1 - l) / (float)(o - 1);
+  if (k > 0 && l < o) return (float)l * inv_o1;
+  if (k < nb - 1 && l >= B - o) return (float)(B - 1 - l) * inv_o1;
   return 1.0f;
 }
 
@@ -1052,12 +1077,17 @@ __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
   float rho[R], v[R];
   const Fld<TR> r(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);
   const bool colok = cg.lx < bw;
+  {
+    const int cx = x0 + min(cg.lx, bw - 1);
 #pragma unroll
-  for (int k = 0; k < R; ++k) {
-    const int ly = cg.g * R + k;
-    rho[k] = (colok && ly < bh) ? r.ld((y0 + ly) * lv.P + x0 + cg.lx) : 0.0f;
+    for (int k = 0; k < R; ++k) rho[k] = r.ld((y0 + min(cg.g * R + k, bh - 1)) * lv.P + cx);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int ly = cg.g * R + k;
+      if (!(colok && ly < bh)) rho[k] = 0.0f;
+    }
   }
-  const double frac = (double)bw * (double)bh / ((double)lv.W * (double)lv.H);
+  const double frac = (double)(bw * bh) * a.inv_area;
   double sn;
   if (a.npart > 0) {
     // the norm's partials, one per workgroup of the pass that wrote r, added
@@ -1081,11 +1111,11 @@ __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
   }
   const Fld<TC> out(a.contrib, (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B,
                     a.s_contrib, a.rho, ch);
-  const float wx = pou_weight(cg.lx, lv.nbx, bx, B, lv.o);
+  const float wx = pou_weight(cg.lx, lv.nbx, bx, B, lv.o, a.inv_o1);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int ly = cg.g * R + k;
-    if (colok && ly < bh) out.st(ly * B + cg.lx, wx * pou_weight(ly, lv.nby, by, B, lv.o) * v[k]);
+    if (colok && ly < bh) out.st(ly * B + cg.lx, wx * pou_weight(ly, lv.nby, by, B, lv.o, a.inv_o1) * v[k]);
   }
   if (a.itot && cg.lane == 0) {
     const size_t ib = (size_t)ch * nblk + bi;
