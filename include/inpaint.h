@@ -20,7 +20,7 @@
  *     memory; host buffers are staged through the library's own device
  *     buffers.  The caller owns f, mask and out; the library never frees them.
  *   - out == f (the same address) is allowed; any other overlap is rejected.
- *     Values of f at unknown pixels are never read and may be NaN.
+ *     Values of f at unknown pixels do not influence the result and may be NaN.
  *   - Relative residual (Section 5.2, "Stopping Criterion"; the start of the
  *     decay is not named in the paper, this library uses the zero-filled start
  *     C f):  rel_res(u) = ||b - A u||_2 / ||b - A C f||_2, in float64 on the

@@ -191,12 +191,10 @@ __device__ __forceinline__ void mask_body(const MaskArgs& a, unsigned lin) {
   const int X = (int)(lin % gxn) * 64 + (threadIdx.x & 63);
   const int Y = (int)(lin / gxn) * 4 + (threadIdx.x >> 6);
   if (X >= cl.W || Y >= cl.H) return;
-  uint8_t m = 0;
-  for (int dy = 0; dy < 2; ++dy)
-    for (int dx = 0; dx < 2; ++dx) {
-      const int y = 2 * Y + dy, x = 2 * X + dx;
-      if (y < fl.H && x < fl.W) m |= cf[(size_t)y * fl.P + x];
-    }
+  // children past the image edge read the existing child (max pool unchanged)
+  const int x0 = 2 * X, y0 = 2 * Y, x1 = min(x0 + 1, fl.W - 1), y1 = min(y0 + 1, fl.H - 1);
+  const uint8_t m = (cf[(size_t)y0 * fl.P + x0] | cf[(size_t)y0 * fl.P + x1]) |
+                    (cf[(size_t)y1 * fl.P + x0] | cf[(size_t)y1 * fl.P + x1]);
   cc[(size_t)Y * cl.P + X] = m ? 1 : 0;
 }
 
@@ -453,14 +451,31 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, unsigned lin) {
   __shared__ uint8_t kn[kTileH + 2][kTileW + 2];
   const float* fc = f + (size_t)ch * Pf * H;
   bool bad = false, any = false;
-  for (int i = threadIdx.x; i < (kTileH + 2) * (kTileW + 2); i += kPassThreads) {
+  // every element of the tile and its halo: mask and f are read from clamped
+  // in-image addresses up front (f at unknown pixels is read but never used)
+  constexpr int NE = (kTileH + 2) * (kTileW + 2);
+  constexpr int NJ = (NE + kPassThreads - 1) / kPassThreads;
+  uint8_t km[NJ];
+  float fv[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int i = min((int)threadIdx.x + j * kPassThreads, NE - 1);
+    const int ty = i / (kTileW + 2), tx = i - ty * (kTileW + 2);
+    const int gx = min(max(x0 + tx - 1, 0), W - 1), gy = min(max(y0 + ty - 1, 0), H - 1);
+    km[j] = mask[(size_t)gy * W + gx];
+    fv[j] = fc[(size_t)gy * Pf + gx];
+  }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int i = (int)threadIdx.x + j * kPassThreads;
+    if (i >= NE) break;
     const int ty = i / (kTileW + 2), tx = i - ty * (kTileW + 2);
     const int gx = x0 + tx - 1, gy = y0 + ty - 1;
     float v = 0.0f;
     uint8_t k = 0;
     if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-      k = mask[(size_t)gy * W + gx] != 0;
-      if (k) v = fc[(size_t)gy * Pf + gx];
+      k = km[j] != 0;
+      v = k ? fv[j] : 0.0f;
       const bool inner = tx >= 1 && tx <= kTileW && ty >= 1 && ty <= kTileH;
       if (inner) {
         bad |= k && !isfinite(v);
@@ -1138,15 +1153,27 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs& a, unsigned lin) {
   float u[R], bb[R], known[R];
   const Fld<T> bp(a.b, (size_t)ch * lv.plane, a.s_b, a.rho, ch);
   const Fld<T> up(a.u, (size_t)ch * lv.plane, a.s_u, a.rho, ch);
+  // loads from clamped in-block addresses, issued together
+  uint8_t cm[R];
+  float uu[R];
+  {
+    const int cx = min(cg.lx, lv.W - 1);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int o = min(cg.g * R + k, lv.H - 1) * lv.P + cx;
+      cm[k] = a.c[o];
+      bb[k] = bp.ld(o);
+      uu[k] = a.init ? 0.0f : up.ld(o);
+    }
+  }
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int ly = cg.g * R + k;
     const bool ok = colok && ly < lv.H;
-    const int o = ly * lv.P + cg.lx;
-    const bool kn = ok && a.c[o] != 0;
+    const bool kn = ok && cm[k] != 0;
     known[k] = kn ? 1.0f : 0.0f;
-    bb[k] = ok ? bp.ld(o) : 0.0f;
-    u[k] = ok ? (a.init ? (kn ? bb[k] : 0.0f) : up.ld(o)) : 0.0f;
+    bb[k] = ok ? bb[k] : 0.0f;
+    u[k] = ok ? (a.init ? (kn ? bb[k] : 0.0f) : uu[k]) : 0.0f;
   }
   // residual r = b - A u (float64 arithmetic), 0 at known pixels
   float rho[R];
