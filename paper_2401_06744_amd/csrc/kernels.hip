@@ -162,20 +162,35 @@ __host__ __device__ __forceinline__ unsigned px_groups(int W, int H) {
 // staging and output
 // ---------------------------------------------------------------------------
 
+// 64 x 16 pixels of one channel per workgroup, four rows per thread, loads
+// issued together from clamped addresses.
+constexpr int kOutRows = 4;
 __device__ __forceinline__ void output_body(const OutputArgs& a, unsigned lin) {
   const LevelView& lv = a.lv;
-  const unsigned gxn = (unsigned)((lv.W + 63) / 64), per = px_groups(lv.W, lv.H);
+  const unsigned gxn = (unsigned)((lv.W + 63) / 64);
+  const unsigned per = gxn * (unsigned)((lv.H + 4 * kOutRows - 1) / (4 * kOutRows));
   const int ch = lin / per;
   const unsigned q = lin - (unsigned)ch * per;
   const int x = (int)(q % gxn) * 64 + (threadIdx.x & 63);
-  const int y = (int)(q / gxn) * 4 + (threadIdx.x >> 6);
-  if (x >= lv.W || y >= lv.H) return;
+  const int y0 = (int)(q / gxn) * 4 * kOutRows + (threadIdx.x >> 6);
+  if (x >= lv.W) return;
   // select without indexing the argument array dynamically (that would place
   // the arguments in scratch memory)
   const float* u = ch == 0 ? a.u[0] : ch == 1 ? a.u[1] : ch == 2 ? a.u[2] : a.u[3];
-  const size_t o = (size_t)y * lv.P + x;
-  const size_t src = (size_t)ch * lv.plane + o;
-  a.out[(size_t)ch * a.Pout * lv.H + (size_t)y * a.Pout + x] = a.c[o] ? a.b[src] : u[src];
+  uint8_t k[kOutRows];
+  float bv[kOutRows], uv[kOutRows];
+#pragma unroll
+  for (int r = 0; r < kOutRows; ++r) {
+    const size_t o = (size_t)min(y0 + 4 * r, lv.H - 1) * lv.P + x;
+    k[r] = a.c[o];
+    bv[r] = a.b[(size_t)ch * lv.plane + o];
+    uv[r] = u[(size_t)ch * lv.plane + o];
+  }
+#pragma unroll
+  for (int r = 0; r < kOutRows; ++r) {
+    const int y = y0 + 4 * r;
+    if (y < lv.H) a.out[(size_t)ch * a.Pout * lv.H + (size_t)y * a.Pout + x] = k[r] ? bv[r] : uv[r];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -576,6 +591,10 @@ __host__ __device__ constexpr bool mode_zero(int m) { return m == PASS_UPD0 || m
 __host__ __device__ constexpr bool mode_fin(int m) { return m == PASS_FIN || m == PASS_FIN0; }
 __host__ __device__ constexpr bool mode_rest(int m) { return m == PASS_UPD || m == PASS_UPD0; }
 
+// Coarse patch of a 64 x 32 tile's prolongation: the tile and its 1-pixel halo
+// span at most 34 coarse columns and 18 coarse rows.
+constexpr int kCoarseW = kTileW / 2 + 2, kCoarseH = kTileH / 2 + 2;
+
 template <int MODE, class TU, class TC>
 struct Former {
   const PassArgs& a;
@@ -584,6 +603,10 @@ struct Former {
   Fld<TC> ea;       // added correction (UPD with e_add)
   int S, o, B, nbx, nby;
   float rS;
+  // PSOL/PCORR: the coarse cells the tile's bilinear stencils touch, staged
+  // in LDS ([kCoarseH][kCoarseW] from coarse (cx0, cy0))
+  const float* cpatch = nullptr;
+  int cx0 = 0, cy0 = 0;
 
   __device__ Former(const PassArgs& a_, int ch)
       : a(a_),
@@ -622,6 +645,10 @@ struct Former {
   }
 
   __device__ float value(const Col& c, int gy) const {
+    bool known;
+    return value(c, gy, known);
+  }
+  __device__ float value(const Col& c, int gy, bool& known_out) const {
     const LevelView& lv = a.lv;
     const int off = gy * lv.P + c.gx;
     if constexpr (MODE == PASS_RES) {
@@ -648,10 +675,12 @@ struct Former {
         return uin.ld(off) + d;
     } else {
       const bool known = a.c[off] != 0;
+      known_out = known;
       int yn, yf;
       prolong_axis(gy, a.Hc, yn, yf);
-      const double p = bilinear(uc.ld(yn * a.Pc + c.xn), uc.ld(yn * a.Pc + c.xf),
-                                uc.ld(yf * a.Pc + c.xn), uc.ld(yf * a.Pc + c.xf));
+      const float* rn = cpatch + (yn - cy0) * kCoarseW - cx0;
+      const float* rf = cpatch + (yf - cy0) * kCoarseW - cx0;
+      const double p = bilinear(rn[c.xn], rn[c.xf], rf[c.xn], rf[c.xf]);
       if constexpr (MODE == PASS_PSOL) {
         const float bk = bb.ld(off);  // read unconditionally: no branch around the load
         return known ? bk : (float)p;
@@ -683,22 +712,42 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   const LevelView& lv = a.lv;
   const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
   __shared__ float t[TH][TW];
-  const Former<MODE, TU, TC> F(a, ch);
+  constexpr bool kProlong = MODE == PASS_PSOL || mode_pcorr(MODE);
+  __shared__ uint8_t kt[kProlong ? TH : 1][kProlong ? TW : 1];  // known flags (prolongations)
+  __shared__ float cp[kProlong ? kCoarseH : 1][kProlong ? kCoarseW : 1];
+  Former<MODE, TU, TC> F(a, ch);
   const int c = threadIdx.x & (kTileW - 1), g = threadIdx.x / kTileW;
+  if constexpr (kProlong) {
+    // coarse cells (x0/2 - 1 .. x0/2 + 32) x (y0/2 - 1 .. y0/2 + 16), clamped
+    const int cx0 = max((x0 >> 1) - 1, 0), cy0 = max((y0 >> 1) - 1, 0);
+    for (int i = threadIdx.x; i < kCoarseW * kCoarseH; i += kPassThreads) {
+      const int py = i / kCoarseW, px = i - py * kCoarseW;
+      const int X = min(cx0 + px, a.Wc - 1), Y = min(cy0 + py, a.Hc - 1);
+      cp[py][px] = F.uc.ld(Y * a.Pc + X);
+    }
+    F.cpatch = &cp[0][0];
+    F.cx0 = cx0;
+    F.cy0 = cy0;
+    __syncthreads();
+  }
   {
     const auto col = F.col(min(x0 + c, lv.W - 1));
     float v[RJ];
+    bool kv[RJ];
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
       // rows past the halo repeat a valid row (their value is not stored)
       const int ty = min(g + NG * j, TH - 1);
       const int gy = min(max(y0 - 1 + ty, 0), lv.H - 1);
-      v[j] = F.value(col, gy);
+      v[j] = F.value(col, gy, kv[j]);
     }
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
       const int ty = g + NG * j;
-      if (ty < TH) t[ty][c + 1] = v[j];
+      if (ty < TH) {
+        t[ty][c + 1] = v[j];
+        if constexpr (kProlong) kt[ty][c + 1] = kv[j];
+      }
     }
   }
   if (threadIdx.x < 2 * TH) {
@@ -724,8 +773,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   float bvv[RK];
   {
     const int gxc = min(gx, lv.W - 1);
+    if constexpr (kProlong) {
 #pragma unroll
-    for (int k = 0; k < RK; ++k) mk[k] = a.c[min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc];
+      for (int k = 0; k < RK; ++k) mk[k] = kt[g * RK + k + 1][c + 1];
+    } else {
+#pragma unroll
+      for (int k = 0; k < RK; ++k) mk[k] = a.c[min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc];
+    }
     if (MODE == PASS_RES || !a.solution) {
 #pragma unroll
       for (int k = 0; k < RK; ++k) bvv[k] = F.bb.ld(min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc);
@@ -1339,7 +1393,10 @@ unsigned work_block(const BlockArgs& a, int C) {
   return (unsigned)a.lv.nbx * (unsigned)a.lv.nby * (unsigned)C;
 }
 unsigned work_coarse(const CoarseArgs&, int C) { return (unsigned)C; }
-unsigned work_output(const OutputArgs& a) { return px_groups(a.lv.W, a.lv.H) * (unsigned)a.C; }
+unsigned work_output(const OutputArgs& a) {
+  return (unsigned)((a.lv.W + 63) / 64) * (unsigned)((a.lv.H + 4 * kOutRows - 1) / (4 * kOutRows)) *
+         (unsigned)a.C;
+}
 
 // ---------------------------------------------------------------------------
 // single-problem launchers
