@@ -1329,15 +1329,19 @@ __global__ void __launch_bounds__(kPassThreads) k_restrict_b(const RestrictArgs*
   restrict_body<TF, TC>(a, lin);
 }
 
-// Five wavefronts per SIMD (at most 96 registers) hide the latency of the
-// cross-lane operations better than the four a free register allocation gives.
+// Five wavefronts per SIMD (at most 96 registers; six for the packed float16
+// solve, 80 registers) hide the latency of the cross-lane operations and the
+// block loads better than the four a free register allocation gives.
+template <class TR>
+constexpr int block_waves() { return is_f32<TR>() ? 5 : 6; }
+
 template <int B, class TR, class TC>
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(5, 8)))
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(block_waves<TR>(), 8)))
 k_block_solve(BlockArgs a) {
   block_body<B, TR, TC>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 template <int B, class TR, class TC>
-__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(5, 8)))
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(block_waves<TR>(), 8)))
 k_block_b(const BlockArgs* __restrict__ args,
                                                    const unsigned* __restrict__ start, int n) {
   INPAINT_BATCH_LOOKUP(BlockArgs)
