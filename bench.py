@@ -292,13 +292,21 @@ def main() -> int:
     roof["traffic"] = measured_traffic(dom)
     log(f"timed and profiled legs done: {fps:.1f} frames/s")
 
-    if args.calibrate_copy:
-        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    # achievable bandwidth of a plain device copy (secondary denominator), and
+    # the calibration launch for the counter runs
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3 if args.calibrate_copy else 1):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    roof["copy_GBps"] = round(2 * COPY_BYTES * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del src, dst
 
     # ---- accuracy of the last output (device rel-res; oracle error below)
     rr = binding.inpaint_rel_res(od, fd, md)
