@@ -106,6 +106,16 @@ __device__ __forceinline__ float lane_from_right(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
                                                                0x130, 0xf, 0xf, true));
 }
+// DPP row_shr:1 / row_shl:1 -- inside each row of 16 lanes, lane i receives
+// lane i-1 (i+1); the first (last) lane of a row receives 0.
+__device__ __forceinline__ float row_from_left(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x111, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float row_from_right(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x101, 0xf, 0xf, true));
+}
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
@@ -114,6 +124,11 @@ __device__ __forceinline__ float dpp_f(float v) {
 __device__ __forceinline__ float readlane_f(float v, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }
+
+// Smallest normal float32.  The CG coefficients use the hardware reciprocal,
+// which flushes subnormal inputs (1/x becomes inf): a local CG stops once its
+// squared residual norm or p.Ap leaves the normal range.
+constexpr float kTiny = 1.17549435e-38f;
 
 // Sum over the 64 lanes of a fully active wavefront, in a fixed order; the
 // result is uniform.  quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror and
@@ -988,14 +1003,14 @@ struct BlockCG {
     }
     rr = wave_sum(rr);
     int it = 0;
-    while (it < maxit && rr > thr) {
+    while (it < maxit && rr > thr && rr >= kTiny) {
       apply(p, q);
       float pq = 0.0f;
 #pragma unroll
       for (int k = 0; k < R; ++k) pq += p[k] * q[k];
       pq = wave_sum(pq);
-      if (!(pq > 0.0f)) break;
-      const float alpha = __fdividef(rr, pq);  // reciprocal + multiply: CG needs no IEEE division
+      if (!(pq >= kTiny)) break;
+      const float alpha = rr * __builtin_amdgcn_rcpf(pq);  // CG needs no IEEE division
       float rn = 0.0f;
 #pragma unroll
       for (int k = 0; k < R; ++k) {
@@ -1004,10 +1019,127 @@ struct BlockCG {
         rn += rho[k] * rho[k];
       }
       rn = wave_sum(rn);
-      const float beta = __fdividef(rn, rr);
+      const float beta = rn * __builtin_amdgcn_rcpf(rr);
       rr = rn;
 #pragma unroll
       for (int k = 0; k < R; ++k) p[k] = rho[k] + beta * p[k];
+      ++it;
+    }
+    return it;
+  }
+};
+
+// The local CG for B = 32 in float32 with two columns per lane: lane = c + 16 g
+// holds columns 2c and 2c + 1 (index h = 0, 1) of rows 8g .. 8g + 7.  One
+// block row then spans one 16-lane DPP row, whose shifts bring in 0 at the
+// block's left and right edges by themselves, and both horizontal neighbours
+// of a pixel cost one shifted add.  Arithmetic is that of BlockCG (same
+// stencil evaluation order); only the order of the dot-product sums differs.
+struct BlockCG2 {
+  static constexpr int B = 32, C = 16, G = 4, R = 8;
+  int lane, c, g;
+  float dg[2][R];  // diagonal of A_i, 0 at known and outside pixels
+  bool nm[2][R];   // unknown pixel of the block
+
+  __device__ void apply(const float (&x)[2][R], float (&q)[2][R]) const {
+    float ua = __shfl(x[0][R - 1], (lane - C) & 63), ub = __shfl(x[1][R - 1], (lane - C) & 63);
+    float da = __shfl(x[0][0], (lane + C) & 63), db = __shfl(x[1][0], (lane + C) & 63);
+    ua = g > 0 ? ua : 0.0f;
+    ub = g > 0 ? ub : 0.0f;
+    da = g < G - 1 ? da : 0.0f;
+    db = g < G - 1 ? db : 0.0f;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      // left and right of column 2c: column 2c + 1 of the lane to the left, own column 2c + 1
+      const float ha = row_from_left(x[1][k]) + x[1][k];
+      // left and right of column 2c + 1: own column 2c, column 2c of the lane to the right
+      const float hb = x[0][k] + row_from_right(x[0][k]);
+      const float upa = k > 0 ? x[0][k - 1] : ua, dna = k < R - 1 ? x[0][k + 1] : da;
+      const float upb = k > 0 ? x[1][k - 1] : ub, dnb = k < R - 1 ? x[1][k + 1] : db;
+      q[0][k] = nm[0][k] ? dg[0][k] * x[0][k] - (ha + (upa + dna)) : 0.0f;
+      q[1][k] = nm[1][k] ? dg[1][k] * x[1][k] - (hb + (upb + dnb)) : 0.0f;
+    }
+  }
+
+  // Lane geometry and diagonal for a block at (x0, y0) of size bw x bh on a
+  // W x H level, as BlockCG::setup.
+  __device__ void setup(int x0, int y0, int bw, int bh, int W, int H, float gamma,
+                        const uint8_t* __restrict__ m, int P) {
+    lane = threadIdx.x & 63;
+    c = lane & (C - 1);
+    g = lane / C;
+    float dl[2], dr[2];
+    int cx[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int lx = 2 * c + h;
+      dl[h] = lx > 0 ? 1.0f : (x0 > 0 ? gamma : 0.0f);
+      dr[h] = lx < bw - 1 ? 1.0f : (x0 + bw < W ? gamma : 0.0f);
+      cx[h] = x0 + min(lx, bw - 1);
+    }
+    uint8_t cm[2][R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const size_t row = (size_t)(y0 + min(g * R + k, bh - 1)) * P;
+      cm[0][k] = m[row + cx[0]];
+      cm[1][k] = m[row + cx[1]];
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int ly = g * R + k;
+      const float du = ly > 0 ? 1.0f : (y0 > 0 ? gamma : 0.0f);
+      const float dd = ly < bh - 1 ? 1.0f : (y0 + bh < H ? gamma : 0.0f);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool unknown = 2 * c + h < bw && ly < bh && cm[h][k] == 0;
+        nm[h][k] = unknown;
+        dg[h][k] = unknown ? (dl[h] + dr[h]) + (du + dd) : 0.0f;
+      }
+    }
+  }
+
+  // Plain CG from v = 0 on A_i v = rho (rho is overwritten by the final
+  // residual).  Stops when ||rho||^2 <= thr or after maxit iterations.
+  __device__ int solve(float (&rho)[2][R], float (&v)[2][R], float thr, int maxit) const {
+    float p[2][R], q[2][R];
+    float rr = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        rho[h][k] = nm[h][k] ? rho[h][k] : 0.0f;
+        v[h][k] = 0.0f;
+        p[h][k] = rho[h][k];
+        rr += rho[h][k] * rho[h][k];
+      }
+    rr = wave_sum(rr);
+    int it = 0;
+    while (it < maxit && rr > thr && rr >= kTiny) {
+      apply(p, q);
+      float pq = 0.0f;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < R; ++k) pq += p[h][k] * q[h][k];
+      pq = wave_sum(pq);
+      if (!(pq >= kTiny)) break;
+      const float alpha = rr * __builtin_amdgcn_rcpf(pq);
+      float rn = 0.0f;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          v[h][k] += alpha * p[h][k];
+          rho[h][k] -= alpha * q[h][k];
+          rn += rho[h][k] * rho[h][k];
+        }
+      rn = wave_sum(rn);
+      const float beta = rn * __builtin_amdgcn_rcpf(rr);
+      rr = rn;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < R; ++k) asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(p[h][k]) : "v"(beta), "v"(rho[h][k]));
       ++it;
     }
     return it;
@@ -1092,11 +1224,11 @@ struct BlockCGh {
     float rr = dot(r, r);
     const float t = thr * sc * sc;
     int it = 0;
-    while (it < maxit && rr > t) {
+    while (it < maxit && rr > t && rr >= kTiny) {
       apply(p, q);
       const float pq = dot(p, q);
-      if (!(pq > 0.0f)) break;
-      const float alpha = __fdividef(rr, pq);  // reciprocal + multiply: CG needs no IEEE division
+      if (!(pq >= kTiny)) break;
+      const float alpha = rr * __builtin_amdgcn_rcpf(pq);  // CG needs no IEEE division
       const _Float16 ah = (_Float16)alpha;
       const half2_t a2 = half2_t{ah, ah};
 #pragma unroll
@@ -1106,7 +1238,7 @@ struct BlockCGh {
         r[j] = r[j] - a2 * q[j];
       }
       const float rn = dot(r, r);
-      const float beta = __fdividef(rn, rr);
+      const float beta = rn * __builtin_amdgcn_rcpf(rr);
       rr = rn;
       const _Float16 bh = (_Float16)beta;
       const half2_t b2 = half2_t{bh, bh};
@@ -1129,12 +1261,81 @@ __device__ __forceinline__ float pou_weight(int l, int nb, int k, int B, int o, 
   return 1.0f;
 }
 
+// Threshold of the local CG stop (Section 3.2): tau * ||r||^2 * |Omega_i| / N.
+__device__ __forceinline__ float block_threshold(const BlockArgs& a, int ch, int bw, int bh) {
+  const double frac = (double)(bw * bh) * a.inv_area;
+  double sn;
+  if (a.npart > 0) {
+    // the norm's partials, one per workgroup of the pass that wrote r, added
+    // in a fixed order
+    const double* p = a.snorm + (size_t)ch * a.pstride;
+    double v = 0.0;
+    for (int i = (int)(threadIdx.x & 63); i < a.npart; i += kWave) v += p[i];
+    sn = wave_sum_d(v);
+  } else {
+    sn = a.snorm[ch];
+  }
+  return (float)((double)a.tau * sn * frac);
+}
+
+__device__ __forceinline__ void count_iterations(const BlockArgs& a, size_t ib, int it) {
+  if (a.itot && (threadIdx.x & 63) == 0) {
+    a.itot[ib] += it;
+    a.imax[ib] = max(a.imax[ib], it);
+  }
+}
+
+// float32 local problems of side 32: BlockCG2 lane layout
+template <class TC>
+__device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsigned bi, unsigned nblk) {
+  constexpr int B = 32, R = BlockCG2::R;
+  const LevelView& lv = a.lv;
+  const int S = B - lv.o;
+  const int bx = bi % lv.nbx, by = bi / lv.nbx;
+  const int x0 = bx * S, y0 = by * S;
+  const int bw = min(B, lv.W - x0), bh = min(B, lv.H - y0);
+  BlockCG2 cg;
+  cg.setup(x0, y0, bw, bh, lv.W, lv.H, a.gamma, a.c, lv.P);
+  float rho[2][R], v[2][R];
+  const float* r = (const float*)a.r + (size_t)ch * lv.plane;
+  {
+    const int cx0 = x0 + min(2 * cg.c, bw - 1), cx1 = x0 + min(2 * cg.c + 1, bw - 1);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const size_t row = (size_t)(y0 + min(cg.g * R + k, bh - 1)) * lv.P;
+      rho[0][k] = r[row + cx0];
+      rho[1][k] = r[row + cx1];
+    }
+  }
+  const float thr = block_threshold(a, ch, bw, bh);
+  const int it = cg.solve(rho, v, thr, a.maxit);  // zeroes rho outside the block
+  const Fld<TC> out(a.contrib, (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B,
+                    a.s_contrib, a.rho, ch);
+  float wx[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) wx[h] = pou_weight(2 * cg.c + h, lv.nbx, bx, B, lv.o, a.inv_o1);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int ly = cg.g * R + k;
+    if (ly >= bh) continue;
+    const float wy = pou_weight(ly, lv.nby, by, B, lv.o, a.inv_o1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+      if (2 * cg.c + h < bw) out.st(ly * B + 2 * cg.c + h, wx[h] * wy * v[h][k]);
+  }
+  count_iterations(a, (size_t)ch * nblk + bi, it);
+}
+
 template <int B, class TR, class TC>
 __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
   const unsigned nblk = (unsigned)a.lv.nbx * (unsigned)a.lv.nby;
   const int ch = lin / nblk;
   const unsigned bi = lin - (unsigned)ch * nblk;
   if (a.active && !a.active[ch]) return;
+  if constexpr (B == 32 && is_f32<TR>()) {
+    block_body_f32<TC>(a, ch, bi, nblk);
+    return;
+  }
   const LevelView& lv = a.lv;
   const int S = B - lv.o;
   const int bx = bi % lv.nbx, by = bi / lv.nbx;
@@ -1156,19 +1357,7 @@ __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
       if (!(colok && ly < bh)) rho[k] = 0.0f;
     }
   }
-  const double frac = (double)(bw * bh) * a.inv_area;
-  double sn;
-  if (a.npart > 0) {
-    // the norm's partials, one per workgroup of the pass that wrote r, added
-    // in a fixed order
-    const double* p = a.snorm + (size_t)ch * a.pstride;
-    double v = 0.0;
-    for (int i = cg.lane; i < a.npart; i += kWave) v += p[i];
-    sn = wave_sum_d(v);
-  } else {
-    sn = a.snorm[ch];
-  }
-  const float thr = (float)((double)a.tau * sn * frac);
+  const float thr = block_threshold(a, ch, bw, bh);
   int it;
   if constexpr (B == 32 && !is_f32<TR>()) {
     // 16-bit forms: the local solve in packed float16 arithmetic
@@ -1186,11 +1375,7 @@ __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
     const int ly = cg.g * R + k;
     if (colok && ly < bh) out.st(ly * B + cg.lx, wx * pou_weight(ly, lv.nby, by, B, lv.o, a.inv_o1) * v[k]);
   }
-  if (a.itot && cg.lane == 0) {
-    const size_t ib = (size_t)ch * nblk + bi;
-    a.itot[ib] += it;
-    a.imax[ib] = max(a.imax[ib], it);
-  }
+  count_iterations(a, (size_t)ch * nblk + bi, it);
 }
 
 // The coarsest grid is a single block.  Residual in float64 from u, then CG,

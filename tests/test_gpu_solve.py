@@ -60,6 +60,20 @@ def test_ragged_sizes(W, H, C, dens, seed):
     _check(out, f, m)
 
 
+def test_local_residuals_reaching_subnormal_range():
+    """Regression: in this problem (659x467 RGB, 9.4 % mask) some local CG
+    solves drive their squared residual norm below the smallest normal
+    float32; a hardware reciprocal of such a value is inf and used to turn the
+    whole solve into NaN."""
+    f, m = synth.batched_problems()[60]
+    assert f.shape == (3, 467, 659)
+    out, st, stats = _solve(f, m)
+    assert st == binding.OK and np.isfinite(out).all()
+    assert np.array_equal(out[:, m != 0], f[:, m != 0])
+    rr = oracle.rel_res(out.astype(np.float64), f.astype(np.float64), m)
+    assert np.all(rr <= TOL), rr
+
+
 def test_single_pixel_and_all_known():
     f = synth.plain_image(40, 30, seed=3)
     m = np.zeros((30, 40), np.uint8)
