@@ -43,6 +43,17 @@ constexpr bool is_f32() {
   return std::is_same<T, float>::value;
 }
 
+// Global-memory pointers.  The field pointers arrive inside argument structs
+// read from memory, so the compiler cannot tell them from LDS pointers and
+// would use flat instructions: 64-bit address arithmetic per access, and a
+// wait for LDS results that also waits for every outstanding HBM access.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> glb(T* p) {
+  return (gptr<T>)p;
+}
+
 __device__ __forceinline__ float scale_of(Sc s, const float* rho, int ch) {
   return s.rel ? s.f * rho[ch] : s.f;
 }
@@ -51,10 +62,10 @@ __device__ __forceinline__ float scale_of(Sc s, const float* rho, int ch) {
 // undoing and applying the channel's scale for 16-bit types.
 template <class T>
 struct Fld {
-  T* p;
+  gptr<T> p;
   float s, inv;
   __device__ __forceinline__ Fld(const void* base, size_t chan_off, Sc sc, const float* rho, int ch) {
-    p = base ? (T*)base + chan_off : nullptr;  // optional fields may be absent
+    p = base ? glb((T*)base + chan_off) : nullptr;  // optional fields may be absent
     if constexpr (is_f32<T>()) {
       s = inv = 1.0f;
     } else {
@@ -191,20 +202,20 @@ __device__ __forceinline__ void output_body(const OutputArgs& a, unsigned lin) {
   if (x >= lv.W) return;
   // select without indexing the argument array dynamically (that would place
   // the arguments in scratch memory)
-  const float* u = ch == 0 ? a.u[0] : ch == 1 ? a.u[1] : ch == 2 ? a.u[2] : a.u[3];
+  const gptr<const float> u = glb(ch == 0 ? a.u[0] : ch == 1 ? a.u[1] : ch == 2 ? a.u[2] : a.u[3]);
   uint8_t k[kOutRows];
   float bv[kOutRows], uv[kOutRows];
 #pragma unroll
   for (int r = 0; r < kOutRows; ++r) {
     const size_t o = (size_t)min(y0 + 4 * r, lv.H - 1) * lv.P + x;
-    k[r] = a.c[o];
-    bv[r] = a.b[(size_t)ch * lv.plane + o];
+    k[r] = glb(a.c)[o];
+    bv[r] = glb(a.b)[(size_t)ch * lv.plane + o];
     uv[r] = u[(size_t)ch * lv.plane + o];
   }
 #pragma unroll
   for (int r = 0; r < kOutRows; ++r) {
     const int y = y0 + 4 * r;
-    if (y < lv.H) a.out[(size_t)ch * a.Pout * lv.H + (size_t)y * a.Pout + x] = k[r] ? bv[r] : uv[r];
+    if (y < lv.H) glb(a.out)[(size_t)ch * a.Pout * lv.H + (size_t)y * a.Pout + x] = k[r] ? bv[r] : uv[r];
   }
 }
 
@@ -463,13 +474,13 @@ __global__ void k_fill(double* p, size_t n, double v) {
 // relative residual):  at an unknown pixel it is the sum of the known
 // neighbours' values, at a known pixel 0.
 __device__ __forceinline__ void stage_body(const StageArgs& a, unsigned lin) {
-  const float* __restrict__ f = a.f;
-  const uint8_t* __restrict__ mask = a.mask;
+  const gptr<const float> f = glb(a.f);
+  const gptr<const uint8_t> mask = glb(a.mask);
   const int W = a.W, H = a.H, Pf = a.Pf;
   const LevelView& lv = a.lv;
-  uint8_t* __restrict__ c = a.c;
-  float* __restrict__ b = a.b;
-  float* __restrict__ u = a.u;
+  const gptr<uint8_t> c = glb(a.c);
+  const gptr<float> b = glb(a.b);
+  const gptr<float> u = a.u ? glb(a.u) : nullptr;
   int* __restrict__ status = a.status;
   const NormOut& den = a.den;
   const unsigned tiles_x = (unsigned)((lv.W + kTileW - 1) / kTileW);
@@ -479,7 +490,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, unsigned lin) {
   const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
   __shared__ float t[kTileH + 2][kTileW + 2];
   __shared__ uint8_t kn[kTileH + 2][kTileW + 2];
-  const float* fc = f + (size_t)ch * Pf * H;
+  const gptr<const float> fc = f + (size_t)ch * Pf * H;
   bool bad = false, any = false;
   // every element of the tile and its halo: mask and f are read from clamped
   // in-image addresses up front (f at unknown pixels is read but never used)
@@ -689,7 +700,7 @@ struct Former {
       else
         return uin.ld(off) + d;
     } else {
-      const bool known = a.c[off] != 0;
+      const bool known = glb(a.c)[off] != 0;
       known_out = known;
       int yn, yf;
       prolong_axis(gy, a.Hc, yn, yf);
@@ -793,7 +804,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
       for (int k = 0; k < RK; ++k) mk[k] = kt[g * RK + k + 1][c + 1];
     } else {
 #pragma unroll
-      for (int k = 0; k < RK; ++k) mk[k] = a.c[min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc];
+      for (int k = 0; k < RK; ++k) mk[k] = glb(a.c)[min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc];
     }
     if (MODE == PASS_RES || !a.solution) {
 #pragma unroll
@@ -976,7 +987,7 @@ struct BlockCG {
     const int cx = x0 + min(lx, bw - 1);
     uint8_t cm[R];
 #pragma unroll
-    for (int k = 0; k < R; ++k) cm[k] = c[(size_t)(y0 + min(g * R + k, bh - 1)) * P + cx];
+    for (int k = 0; k < R; ++k) cm[k] = glb(c)[(size_t)(y0 + min(g * R + k, bh - 1)) * P + cx];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int ly = g * R + k;
@@ -1078,11 +1089,12 @@ struct BlockCG2 {
       cx[h] = x0 + min(lx, bw - 1);
     }
     uint8_t cm[2][R];
+    const gptr<const uint8_t> mg = glb(m);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const size_t row = (size_t)(y0 + min(g * R + k, bh - 1)) * P;
-      cm[0][k] = m[row + cx[0]];
-      cm[1][k] = m[row + cx[1]];
+      const unsigned row = (unsigned)(y0 + min(g * R + k, bh - 1)) * (unsigned)P;
+      cm[0][k] = mg[row + cx[0]];
+      cm[1][k] = mg[row + cx[1]];
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -1136,10 +1148,13 @@ struct BlockCG2 {
       rn = wave_sum(rn);
       const float beta = rn * __builtin_amdgcn_rcpf(rr);
       rr = rn;
+      // p = p * beta + rho in place: written as C++ the compiler copies rho,
+      // accumulates with v_fmac and copies the result back (32 extra moves)
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int k = 0; k < R; ++k) asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(p[h][k]) : "v"(beta), "v"(rho[h][k]));
+        for (int k = 0; k < R; ++k)
+          asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(p[h][k]) : "v"(beta), "v"(rho[h][k]));
       ++it;
     }
     return it;
@@ -1297,12 +1312,12 @@ __device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsig
   BlockCG2 cg;
   cg.setup(x0, y0, bw, bh, lv.W, lv.H, a.gamma, a.c, lv.P);
   float rho[2][R], v[2][R];
-  const float* r = (const float*)a.r + (size_t)ch * lv.plane;
+  const gptr<const float> r = glb((const float*)a.r + (size_t)ch * lv.plane);
   {
-    const int cx0 = x0 + min(2 * cg.c, bw - 1), cx1 = x0 + min(2 * cg.c + 1, bw - 1);
+    const unsigned cx0 = x0 + min(2 * cg.c, bw - 1), cx1 = x0 + min(2 * cg.c + 1, bw - 1);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const size_t row = (size_t)(y0 + min(cg.g * R + k, bh - 1)) * lv.P;
+      const unsigned row = (unsigned)(y0 + min(cg.g * R + k, bh - 1)) * (unsigned)lv.P;
       rho[0][k] = r[row + cx0];
       rho[1][k] = r[row + cx1];
     }
@@ -1400,7 +1415,7 @@ __device__ __forceinline__ void coarse_body(const CoarseArgs& a, unsigned lin) {
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const int o = min(cg.g * R + k, lv.H - 1) * lv.P + cx;
-      cm[k] = a.c[o];
+      cm[k] = glb(a.c)[o];
       bb[k] = bp.ld(o);
       uu[k] = a.init ? 0.0f : up.ld(o);
     }
