@@ -700,21 +700,39 @@ struct Former {
       else
         return uin.ld(off) + d;
     } else {
-      const bool known = glb(a.c)[off] != 0;
-      known_out = known;
-      int yn, yf;
-      prolong_axis(gy, a.Hc, yn, yf);
-      const float* rn = cpatch + (yn - cy0) * kCoarseW - cx0;
-      const float* rf = cpatch + (yf - cy0) * kCoarseW - cx0;
-      const double p = bilinear(rn[c.xn], rn[c.xf], rf[c.xn], rf[c.xf]);
-      if constexpr (MODE == PASS_PSOL) {
-        const float bk = bb.ld(off);  // read unconditionally: no branch around the load
-        return known ? bk : (float)p;
-      } else {
-        const float u = mode_zero(MODE) ? 0.0f : uin.ld(off);
-        return known ? u : (float)((double)u + p);
-      }
+      const Pre pr = pre(c, gy);
+      known_out = pr.known;
+      return fin(c, gy, pr);
     }
+  }
+
+  // Prolongations in two steps: the pixel's global inputs (known flag, and
+  // its known value (PSOL) or iterate (PCORR)), then the value from the
+  // coarse patch in LDS.
+  struct Pre {
+    bool known;
+    float x;
+  };
+  __device__ Pre pre(const Col& c, int gy) const {
+    const int off = gy * a.lv.P + c.gx;
+    Pre p;
+    p.known = glb(a.c)[off] != 0;
+    if constexpr (MODE == PASS_PSOL)
+      p.x = bb.ld(off);  // read unconditionally: no branch around the load
+    else
+      p.x = mode_zero(MODE) ? 0.0f : uin.ld(off);
+    return p;
+  }
+  __device__ float fin(const Col& c, int gy, const Pre& pr) const {
+    int yn, yf;
+    prolong_axis(gy, a.Hc, yn, yf);
+    const float* rn = cpatch + (yn - cy0) * kCoarseW - cx0;
+    const float* rf = cpatch + (yf - cy0) * kCoarseW - cx0;
+    const double p = bilinear(rn[c.xn], rn[c.xf], rf[c.xn], rf[c.xf]);
+    if constexpr (MODE == PASS_PSOL)
+      return pr.known ? pr.x : (float)p;
+    else
+      return pr.known ? pr.x : (float)((double)pr.x + p);
   }
 };
 
@@ -743,29 +761,66 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   __shared__ float cp[kProlong ? kCoarseH : 1][kProlong ? kCoarseW : 1];
   Former<MODE, TU, TC> F(a, ch);
   const int c = threadIdx.x & (kTileW - 1), g = threadIdx.x / kTileW;
-  if constexpr (kProlong) {
-    // coarse cells (x0/2 - 1 .. x0/2 + 32) x (y0/2 - 1 .. y0/2 + 16), clamped
-    const int cx0 = max((x0 >> 1) - 1, 0), cy0 = max((y0 >> 1) - 1, 0);
-    for (int i = threadIdx.x; i < kCoarseW * kCoarseH; i += kPassThreads) {
-      const int py = i / kCoarseW, px = i - py * kCoarseW;
-      const int X = min(cx0 + px, a.Wc - 1), Y = min(cy0 + py, a.Hc - 1);
-      cp[py][px] = F.uc.ld(Y * a.Pc + X);
+  constexpr int RK = kTileH / NG;  // phase-2 rows per thread
+  const int gx = x0 + c;
+  const int gxc = min(gx, lv.W - 1);
+  // Phase-2 inputs that do not depend on phase 1 (masks and right-hand sides
+  // of this thread's rows) are loaded first, from clamped addresses, so that
+  // their latency overlaps phase 1's.
+  // (The final pass of the correction form holds more phase-1 state and
+  // loads them for phase 2 instead.)
+  uint8_t mk[RK];
+  float bvv[RK];
+  if constexpr (!kProlong && !mode_fin(MODE)) {
+#pragma unroll
+    for (int k = 0; k < RK; ++k) mk[k] = glb(a.c)[min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc];
+  }
+  if constexpr (!mode_fin(MODE)) {
+    if (MODE == PASS_RES || !a.solution) {
+#pragma unroll
+      for (int k = 0; k < RK; ++k) bvv[k] = F.bb.ld(min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc);
+    } else {
+#pragma unroll
+      for (int k = 0; k < RK; ++k) bvv[k] = 0.0f;
     }
-    F.cpatch = &cp[0][0];
-    F.cx0 = cx0;
-    F.cy0 = cy0;
-    __syncthreads();
   }
   {
     const auto col = F.col(min(x0 + c, lv.W - 1));
     float v[RJ];
     bool kv[RJ];
+    if constexpr (kProlong) {
+      // the rows' own inputs first, then the coarse patch
+      typename Former<MODE, TU, TC>::Pre pr[RJ];
 #pragma unroll
-    for (int j = 0; j < RJ; ++j) {
-      // rows past the halo repeat a valid row (their value is not stored)
-      const int ty = min(g + NG * j, TH - 1);
-      const int gy = min(max(y0 - 1 + ty, 0), lv.H - 1);
-      v[j] = F.value(col, gy, kv[j]);
+      for (int j = 0; j < RJ; ++j) {
+        const int ty = min(g + NG * j, TH - 1);
+        pr[j] = F.pre(col, min(max(y0 - 1 + ty, 0), lv.H - 1));
+      }
+      // coarse cells (x0/2 - 1 .. x0/2 + 32) x (y0/2 - 1 .. y0/2 + 16), clamped
+      const int cx0 = max((x0 >> 1) - 1, 0), cy0 = max((y0 >> 1) - 1, 0);
+      for (int i = threadIdx.x; i < kCoarseW * kCoarseH; i += kPassThreads) {
+        const int py = i / kCoarseW, px = i - py * kCoarseW;
+        const int X = min(cx0 + px, a.Wc - 1), Y = min(cy0 + py, a.Hc - 1);
+        cp[py][px] = F.uc.ld(Y * a.Pc + X);
+      }
+      F.cpatch = &cp[0][0];
+      F.cx0 = cx0;
+      F.cy0 = cy0;
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < RJ; ++j) {
+        const int ty = min(g + NG * j, TH - 1);
+        v[j] = F.fin(col, min(max(y0 - 1 + ty, 0), lv.H - 1), pr[j]);
+        kv[j] = pr[j].known;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < RJ; ++j) {
+        // rows past the halo repeat a valid row (their value is not stored)
+        const int ty = min(g + NG * j, TH - 1);
+        const int gy = min(max(y0 - 1 + ty, 0), lv.H - 1);
+        v[j] = F.value(col, gy, kv[j]);
+      }
     }
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
@@ -784,8 +839,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
     t[ty][side == 0 ? 0 : TW - 1] = F.value(F.col(gx), gy);
   }
   __syncthreads();
-  constexpr int RK = kTileH / NG;  // phase-2 rows per thread
-  const int gx = x0 + c;
   const bool colin = gx < lv.W;
   const bool rest = mode_rest(MODE) && a.rest;
   __shared__ float rt[mode_rest(MODE) ? kTileH : 1][mode_rest(MODE) ? kTileW : 1];
@@ -793,20 +846,15 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   const Fld<TU> ro(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);
   const Fld<TC> rlo(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);  // r_tc
   double acc = 0.0;
-  // masks (and right-hand sides) of this thread's rows, loaded up front from
-  // clamped addresses so that the loads issue together
-  uint8_t mk[RK];
-  float bvv[RK];
-  {
-    const int gxc = min(gx, lv.W - 1);
-    if constexpr (kProlong) {
+  if constexpr (kProlong) {
+    // the known flags were read in phase 1
 #pragma unroll
-      for (int k = 0; k < RK; ++k) mk[k] = kt[g * RK + k + 1][c + 1];
-    } else {
+    for (int k = 0; k < RK; ++k) mk[k] = kt[g * RK + k + 1][c + 1];
+  }
+  if constexpr (mode_fin(MODE)) {
 #pragma unroll
-      for (int k = 0; k < RK; ++k) mk[k] = glb(a.c)[min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc];
-    }
-    if (MODE == PASS_RES || !a.solution) {
+    for (int k = 0; k < RK; ++k) mk[k] = glb(a.c)[min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc];
+    if (!a.solution) {
 #pragma unroll
       for (int k = 0; k < RK; ++k) bvv[k] = F.bb.ld(min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc);
     } else {
@@ -814,6 +862,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
       for (int k = 0; k < RK; ++k) bvv[k] = 0.0f;
     }
   }
+
 #pragma unroll
   for (int k = 0; k < RK; ++k) {
     const int ty = g * RK + k;
