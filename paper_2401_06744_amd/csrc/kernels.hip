@@ -1210,96 +1210,119 @@ struct BlockCG2 {
   }
 };
 
-// The same local CG in packed float16 arithmetic, for the 16-bit forms and
-// B = 32: each lane's 16 rows are held as 8 pairs (rows 2j, 2j + 1) in
-// half2 registers, so that one packed instruction works on two pixels.  The
-// right-hand side is normalised to unit norm first (all values then lie well
-// inside the float16 range); dot products accumulate in float32 (dot2), and
-// the solution accumulates in float32.
+// The local CG of the 16-bit forms (B = 32) in packed float16 arithmetic,
+// in the BlockCG2 lane layout: a lane's two pixels of one row form one half2
+// (low half: column 2c), so that one packed instruction works on both and
+// vertical neighbours are whole registers of the same lane.  The right-hand
+// side arrives normalised to unit norm (all values well inside the float16
+// range); dot products accumulate in float32 (dot2) and so does the
+// solution.
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ unsigned h2_bits(half2_t v) { return __builtin_bit_cast(unsigned, v); }
 __device__ __forceinline__ half2_t bits_h2(unsigned v) { return __builtin_bit_cast(half2_t, v); }
 
-struct BlockCGh {
-  static constexpr int B = 32, R = 16, J = 8;
-  int lane, g;
-  half2_t hL, hR;   // 1 where the left / right lane belongs to the same block row
-  half2_t dg[J];    // diagonal of A_i (0 at known and outside pixels)
-  half2_t nm[J];    // 1 at unknown pixels of the block, else 0
+struct BlockCGh2 {
+  static constexpr int B = 32, C = 16, G = 4, R = 8;
+  int lane, c, g;
+  half2_t dg[R];  // diagonal of A_i (0 at known and outside pixels)
+  half2_t nm[R];  // 1 at unknown pixels of the block, else 0
 
-  __device__ void from(const BlockCG<32>& c) {
-    lane = c.lane;
-    g = c.g;
-    hL = half2_t{(_Float16)c.hasL, (_Float16)c.hasL};
-    hR = half2_t{(_Float16)c.hasR, (_Float16)c.hasR};
+  // as BlockCG2::setup
+  __device__ void setup(int x0, int y0, int bw, int bh, int W, int H, float gamma,
+                        const uint8_t* __restrict__ m, int P) {
+    lane = threadIdx.x & 63;
+    c = lane & (C - 1);
+    g = lane / C;
+    float dl[2], dr[2];
+    int cx[2];
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      dg[j] = half2_t{(_Float16)c.dg[2 * j], (_Float16)c.dg[2 * j + 1]};
-      nm[j] = half2_t{(_Float16)(c.nm[2 * j] ? 1.0f : 0.0f), (_Float16)(c.nm[2 * j + 1] ? 1.0f : 0.0f)};
+    for (int h = 0; h < 2; ++h) {
+      const int lx = 2 * c + h;
+      dl[h] = lx > 0 ? 1.0f : (x0 > 0 ? gamma : 0.0f);
+      dr[h] = lx < bw - 1 ? 1.0f : (x0 + bw < W ? gamma : 0.0f);
+      cx[h] = x0 + min(lx, bw - 1);
+    }
+    uint8_t cm[2][R];
+    const gptr<const uint8_t> mg = glb(m);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const unsigned row = (unsigned)(y0 + min(g * R + k, bh - 1)) * (unsigned)P;
+      cm[0][k] = mg[row + cx[0]];
+      cm[1][k] = mg[row + cx[1]];
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int ly = g * R + k;
+      const float du = ly > 0 ? 1.0f : (y0 > 0 ? gamma : 0.0f);
+      const float dd = ly < bh - 1 ? 1.0f : (y0 + bh < H ? gamma : 0.0f);
+      float d[2], n[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool unknown = 2 * c + h < bw && ly < bh && cm[h][k] == 0;
+        n[h] = unknown ? 1.0f : 0.0f;
+        d[h] = unknown ? (dl[h] + dr[h]) + (du + dd) : 0.0f;
+      }
+      dg[k] = half2_t{(_Float16)d[0], (_Float16)d[1]};
+      nm[k] = half2_t{(_Float16)n[0], (_Float16)n[1]};
     }
   }
 
-  __device__ void apply(const half2_t (&x)[J], half2_t (&q)[J]) const {
-    // the last row of the row group above (high half of x[J-1] of lane - B),
-    // the first row of the one below (low half of x[0] of lane + B)
-    unsigned fa = (unsigned)__shfl((int)h2_bits(x[J - 1]), (lane - B) & 63);
-    unsigned fb = (unsigned)__shfl((int)h2_bits(x[0]), (lane + B) & 63);
+  __device__ void apply(const half2_t (&x)[R], half2_t (&q)[R]) const {
+    unsigned fa = (unsigned)__shfl((int)h2_bits(x[R - 1]), (lane - C) & 63);
+    unsigned fb = (unsigned)__shfl((int)h2_bits(x[0]), (lane + C) & 63);
     fa = g > 0 ? fa : 0u;
-    fb = g < 1 ? fb : 0u;
+    fb = g < G - 1 ? fb : 0u;
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const unsigned xb = h2_bits(x[j]);
-      const half2_t l = bits_h2((unsigned)__builtin_amdgcn_update_dpp(0, (int)xb, 0x138, 0xf, 0xf, true)) * hL;
-      const half2_t r = bits_h2((unsigned)__builtin_amdgcn_update_dpp(0, (int)xb, 0x130, 0xf, 0xf, true)) * hR;
-      // up = (row 2j - 1, row 2j), down = (row 2j + 1, row 2j + 2)
-      const half2_t up = bits_h2(__builtin_amdgcn_alignbit(xb, j > 0 ? h2_bits(x[j - 1]) : fa, 16));
-      const half2_t dn = bits_h2(__builtin_amdgcn_alignbit(j < J - 1 ? h2_bits(x[j + 1]) : fb, xb, 16));
-      q[j] = (dg[j] * x[j] - ((l + r) + (up + dn))) * nm[j];
+    for (int k = 0; k < R; ++k) {
+      const unsigned xb = h2_bits(x[k]);
+      // row shifts: the pair of the lane to the left / right (0 past the block row)
+      const unsigned lp = (unsigned)__builtin_amdgcn_update_dpp(0, (int)xb, 0x111, 0xf, 0xf, true);
+      const unsigned rp = (unsigned)__builtin_amdgcn_update_dpp(0, (int)xb, 0x101, 0xf, 0xf, true);
+      // (left of column 2c, right of column 2c + 1) + (right of 2c, left of 2c + 1)
+      const half2_t h = bits_h2(__builtin_amdgcn_alignbit(rp, lp, 16)) +
+                        __builtin_shufflevector(x[k], x[k], 1, 0);
+      const half2_t up = k > 0 ? x[k - 1] : bits_h2(fa);
+      const half2_t dn = k < R - 1 ? x[k + 1] : bits_h2(fb);
+      q[k] = (dg[k] * x[k] - (h + (up + dn))) * nm[k];
     }
   }
 
-  __device__ static float dot(const half2_t (&a)[J], const half2_t (&b)[J]) {
+  __device__ static float dot(const half2_t (&a)[R], const half2_t (&b)[R]) {
     float s = 0.0f;
 #pragma unroll
-    for (int j = 0; j < J; ++j) s = __builtin_amdgcn_fdot2(a[j], b[j], s, false);
+    for (int k = 0; k < R; ++k) s = __builtin_amdgcn_fdot2(a[k], b[k], s, false);
     return wave_sum(s);
   }
 
-  // CG from v = 0 on A_i v = rho (rho: the block's residual, 0 at known
-  // pixels), stopping when ||rho||^2 <= thr or after maxit iterations; v in
-  // float32.
-  __device__ int solve(const float (&rho)[R], float (&v)[R], float thr, int maxit) const {
-    float rr0 = 0.0f;
+  // CG from v = 0 on A_i v = r for a unit-norm r (0 at known pixels),
+  // stopping when ||r||^2 <= t or after maxit iterations; v in float32.
+  __device__ int solve(half2_t (&r)[R], float (&v)[2][R], float t, int maxit) const {
+    half2_t p[R], q[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      v[k] = 0.0f;
-      rr0 += rho[k] * rho[k];
-    }
-    rr0 = wave_sum(rr0);
-    if (!(rr0 > thr) || maxit <= 0) return 0;
-    const float sc = __builtin_amdgcn_rsqf(rr0);  // normalise: ||r|| = 1
-    half2_t r[J], p[J], q[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-      r[j] = half2_t{(_Float16)(rho[2 * j] * sc), (_Float16)(rho[2 * j + 1] * sc)} * nm[j];
-      p[j] = r[j];
+      v[0][k] = 0.0f;
+      v[1][k] = 0.0f;
+      p[k] = r[k];
     }
     float rr = dot(r, r);
-    const float t = thr * sc * sc;
     int it = 0;
-    while (it < maxit && rr > t && rr >= kTiny) {
+    bool stop = false;
+    // one exit only: a breakdown (p.Ap not positive and normal) takes a zero
+    // step and ends the loop at its head (a second exit makes the compiler
+    // copy the float32 solution registers every iteration)
+    while (!stop && it < maxit && rr > t && rr >= kTiny) {
       apply(p, q);
       const float pq = dot(p, q);
-      if (!(pq >= kTiny)) break;
-      const float alpha = rr * __builtin_amdgcn_rcpf(pq);  // CG needs no IEEE division
+      stop = !(pq >= kTiny);
+      const float alpha = stop ? 0.0f : rr * __builtin_amdgcn_rcpf(pq);  // no IEEE division
       const _Float16 ah = (_Float16)alpha;
       const half2_t a2 = half2_t{ah, ah};
 #pragma unroll
-      for (int j = 0; j < J; ++j) {
-        v[2 * j] += alpha * (float)p[j].x;
-        v[2 * j + 1] += alpha * (float)p[j].y;
-        r[j] = r[j] - a2 * q[j];
+      for (int k = 0; k < R; ++k) {
+        v[0][k] += alpha * (float)p[k].x;
+        v[1][k] += alpha * (float)p[k].y;
+        r[k] = r[k] - a2 * q[k];
       }
       const float rn = dot(r, r);
       const float beta = rn * __builtin_amdgcn_rcpf(rr);
@@ -1307,12 +1330,9 @@ struct BlockCGh {
       const _Float16 bh = (_Float16)beta;
       const half2_t b2 = half2_t{bh, bh};
 #pragma unroll
-      for (int j = 0; j < J; ++j) p[j] = r[j] + b2 * p[j];
-      ++it;
+      for (int k = 0; k < R; ++k) p[k] = r[k] + b2 * p[k];
+      it += stop ? 0 : 1;
     }
-    const float un = rr0 * sc;  // ||rho||
-#pragma unroll
-    for (int k = 0; k < R; ++k) v[k] *= un;
     return it;
   }
 };
@@ -1390,14 +1410,95 @@ __device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsig
   count_iterations(a, (size_t)ch * nblk + bi, it);
 }
 
+// 16-bit local problems of side 32: BlockCGh2 in packed float16
+template <class TR, class TC>
+__device__ __forceinline__ void block_body_h(const BlockArgs& a, int ch, unsigned bi, unsigned nblk) {
+  constexpr int B = 32, R = BlockCGh2::R;
+  const LevelView& lv = a.lv;
+  const int S = B - lv.o;
+  const int bx = bi % lv.nbx, by = bi / lv.nbx;
+  const int x0 = bx * S, y0 = by * S;
+  const int bw = min(B, lv.W - x0), bh = min(B, lv.H - y0);
+  BlockCGh2 cg;
+  cg.setup(x0, y0, bw, bh, lv.W, lv.H, a.gamma, a.c, lv.P);
+  // the stored (scaled) residual values; the residual is rs * stored
+  const Fld<TR> rf(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);
+  float raw[2][R];
+  {
+    const gptr<const TR> r = glb((const TR*)a.r + (size_t)ch * lv.plane);
+    const unsigned cx0 = x0 + min(2 * cg.c, bw - 1), cx1 = x0 + min(2 * cg.c + 1, bw - 1);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const unsigned row = (unsigned)(y0 + min(cg.g * R + k, bh - 1)) * (unsigned)lv.P;
+      raw[0][k] = (float)r[row + cx0];
+      raw[1][k] = (float)r[row + cx1];
+    }
+  }
+  float ss = 0.0f;
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const bool rowin = cg.g * R + k < bh;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      raw[h][k] = rowin && 2 * cg.c + h < bw ? raw[h][k] : 0.0f;  // outside the block
+      ss += raw[h][k] * raw[h][k];
+    }
+  }
+  ss = wave_sum(ss);  // ||r||^2 / rs^2
+  const float thr = block_threshold(a, ch, bw, bh);
+  const float rs2 = rf.s * rf.s;
+  float v[2][R];
+  int it = 0;
+  float un = 0.0f;  // ||r||; stays 0 (and v = 0) when the block needs no solve
+  if (ss * rs2 > thr && a.maxit > 0) {
+    const float sc = __builtin_amdgcn_rsqf(ss);  // unit-norm right-hand side
+    half2_t rh[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) rh[k] = half2_t{(_Float16)(raw[0][k] * sc), (_Float16)(raw[1][k] * sc)};
+    it = cg.solve(rh, v, thr * sc * sc / rs2, a.maxit);
+    un = ss * sc * rf.s;
+  } else {
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[0][k] = v[1][k] = 0.0f;
+  }
+  // contribution = PoU weights * ||r|| * v in the correction type and scale;
+  // a lane's two pixels of a row are adjacent: one 32-bit store
+  static_assert(sizeof(TC) == 2, "16-bit corrections");
+  const Fld<TC> out(a.contrib, (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B,
+                    a.s_contrib, a.rho, ch);
+  float wx[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    wx[h] = pou_weight(2 * cg.c + h, lv.nbx, bx, B, lv.o, a.inv_o1) * (un * out.inv);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int ly = cg.g * R + k;
+    if (ly >= bh) continue;
+    const float wy = pou_weight(ly, lv.nby, by, B, lv.o, a.inv_o1);
+    const TC c0 = (TC)(wx[0] * wy * v[0][k]), c1 = (TC)(wx[1] * wy * v[1][k]);
+    const int e = ly * B + 2 * cg.c;
+    if (2 * cg.c + 1 < bw) {
+      const unsigned pair = (unsigned)__builtin_bit_cast(unsigned short, c0) |
+                            ((unsigned)__builtin_bit_cast(unsigned short, c1) << 16);
+      *(gptr<unsigned>)(out.p + e) = pair;
+    } else if (2 * cg.c < bw) {
+      out.p[e] = c0;
+    }
+  }
+  count_iterations(a, (size_t)ch * nblk + bi, it);
+}
+
 template <int B, class TR, class TC>
 __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
   const unsigned nblk = (unsigned)a.lv.nbx * (unsigned)a.lv.nby;
   const int ch = lin / nblk;
   const unsigned bi = lin - (unsigned)ch * nblk;
   if (a.active && !a.active[ch]) return;
-  if constexpr (B == 32 && is_f32<TR>()) {
-    block_body_f32<TC>(a, ch, bi, nblk);
+  if constexpr (B == 32) {
+    if constexpr (is_f32<TR>())
+      block_body_f32<TC>(a, ch, bi, nblk);
+    else
+      block_body_h<TR, TC>(a, ch, bi, nblk);
     return;
   }
   const LevelView& lv = a.lv;
@@ -1422,15 +1523,7 @@ __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
     }
   }
   const float thr = block_threshold(a, ch, bw, bh);
-  int it;
-  if constexpr (B == 32 && !is_f32<TR>()) {
-    // 16-bit forms: the local solve in packed float16 arithmetic
-    BlockCGh h;
-    h.from(cg);
-    it = h.solve(rho, v, thr, a.maxit);
-  } else {
-    it = cg.solve(rho, v, thr, a.maxit);
-  }
+  const int it = cg.solve(rho, v, thr, a.maxit);
   const Fld<TC> out(a.contrib, (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B,
                     a.s_contrib, a.rho, ch);
   const float wx = pou_weight(cg.lx, lv.nbx, bx, B, lv.o, a.inv_o1);
