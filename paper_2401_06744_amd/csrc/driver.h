@@ -197,7 +197,7 @@ struct Run {
   }
 
   // Largest number of workgroup partials a block solve adds itself.
-  static constexpr size_t kDeferMax = 256;
+  static constexpr size_t kDeferMax = kDeferParts;
 
   // Norm of level l's residual written by a pass of writer_tiles workgroups.
   // The convergence test needs the full in-pass reduction; a norm that no

@@ -16,6 +16,8 @@ constexpr int kMaxLevels = 24;
 // Tile of the grid passes: 64 columns x 32 rows, 256 threads (8 rows each).
 constexpr int kTileW = 64;
 constexpr int kTileH = 32;
+// Most norm partials a block solve adds up itself (deferred norms).
+constexpr int kDeferParts = 256;
 
 // Storage precision of the correction fields (the weighted block corrections
 // on every level and every field of the coarser levels).  The finest grid's

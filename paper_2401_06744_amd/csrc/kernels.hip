@@ -54,6 +54,13 @@ __device__ __forceinline__ gptr<T> glb(T* p) {
   return (gptr<T>)p;
 }
 
+// Whether channel ch still iterates (no flags: always).  Read as early as
+// possible and tested late, so that the flag's round trip overlaps the
+// kernel's first loads instead of preceding them.
+__device__ __forceinline__ bool channel_active(const int* active, int ch) {
+  return !active || glb(active)[ch] != 0;
+}
+
 __device__ __forceinline__ float scale_of(Sc s, const float* rho, int ch) {
   return s.rel ? s.f * rho[ch] : s.f;
 }
@@ -752,7 +759,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   const unsigned ntiles = tiles_x * (unsigned)((a.lv.H + kTileH - 1) / kTileH);
   const int ch = lin / ntiles;
   const unsigned tile = lin - (unsigned)ch * ntiles;
-  if (a.active && !a.active[ch]) return;
+  const bool act = channel_active(a.active, ch);  // tested after the first loads
   const LevelView& lv = a.lv;
   const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
   __shared__ float t[TH][TW];
@@ -796,6 +803,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
         const int ty = min(g + NG * j, TH - 1);
         pr[j] = F.pre(col, min(max(y0 - 1 + ty, 0), lv.H - 1));
       }
+      if (!act) return;  // the whole workgroup: one channel
       // coarse cells (x0/2 - 1 .. x0/2 + 32) x (y0/2 - 1 .. y0/2 + 16), clamped
       const int cx0 = max((x0 >> 1) - 1, 0), cy0 = max((y0 >> 1) - 1, 0);
       for (int i = threadIdx.x; i < kCoarseW * kCoarseH; i += kPassThreads) {
@@ -821,6 +829,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
         const int gy = min(max(y0 - 1 + ty, 0), lv.H - 1);
         v[j] = F.value(col, gy, kv[j]);
       }
+      if (!act) return;  // the whole workgroup: one channel
     }
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
@@ -949,7 +958,7 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs& a, unsigned li
   const unsigned ntiles = tiles_x * (unsigned)((a.cl.H + kTileH - 1) / kTileH);
   const int ch = lin / ntiles;
   const unsigned tile = lin - (unsigned)ch * ntiles;
-  if (a.active && !a.active[ch]) return;
+  if (!channel_active(a.active, ch)) return;
   const LevelView& fl = a.fl;
   const LevelView& cl = a.cl;
   const int X = (int)(tile % tiles_x) * kTileW + (threadIdx.x & 63);
@@ -1041,7 +1050,7 @@ struct BlockCG {
     for (int k = 0; k < R; ++k) {
       const int ly = g * R + k;
       const bool ok = colok && ly < bh;
-      const bool unknown = ok && cm[k] == 0;
+      const bool unknown = ok & (cm[k] == 0);  // no short circuit: keeps every load unconditional
       const float du = ly > 0 ? 1.0f : (y0 > 0 ? gamma : 0.0f);
       const float dd = ly < bh - 1 ? 1.0f : (y0 + bh < H ? gamma : 0.0f);
       nm[k] = unknown;
@@ -1152,7 +1161,7 @@ struct BlockCG2 {
       const float dd = ly < bh - 1 ? 1.0f : (y0 + bh < H ? gamma : 0.0f);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const bool unknown = 2 * c + h < bw && ly < bh && cm[h][k] == 0;
+        const bool unknown = (2 * c + h < bw) & (ly < bh) & (cm[h][k] == 0);  // loads stay unconditional
         nm[h][k] = unknown;
         dg[h][k] = unknown ? (dl[h] + dr[h]) + (du + dd) : 0.0f;
       }
@@ -1259,7 +1268,7 @@ struct BlockCGh2 {
       float d[2], n[2];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const bool unknown = 2 * c + h < bw && ly < bh && cm[h][k] == 0;
+        const bool unknown = (2 * c + h < bw) & (ly < bh) & (cm[h][k] == 0);  // loads stay unconditional
         n[h] = unknown ? 1.0f : 0.0f;
         d[h] = unknown ? (dl[h] + dr[h]) + (du + dd) : 0.0f;
       }
@@ -1352,12 +1361,18 @@ __device__ __forceinline__ float block_threshold(const BlockArgs& a, int ch, int
   if (a.npart > 0) {
     // the norm's partials, one per workgroup of the pass that wrote r, added
     // in a fixed order
-    const double* p = a.snorm + (size_t)ch * a.pstride;
+    // (at most kDeferParts of them: every load is issued before the first add)
+    const gptr<const double> p = glb(a.snorm + (size_t)ch * a.pstride);
+    const int lane = (int)(threadIdx.x & 63);
+    double pv[kDeferParts / kWave];
+#pragma unroll
+    for (int j = 0; j < kDeferParts / kWave; ++j) pv[j] = p[min(lane + j * kWave, a.npart - 1)];
     double v = 0.0;
-    for (int i = (int)(threadIdx.x & 63); i < a.npart; i += kWave) v += p[i];
+#pragma unroll
+    for (int j = 0; j < kDeferParts / kWave; ++j) v += lane + j * kWave < a.npart ? pv[j] : 0.0;
     sn = wave_sum_d(v);
   } else {
-    sn = a.snorm[ch];
+    sn = glb(a.snorm)[ch];
   }
   return (float)((double)a.tau * sn * frac);
 }
@@ -1371,7 +1386,8 @@ __device__ __forceinline__ void count_iterations(const BlockArgs& a, size_t ib, 
 
 // float32 local problems of side 32: BlockCG2 lane layout
 template <class TC>
-__device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsigned bi, unsigned nblk) {
+__device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsigned bi, unsigned nblk,
+                                               bool act) {
   constexpr int B = 32, R = BlockCG2::R;
   const LevelView& lv = a.lv;
   const int S = B - lv.o;
@@ -1392,7 +1408,8 @@ __device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsig
     }
   }
   const float thr = block_threshold(a, ch, bw, bh);
-  const int it = cg.solve(rho, v, thr, a.maxit);  // zeroes rho outside the block
+  const int it = cg.solve(rho, v, thr, act ? a.maxit : 0);  // zeroes rho outside the block
+  if (!act) return;
   const Fld<TC> out(a.contrib, (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B,
                     a.s_contrib, a.rho, ch);
   float wx[2];
@@ -1412,7 +1429,8 @@ __device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsig
 
 // 16-bit local problems of side 32: BlockCGh2 in packed float16
 template <class TR, class TC>
-__device__ __forceinline__ void block_body_h(const BlockArgs& a, int ch, unsigned bi, unsigned nblk) {
+__device__ __forceinline__ void block_body_h(const BlockArgs& a, int ch, unsigned bi, unsigned nblk,
+                                             bool act) {
   constexpr int B = 32, R = BlockCGh2::R;
   const LevelView& lv = a.lv;
   const int S = B - lv.o;
@@ -1450,6 +1468,7 @@ __device__ __forceinline__ void block_body_h(const BlockArgs& a, int ch, unsigne
   float v[2][R];
   int it = 0;
   float un = 0.0f;  // ||r||; stays 0 (and v = 0) when the block needs no solve
+  if (!act) return;
   if (ss * rs2 > thr && a.maxit > 0) {
     const float sc = __builtin_amdgcn_rsqf(ss);  // unit-norm right-hand side
     half2_t rh[R];
@@ -1493,14 +1512,15 @@ __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
   const unsigned nblk = (unsigned)a.lv.nbx * (unsigned)a.lv.nby;
   const int ch = lin / nblk;
   const unsigned bi = lin - (unsigned)ch * nblk;
-  if (a.active && !a.active[ch]) return;
+  const bool act = channel_active(a.active, ch);  // tested after the loads
   if constexpr (B == 32) {
     if constexpr (is_f32<TR>())
-      block_body_f32<TC>(a, ch, bi, nblk);
+      block_body_f32<TC>(a, ch, bi, nblk, act);
     else
-      block_body_h<TR, TC>(a, ch, bi, nblk);
+      block_body_h<TR, TC>(a, ch, bi, nblk, act);
     return;
   }
+  if (!act) return;
   const LevelView& lv = a.lv;
   const int S = B - lv.o;
   const int bx = bi % lv.nbx, by = bi / lv.nbx;
@@ -1540,7 +1560,7 @@ __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
 template <int B, class T>
 __device__ __forceinline__ void coarse_body(const CoarseArgs& a, unsigned lin) {
   const int ch = (int)lin;
-  if (a.active && !a.active[ch]) return;
+  if (!channel_active(a.active, ch)) return;
   const LevelView& lv = a.lv;
   BlockCG<B> cg;
   cg.setup(0, 0, lv.W, lv.H, lv.W, lv.H, 0.0f, a.c, lv.P);
