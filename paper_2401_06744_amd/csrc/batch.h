@@ -106,7 +106,7 @@ hipError_t issue(const Plan& P, int prec, int B, hipStream_t s, Prof* prof = nul
 // One problem of a batch.
 struct Member {
   int idx = 0;   // position in the caller's array
-  int slot = 0;  // 64-byte slot of its flags in the gathered flag array
+  int slot = 0;  // slot of its flag block (kFlagInts ints) in the gathered flag array
   int W = 0, H = 0, C = 0;
   Lease lease;
   Workspace* ws = nullptr;
@@ -137,7 +137,7 @@ void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o);
 // multilevel and single-level schedules).
 void build_cycle(Plan& P, const std::vector<Member*>& ms, const Opts& o);
 void build_output(Plan& P, const std::vector<Member*>& ms);
-// Copy of each member's flag block to flags_dev + 16 * member.slot.
+// Copy of each member's flag block to flags_dev + kFlagInts * member.slot.
 void add_gather(Plan& P, const std::vector<Member*>& ms, int* flags_dev);
 
 // Build a plan with `body` and record, per member, what one run of it adds to
@@ -171,6 +171,14 @@ void validate_problem(const inpaint_problem& p, int i);
 void check_prepared(const int* flags_host, Member* m);
 // Apply gathered flags after plan P ran over ms; returns true when all are done.
 bool apply_flags(const int* flags_host, const std::vector<Member*>& ms, const Plan& P);
+// Apply gathered flags after the plans seq (the cascade, then cycle plans in
+// issue order) ran over ms: each channel's count of convergence tests names
+// the plan it stopped in.  Sets final buffers, counters and cycle counts;
+// returns true when all are done.
+bool apply_counted(const int* flags_host, const std::vector<Member*>& ms,
+                   const std::vector<const Plan*>& seq);
+// Back to the state init_member left (before a repeated solve).
+void reset_member(Member* m);
 // Add one run of P to the counters of the members still running.
 void account(const std::vector<Member*>& ms, const Plan& P);
 // After the last plan: final buffers of unfinished channels and the status.
@@ -194,11 +202,14 @@ struct BatchCtx {
   Plan cascade;
   Plan cycle[2];  // cycle plans alternate when a V-cycle flips the iterate buffers
   int ncycle = 0;
+  // V-cycles the last solve in this context needed (all members converged);
+  // 0: wait for the input checks and test convergence after every plan
+  int expect = 0;
   unsigned char* plan_dev = nullptr;
   size_t plan_cap = 0;
   unsigned char* call_dev = nullptr;  // per-call plans (prepare, output)
   size_t call_cap = 0;
-  int* flags_dev = nullptr;   // [n][16] gathered flag blocks
+  int* flags_dev = nullptr;   // [n][kFlagInts] gathered flag blocks
   int* flags_host = nullptr;  // pinned copy
   hipStream_t cap = nullptr;  // capture stream
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

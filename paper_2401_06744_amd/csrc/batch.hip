@@ -24,12 +24,13 @@ namespace {
 struct ResetArgs {
   int* active;
   int* status;
+  int* checks;
   unsigned long long* cgstat;
   int C;
 };
 
-// Copy of one problem's 64-byte flag block (relres[4] doubles, active[4] and
-// status[4] ints) into the batch's gathered array.
+// Copy of one problem's flag block (kFlagInts ints: relres[4] doubles,
+// active[4], status[4], checks[4] ints) into the batch's gathered array.
 struct GatherArgs {
   const int* src;
   int* dst;
@@ -40,13 +41,14 @@ __global__ void __launch_bounds__(64) k_reset_b(const ResetArgs* __restrict__ ar
   const int t = threadIdx.x;
   if (t < a.C) a.active[t] = 1;
   if (t < 4) a.status[t] = 0;
+  if (t < 4) a.checks[t] = 0;
   for (int i = t; i < 3 * a.C * kMaxLevels; i += blockDim.x) a.cgstat[i] = 0;
 }
 
 __global__ void __launch_bounds__(64) k_gather(const GatherArgs* __restrict__ args) {
   const GatherArgs a = args[blockIdx.x];
   const int t = threadIdx.x;
-  if (t < 16) a.dst[t] = a.src[t];
+  if (t < kFlagInts) a.dst[t] = a.src[t];
 }
 
 }  // namespace
@@ -372,7 +374,7 @@ void build_cycle(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
 
 void add_gather(Plan& P, const std::vector<Member*>& ms, int* flags_dev) {
   P.begin(S_GATHER);
-  for (Member* m : ms) P.add(GatherArgs{(const int*)m->ws->relres, flags_dev + 16 * m->slot}, 1u);
+  for (Member* m : ms) P.add(GatherArgs{(const int*)m->ws->relres, flags_dev + kFlagInts * m->slot}, 1u);
   P.end();
 }
 
@@ -444,8 +446,8 @@ std::shared_ptr<BatchCtx> batch_ctx(int dev, const std::vector<Member*>& ms, con
   c->key = key;
   c->dev_id = dev;
   c->n = n;
-  HIPCHK(hipMalloc(&c->flags_dev, (size_t)n * 64));
-  HIPCHK(hipHostMalloc(&c->flags_host, (size_t)n * 64, hipHostMallocDefault));
+  HIPCHK(hipMalloc(&c->flags_dev, (size_t)n * kFlagInts * sizeof(int)));
+  HIPCHK(hipHostMalloc(&c->flags_host, (size_t)n * kFlagInts * sizeof(int), hipHostMallocDefault));
   HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
   HIPCHK(hipEventCreate(&c->ev0));
   HIPCHK(hipEventCreate(&c->ev1));
@@ -499,19 +501,13 @@ void run_plan(const Plan& P, int prec, int B, hipStream_t s) {
     HIPCHK(issue(P, prec, B, s));
 }
 
-bool poll_members(BatchCtx& c, const std::vector<Member*>& ms, const Plan& P, hipStream_t s) {
-  HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)c.n * 64, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  return apply_flags(c.flags_host, ms, P);
-}
-
 }  // namespace
 
 bool apply_flags(const int* flags_host, const std::vector<Member*>& ms, const Plan& P) {
   bool all = true;
   for (size_t i = 0; i < ms.size(); ++i) {
     Member* m = ms[i];
-    const int* blk = flags_host + 16 * m->slot;
+    const int* blk = flags_host + kFlagInts * m->slot;
     const double* rr = (const double*)blk;
     const int* act = blk + 8;
     const int* st = blk + 12;
@@ -556,6 +552,57 @@ void finish_member(Member* m, int last_cur0) {
   }
 }
 
+bool apply_counted(const int* flags_host, const std::vector<Member*>& ms,
+                   const std::vector<const Plan*>& seq) {
+  bool all = true;
+  for (size_t i = 0; i < ms.size(); ++i) {
+    Member* m = ms[i];
+    const int* blk = flags_host + kFlagInts * m->slot;
+    const double* rr = (const double*)blk;
+    const int* act = blk + 8;
+    const int* st = blk + 12;
+    const int* tests = blk + 16;
+    if (st[0] & 4) fail(INPAINT_E_DEVICE, "a norm partial never arrived (spin budget exhausted)");
+    bool d = true;
+    int last = 0;  // index in seq of the last plan that iterated the member
+    for (int ch = 0; ch < m->C; ++ch) {
+      // one test per plan while the channel iterates: a channel that stopped
+      // (converged, or a non-finite residual) stopped in plan tests - 1
+      const int k = tests[ch];
+      if (k < 1 || k > (int)seq.size()) fail(INPAINT_E_DEVICE, "inconsistent convergence-test count");
+      m->rel[ch] = rr[ch];
+      if (!act[ch] || !std::isfinite(rr[ch])) {
+        m->final_cur[ch] = seq[k - 1]->cur0[i];
+        last = std::max(last, k - 1);
+      } else {
+        m->final_cur[ch] = -1;
+        d = false;
+      }
+    }
+    if (!d) last = (int)seq.size() - 1;
+    m->done = d;
+    m->cycles = last;
+    m->oras = m->blocks = m->finest_blocks = 0;
+    for (int p = 0; p <= last; ++p) {
+      m->oras += seq[p]->delta[i][0];
+      m->blocks += seq[p]->delta[i][1];
+      m->finest_blocks += seq[p]->delta[i][2];
+    }
+    all = all && d;
+  }
+  return all;
+}
+
+void reset_member(Member* m) {
+  m->status = INPAINT_OK;
+  m->msg.clear();
+  m->final_cur.assign(m->C, -1);
+  m->rel.assign(m->C, 0.0);
+  m->cycles = 0;
+  m->done = false;
+  m->oras = m->blocks = m->finest_blocks = 0;
+}
+
 void fill_stats(const Member* m, inpaint_stats& st) {
   std::memset(&st, 0, sizeof st);
   st.status = m->status;
@@ -573,7 +620,7 @@ void fill_stats(const Member* m, inpaint_stats& st) {
 
 // Reads the flag block written by the prepare plan: input checks of f and the mask.
 void check_prepared(const int* flags_host, Member* m) {
-  const int st = flags_host[16 * m->slot + 12];
+  const int st = flags_host[kFlagInts * m->slot + 12];
   if (st & 1) {
     m->status = INPAINT_E_INVALID;
     m->msg = "f is not finite at a known pixel";
@@ -634,7 +681,7 @@ void init_member(Member& m, const inpaint_problem& p, Workspace* ws, const Opts&
 void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* flags_dev) {
   const bool single = o.schedule == INPAINT_SCHED_SINGLE;
   P.begin(S_RESET);
-  for (Member* m : ms) P.add(ResetArgs{m->ws->active, m->ws->status, m->ws->cgstat, m->C}, 1u);
+  for (Member* m : ms) P.add(ResetArgs{m->ws->active, m->ws->status, m->ws->checks, m->ws->cgstat, m->C}, 1u);
   P.end();
   P.begin(S_STAGE, 0, 0);
   for (Member* m : ms) {
@@ -761,14 +808,26 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
   build(prep, all, [&] { build_prepare(prep, all, o, c.flags_dev); });
   upload({&prep}, &c.call_dev, &c.call_cap, s);
   HIPCHK(issue(prep, prec, B, s, prof));
-  HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)n * 64, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  // With plans cached for every member and the cycle count of the last solve
+  // in this context, the solve runs ahead: the input checks and the first
+  // convergence tests are read back once, after that many V-cycles (a channel
+  // that converges earlier skips the remaining launches).
+  const std::string all_live(n, 1);
+  const bool ahead = !prof && c.expect > 0 && c.live_key == all_live;
   std::vector<Member*> live;
   std::string live_key;
-  for (Member* m : all) {
-    check_prepared(c.flags_host, m);
-    live_key.push_back(m->status == INPAINT_OK ? 1 : 0);
-    if (m->status == INPAINT_OK) live.push_back(m);
+  if (ahead) {
+    live = all;
+    live_key = all_live;
+  } else {
+    HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)n * kFlagInts * sizeof(int),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (Member* m : all) {
+      check_prepared(c.flags_host, m);
+      live_key.push_back(m->status == INPAINT_OK ? 1 : 0);
+      if (m->status == INPAINT_OK) live.push_back(m);
+    }
   }
 
   if (!live.empty()) {
@@ -799,23 +858,47 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
         for (int k = 0; k < c.ncycle; ++k) capture(c.cycle[k], c, prec, B);
     }
     HIPCHK(issue(c.cascade, prec, B, s, prof));
-    account(live, c.cascade);
-    bool done = poll_members(c, live, c.cascade, s);
+    std::vector<const Plan*> seq{&c.cascade};
     int cycles = 0;
+    for (const int k = ahead ? std::min(c.expect, o.max_cycles) : 0; cycles < k; ++cycles) {
+      const Plan& P = c.cycle[cycles % c.ncycle];
+      run_plan(P, prec, B, s);
+      seq.push_back(&P);
+    }
+    HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)n * kFlagInts * sizeof(int),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (ahead) {
+      bool rejected = false;
+      for (Member* m : all) {
+        check_prepared(c.flags_host, m);
+        rejected = rejected || m->status != INPAINT_OK;
+      }
+      if (rejected) {
+        // an input check failed: solve again, waiting for the checks first
+        for (Member* m : all) reset_member(m);
+        c.expect = 0;
+        return run_batch(all, o, tol, s, prof);
+      }
+    }
+    bool done = apply_counted(c.flags_host, live, seq);
     while (!done && cycles < o.max_cycles) {
       const Plan& P = c.cycle[cycles % c.ncycle];
-      for (Member* m : live)
-        if (!m->done) ++m->cycles;
-      account(live, P);
       if (prof)
         HIPCHK(issue(P, prec, B, s, prof));
       else
         run_plan(P, prec, B, s);
+      seq.push_back(&P);
       ++cycles;
-      done = poll_members(c, live, P, s);
+      HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)n * kFlagInts * sizeof(int),
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      done = apply_counted(c.flags_host, live, seq);
     }
-    const Plan& last = cycles == 0 ? c.cascade : c.cycle[(cycles - 1) % c.ncycle];
-    for (size_t i = 0; i < live.size(); ++i) finish_member(live[i], last.cur0[i]);
+    int need = 0;
+    for (Member* m : live) need = std::max(need, m->cycles);
+    c.expect = done ? need : 0;
+    for (size_t i = 0; i < live.size(); ++i) finish_member(live[i], seq.back()->cur0[i]);
     Plan out;
     build_output(out, live);
     upload({&out}, &c.call_dev, &c.call_cap, s);

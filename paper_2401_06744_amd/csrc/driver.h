@@ -114,6 +114,7 @@ struct Workspace {
   double* relres = nullptr; // [C]
   int* active = nullptr;    // [C]
   int* status = nullptr;    // [4]
+  int* checks = nullptr;    // [C] convergence tests run per channel
   unsigned long long* cgstat = nullptr;  // [L][C][3]: total, max, pixel-weighted local CG iterations
   std::vector<hipEvent_t> evpool;        // events for per-launch profiling
   // host-pointer staging (allocated on first use)
@@ -227,6 +228,7 @@ struct Run {
     n.den = ws->den;
     n.relres = ws->relres;
     n.active = ws->active;
+    n.checks = ws->checks;
     n.tol = tol;
     n.check = check ? 1 : 0;
     return n;

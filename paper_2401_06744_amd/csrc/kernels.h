@@ -16,6 +16,9 @@ constexpr int kMaxLevels = 24;
 // Tile of the grid passes: 64 columns x 32 rows, 256 threads (8 rows each).
 constexpr int kTileW = 64;
 constexpr int kTileH = 32;
+// Ints per flag block of a problem: relres[4] doubles, active[4], status[4],
+// checks[4] ints, spare.  One block is copied to the host per poll.
+constexpr int kFlagInts = 32;
 // Most norm partials a block solve adds up itself (deferred norms).
 constexpr int kDeferParts = 256;
 
@@ -67,6 +70,7 @@ struct NormOut {
   const double* den;  // [C] squared norm of the reference residual
   double* relres;     // [C] sqrt(out / den)
   int* active;        // [C] set to 0 once relres <= tol
+  int* checks;        // [C] number of tests run (optional)
   double tol;
   int check;
   // Optional (stage only): rho[ch] = sqrt(out[ch] * inv_n), the rms of the

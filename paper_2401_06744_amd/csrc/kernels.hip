@@ -419,6 +419,7 @@ __device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, 
       const double rel = den > 0.0 ? sqrt(tot / den) : (tot > 0.0 ? INFINITY : 0.0);
       no.relres[ch] = rel;
       if (rel <= no.tol) no.active[ch] = 0;
+      if (no.checks) no.checks[ch] += 1;
     }
   }
 }

@@ -212,7 +212,7 @@ void inpaint_server::loop() {
       build(prep, fm, [&] { build_prepare(prep, fm, o, flags_dev); });
       upload({&prep}, &prep_dev, &prep_cap, s);
       HIPCHK(issue(prep, o.prec, o.B, s));
-      HIPCHK(hipMemcpyAsync(flags_host, flags_dev, (size_t)max_batch * 64, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(flags_host, flags_dev, (size_t)max_batch * kFlagInts * sizeof(int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       for (auto& r : fresh) {
         check_prepared(flags_host, r->m.get());
@@ -241,7 +241,7 @@ void inpaint_server::loop() {
     upload({&pc, &py}, &plan_dev, &plan_cap, s);
     HIPCHK(issue(pc, o.prec, o.B, s));
     HIPCHK(issue(py, o.prec, o.B, s));
-    HIPCHK(hipMemcpyAsync(flags_host, flags_dev, (size_t)max_batch * 64, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(flags_host, flags_dev, (size_t)max_batch * kFlagInts * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     apply_flags(flags_host, cas, pc);
     apply_flags(flags_host, going, py);
@@ -302,8 +302,8 @@ INPAINT_EXPORT int inpaint_server_create(const inpaint_server_cfg* cfg, inpaint_
     HIPCHK(hipMemGetInfo(&fr, &tot));
     sv->budget = (cfg && cfg->hbm_budget) ? cfg->hbm_budget : fr / 10 * 8;
     HIPCHK(hipStreamCreateWithFlags(&sv->s, hipStreamNonBlocking));
-    HIPCHK(hipMalloc(&sv->flags_dev, (size_t)sv->max_batch * 64));
-    HIPCHK(hipHostMalloc(&sv->flags_host, (size_t)sv->max_batch * 64, hipHostMallocDefault));
+    HIPCHK(hipMalloc(&sv->flags_dev, (size_t)sv->max_batch * kFlagInts * sizeof(int)));
+    HIPCHK(hipHostMalloc(&sv->flags_host, (size_t)sv->max_batch * kFlagInts * sizeof(int), hipHostMallocDefault));
     for (int i = sv->max_batch - 1; i >= 0; --i) sv->free_slots.push_back(i);
     sv->t0 = std::chrono::steady_clock::now();
     sv->th = std::thread([p = sv.get()] { p->run(); });

@@ -138,9 +138,9 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
   const size_t o_sn = take((size_t)ws->L * C * sizeof(double));
   const size_t o_den = take((size_t)C * sizeof(double));
   const size_t o_rho = take((size_t)C * sizeof(float));
-  // relres[4] doubles, active[4] ints, status[4] ints: one 64-byte block so
-  // that a poll is a single copy
-  const size_t o_flags = take(64);
+  // relres[4] doubles, active[4], status[4] and checks[4] ints: one block of
+  // kFlagInts ints, so that a poll is a single copy
+  const size_t o_flags = take(kFlagInts * sizeof(int));
   const size_t o_cg = take((size_t)kMaxLevels * C * 3 * sizeof(unsigned long long));
   ws->bytes = off;
   if (!alloc) return ws;
@@ -176,6 +176,8 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
   ws->relres = (double*)(base + o_flags);
   ws->active = (int*)(base + o_flags + 32);
   ws->status = (int*)(base + o_flags + 48);
+  ws->checks = (int*)(base + o_flags + 64);
+  HIPCHK(hipMemset(ws->checks, 0, 4 * sizeof(int)));
   ws->cgstat = (unsigned long long*)(base + o_cg);
   HIPCHK(hipHostMalloc(&ws->host, 4096, hipHostMallocDefault));
   HIPCHK(hipEventCreate(&ws->ev0));

@@ -104,6 +104,49 @@ def test_batched_rejected_problems_leave_the_others_alone():
     assert st2 == binding.OK
     for o, s in zip(outs2, _solo(probs)):
         assert np.array_equal(o, s)
+    # again with the rejected inputs: this call runs ahead without waiting for
+    # the input checks, finds them failed and solves again
+    outs3, st3, stats3 = binding.inpaint_solve_batched(bad, TOL, raise_on_error=False)
+    assert st3 == binding.E_EMPTY_MASK
+    assert [s["status"] for s in stats3] == [s["status"] for s in stats]
+    assert np.array_equal(outs3[0], solo[0]) and np.array_equal(outs3[3], solo[1])
+
+
+def _stats_key(stats):
+    return [(s["status"], s["cycles"], s["oras_iters"], s["finest_block_solves"], s["rel_res"])
+            for s in stats]
+
+
+def test_batched_repeat_runs_ahead_with_identical_results():
+    """A repeated batch issues the V-cycles its context needed last time before
+    reading any convergence test back: outputs and statistics must equal those
+    of the first call, which tested after every cycle."""
+    probs = _mix(seed=700)
+    first, st, stats = binding.inpaint_solve_batched(probs, TOL)
+    assert st == binding.OK
+    assert len({s["cycles"] for s in stats}) > 1  # members stop at different cycles
+    for _ in range(2):
+        again, st2, stats2 = binding.inpaint_solve_batched(probs, TOL)
+        assert st2 == binding.OK
+        assert _stats_key(stats2) == _stats_key(stats)
+        for a, b in zip(again, first):
+            assert np.array_equal(a, b)
+
+
+def test_batched_running_ahead_too_far_changes_nothing():
+    """Same shapes (the same batch context), easier masks after harder ones:
+    the cycles issued ahead beyond convergence must leave results as solo."""
+    hard = [(synth.frame_image(W, H, 3, seed=800 + k), synth.bernoulli_mask(W, H, 0.01, seed=810 + k))
+            for k, (W, H) in enumerate([(301, 203), (160, 96)])]
+    easy = [(f, synth.bernoulli_mask(f.shape[2], f.shape[1], 0.4, seed=820 + k))
+            for k, (f, _) in enumerate(hard)]
+    _, st, sh = binding.inpaint_solve_batched(hard, TOL)
+    assert st == binding.OK
+    outs, st, se = binding.inpaint_solve_batched(easy, TOL)
+    assert st == binding.OK
+    assert max(s["cycles"] for s in se) < max(s["cycles"] for s in sh)
+    for o, s in zip(outs, _solo(easy)):
+        assert np.array_equal(o, s)
 
 
 def test_batched_argument_errors():
