@@ -370,7 +370,7 @@ __device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, 
   if (!last) return;
   // Entries t, t + T, t + 2T, ... are added in that order; loads are issued in
   // batches of U so that the coherent-level round trips overlap.
-  constexpr int U = 1;
+  constexpr int U = 8;
   double s = 0.0;
   int spins = 0;
   bool lost = false;
