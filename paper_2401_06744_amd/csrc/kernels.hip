@@ -1428,7 +1428,7 @@ __device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsig
   count_iterations(a, (size_t)ch * nblk + bi, it);
 }
 
-// 16-bit local problems of side 32: BlockCGh2 in packed float16
+// Local problems of side 32 with 16-bit corrections: BlockCGh2 in packed float16
 template <class TR, class TC>
 __device__ __forceinline__ void block_body_h(const BlockArgs& a, int ch, unsigned bi, unsigned nblk,
                                              bool act) {
@@ -1515,7 +1515,9 @@ __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
   const unsigned bi = lin - (unsigned)ch * nblk;
   const bool act = channel_active(a.active, ch);  // tested after the loads
   if constexpr (B == 32) {
-    if constexpr (is_f32<TR>())
+    // a correction stored in 16 bits is solved for in packed float16 (with
+    // float32 accumulation), whatever the residual's type
+    if constexpr (is_f32<TR>() && is_f32<TC>())
       block_body_f32<TC>(a, ch, bi, nblk, act);
     else
       block_body_h<TR, TC>(a, ch, bi, nblk, act);
