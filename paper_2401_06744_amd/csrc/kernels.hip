@@ -500,43 +500,56 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, unsigned lin) {
   __shared__ uint8_t kn[kTileH + 2][kTileW + 2];
   const gptr<const float> fc = f + (size_t)ch * Pf * H;
   bool bad = false, any = false;
-  // every element of the tile and its halo: mask and f are read from clamped
-  // in-image addresses up front (f at unknown pixels is read but never used)
-  constexpr int NE = (kTileH + 2) * (kTileW + 2);
-  constexpr int NJ = (NE + kPassThreads - 1) / kPassThreads;
-  uint8_t km[NJ];
-  float fv[NJ];
+  // Phase 1, laid out as the grid passes: thread (column c, row group g)
+  // takes column x0 + c of tile rows g, g + 4, ... (the tile plus a one-pixel
+  // halo row above and below; rows past the halo repeat a valid row and are
+  // not kept); a few threads take the two halo columns.  Mask and f are read
+  // from clamped in-image addresses up front (f at unknown pixels is read but
+  // never used); pixels outside the image enter the tile as unknown, 0.
+  constexpr int TW = kTileW + 2, TH = kTileH + 2;
+  constexpr int NG = kPassThreads / kTileW;
+  constexpr int RJ = (TH + NG - 1) / NG;
+  const int cc = threadIdx.x & (kTileW - 1), g = threadIdx.x / kTileW;
+  const int gx = x0 + cc;
+  const int gxc = min(gx, W - 1);
+  uint8_t km[RJ];
+  float fv[RJ];
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int i = min((int)threadIdx.x + j * kPassThreads, NE - 1);
-    const int ty = i / (kTileW + 2), tx = i - ty * (kTileW + 2);
-    const int gx = min(max(x0 + tx - 1, 0), W - 1), gy = min(max(y0 + ty - 1, 0), H - 1);
-    km[j] = mask[(size_t)gy * W + gx];
-    fv[j] = fc[(size_t)gy * Pf + gx];
+  for (int j = 0; j < RJ; ++j) {
+    const int ty = min(g + NG * j, TH - 1);
+    const int gy = min(max(y0 - 1 + ty, 0), H - 1);
+    km[j] = mask[(size_t)gy * W + gxc];
+    fv[j] = fc[(size_t)gy * Pf + gxc];
   }
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    const int i = (int)threadIdx.x + j * kPassThreads;
-    if (i >= NE) break;
-    const int ty = i / (kTileW + 2), tx = i - ty * (kTileW + 2);
-    const int gx = x0 + tx - 1, gy = y0 + ty - 1;
-    float v = 0.0f;
-    uint8_t k = 0;
-    if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-      k = km[j] != 0;
-      v = k ? fv[j] : 0.0f;
-      const bool inner = tx >= 1 && tx <= kTileW && ty >= 1 && ty <= kTileH;
-      if (inner) {
-        bad |= k && !isfinite(v);
-        any |= k;
-        const size_t oc = (size_t)gy * lv.P + gx;
-        if (ch == 0) c[oc] = k;
-        b[(size_t)ch * lv.plane + oc] = v;
-        if (u) u[(size_t)ch * lv.plane + oc] = v;
-      }
+  for (int j = 0; j < RJ; ++j) {
+    const int ty = g + NG * j;
+    if (ty >= TH) break;
+    const int gy = y0 - 1 + ty;
+    const bool in = gx < W && gy >= 0 && gy < H;
+    const uint8_t k = in && km[j] != 0;
+    const float v = k ? fv[j] : 0.0f;
+    if (in && ty >= 1 && ty <= kTileH) {
+      bad |= k && !isfinite(v);
+      any |= k;
+      const size_t oc = (size_t)gy * lv.P + gx;
+      if (ch == 0) c[oc] = k;
+      b[(size_t)ch * lv.plane + oc] = v;
+      if (u) u[(size_t)ch * lv.plane + oc] = v;
     }
-    t[ty][tx] = v;
-    kn[ty][tx] = k;
+    t[ty][cc + 1] = v;
+    kn[ty][cc + 1] = k;
+  }
+  if (threadIdx.x < 2 * TH) {
+    // halo columns tx = 0 and tx = TW - 1 (kept in LDS only)
+    const int side = threadIdx.x / TH, ty = threadIdx.x - side * TH;
+    const int hx = side == 0 ? x0 - 1 : x0 + kTileW, hy = y0 - 1 + ty;
+    const int hxc = min(max(hx, 0), W - 1), hyc = min(max(hy, 0), H - 1);
+    const uint8_t hm = mask[(size_t)hyc * W + hxc];
+    const float hf = fc[(size_t)hyc * Pf + hxc];
+    const uint8_t k = hx >= 0 && hx < W && hy >= 0 && hy < H && hm != 0;
+    t[ty][side == 0 ? 0 : TW - 1] = k ? hf : 0.0f;
+    kn[ty][side == 0 ? 0 : TW - 1] = k;
   }
   // Report through one word shared by the whole grid: skip the atomic when the
   // bit is already set, so that it is issued a handful of times, not per wave.
@@ -548,8 +561,7 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, unsigned lin) {
     if ((have & want) != want) atomicOr(status, want);
   }
   __syncthreads();
-  const int tx = threadIdx.x & 63, tyg = threadIdx.x >> 6;
-  const int gx = x0 + tx;
+  const int tx = cc, tyg = g;  // phase 2: 8 rows of column gx per thread
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < kTileH / 4; ++k) {
