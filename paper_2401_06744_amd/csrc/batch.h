@@ -15,7 +15,6 @@ namespace inpaint {
 enum StepKind : int {
   S_RESET,
   S_STAGE,
-  S_MASK,
   S_RHS,
   S_PASS,
   S_RESTRICT,

@@ -111,7 +111,6 @@ int kernel_class(const Step& st) {
   if (st.level != 0) return -1;
   switch (st.kind) {
     case S_STAGE: return INPAINT_K_STAGE;
-    case S_MASK:
     case S_RHS: return INPAINT_K_PYRAMID;
     case S_BLOCK: return INPAINT_K_BLOCK_SOLVE;
     case S_RESTRICT: return INPAINT_K_RESTRICT;
@@ -169,7 +168,6 @@ hipError_t issue_step(const Step& st, const unsigned char* dev, int prec, int B,
         e = hipGetLastError();
         break;
       case S_STAGE: e = launch_stage_b((const StageArgs*)a, start, st.n, st.total, s); break;
-      case S_MASK: e = launch_mask_b((const MaskArgs*)a, start, st.n, st.total, s); break;
       case S_RHS:
         e = launch_rhs_b((const RhsArgs*)a, start, st.n, st.total, prec, st.f32, s);
         break;
@@ -705,19 +703,11 @@ void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* 
     for (Member* m : ms) maxL = std::max(maxL, m->ws->L);
     for (int l = 0; l + 1 < maxL; ++l) {
       const auto part = subset(ms, [&](Member* m) { return l + 1 < m->ws->L; });
-      P.begin(S_MASK, 0, l);
-      for (Member* m : part) {
-        Level& F = m->ws->lv[l];
-        Level& Cl = m->ws->lv[l + 1];
-        Cl.cur = 0;
-        const MaskArgs a{F.v, Cl.v, F.c, Cl.c};
-        P.add(a, work_mask(a));
-      }
-      P.end();
       P.begin(S_RHS, 0, l);
       for (Member* m : part) {
         Level& F = m->ws->lv[l];
         Level& Cl = m->ws->lv[l + 1];
+        Cl.cur = 0;
         const RhsArgs a{F.v, Cl.v, F.c, F.b, Cl.c, Cl.b, m->C, o.rhs == INPAINT_RHS_NAIVE ? 1 : 0};
         P.add(a, work_rhs(a), l == 0 ? 1 : 0);
       }

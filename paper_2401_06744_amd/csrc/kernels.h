@@ -189,17 +189,11 @@ struct StageArgs {
   NormOut den;
 };
 
-struct MaskArgs {
-  LevelView fl, cl;
-  const uint8_t* cf;
-  uint8_t* cc;
-};
-
 struct RhsArgs {
   LevelView fl, cl;
   const uint8_t* cf;
   const void* bf;
-  const uint8_t* cc;
+  uint8_t* cc;  // written: the coarse mask
   void* bc;
   int C, naive;
 };
@@ -216,7 +210,6 @@ struct OutputArgs {
 // Work items (workgroups) of one problem in each kernel; a batched launch
 // gives problem p the global items [start[p], start[p + 1]).
 unsigned work_stage(const StageArgs& a);
-unsigned work_mask(const MaskArgs& a);
 unsigned work_rhs(const RhsArgs& a);
 unsigned work_pass(const PassArgs& a, int C);
 unsigned work_restrict(const RestrictArgs& a, int C);
@@ -230,8 +223,6 @@ unsigned work_output(const OutputArgs& a);
 // channel count may differ between problems.
 hipError_t launch_stage_b(const StageArgs* args, const unsigned* start, int n, unsigned total,
                           hipStream_t s);
-hipError_t launch_mask_b(const MaskArgs* args, const unsigned* start, int n, unsigned total,
-                         hipStream_t s);
 hipError_t launch_rhs_b(const RhsArgs* args, const unsigned* start, int n, unsigned total, int prec,
                         int fine_f32, hipStream_t s);
 hipError_t launch_pass_b(int mode, const PassArgs* args, const unsigned* start, int n,
@@ -251,11 +242,10 @@ hipError_t launch_output_b(const OutputArgs* args, const unsigned* start, int n,
 hipError_t launch_stage(const float* f, const uint8_t* mask, int W, int H, int C, int Pf,
                         LevelView lv, uint8_t* c, float* b, float* u, int* status, NormOut den,
                         hipStream_t s);
-hipError_t launch_mask_down(LevelView fine, const uint8_t* cf, LevelView coarse, uint8_t* cc,
-                            hipStream_t s);
-// Coarse known values (unscaled); the fine level is float32 when fine_f32.
+// One pyramid level: coarse mask (max pool) and coarse known values
+// (unscaled); the fine level is float32 when fine_f32.
 hipError_t launch_rhs_down(LevelView fine, const uint8_t* cf, const void* bf, LevelView coarse,
-                           const uint8_t* cc, void* bc, int C, int naive, int prec, int fine_f32,
+                           uint8_t* cc, void* bc, int C, int naive, int prec, int fine_f32,
                            hipStream_t s);
 hipError_t launch_pass(int mode, const PassArgs& a, int C, hipStream_t s);
 hipError_t launch_restrict(const RestrictArgs& a, int C, hipStream_t s);

@@ -12,8 +12,8 @@
 //
 // Kernels:
 //   stage        b_0 = C f, mask normalised to 0/1, u_0 = C f, input checks
-//   mask_down    coarse mask by max pooling (Section 4.3)
-//   rhs_down     coarse known values, naive or modified (Section 4.3)
+//   rhs_down     one pyramid level: coarse mask by max pooling and coarse
+//                known values, naive or modified (Section 4.3)
 //   pass<MODE>   one fused grid pass: form the new iterate on a 64x32 tile plus
 //                a 1-pixel halo in LDS (ORAS update, cascade prolongation or
 //                coarse-grid correction), write it, write the float64-evaluated
@@ -230,33 +230,29 @@ __device__ __forceinline__ void output_body(const OutputArgs& a, unsigned lin) {
 // coarse problems (Section 4.3)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void mask_body(const MaskArgs& a, unsigned lin) {
-  const LevelView& fl = a.fl;
-  const LevelView& cl = a.cl;
-  const uint8_t* __restrict__ cf = a.cf;
-  uint8_t* __restrict__ cc = a.cc;
-  const unsigned gxn = (unsigned)((cl.W + 63) / 64);
-  const int X = (int)(lin % gxn) * 64 + (threadIdx.x & 63);
-  const int Y = (int)(lin / gxn) * 4 + (threadIdx.x >> 6);
-  if (X >= cl.W || Y >= cl.H) return;
-  // children past the image edge read the existing child (max pool unchanged)
+// Coarse mask of cell (X, Y): max pool over its existing children (a child
+// past the image edge repeats the existing one).
+__device__ __forceinline__ uint8_t pooled_mask(const gptr<const uint8_t> cf, const LevelView& fl, int X,
+                                               int Y) {
   const int x0 = 2 * X, y0 = 2 * Y, x1 = min(x0 + 1, fl.W - 1), y1 = min(y0 + 1, fl.H - 1);
   const uint8_t m = (cf[(size_t)y0 * fl.P + x0] | cf[(size_t)y0 * fl.P + x1]) |
                     (cf[(size_t)y1 * fl.P + x0] | cf[(size_t)y1 * fl.P + x1]);
-  cc[(size_t)Y * cl.P + X] = m ? 1 : 0;
+  return m ? 1 : 0;
 }
 
-// Coarse known value of cell (X, Y).  Modified form: a known child j is
+// One level of the coarse problems for cell (X, Y): its coarse mask (max pool,
+// Section 4.3) and its known value.  Modified form: a known child j is
 // weighted by its number of direct neighbours that are not known, judging a
 // neighbour in the same cell by the fine mask and one in an adjacent cell by
-// that cell's coarse mask; neighbours outside the image are not counted.  If
-// every weight is 0 the plain mean of the known children is used.
+// that cell's coarse mask (pooled here from the fine mask, so that both
+// pyramids take one launch per level); neighbours outside the image are not
+// counted.  If every weight is 0 the plain mean of the known children is used.
 template <class TF, class TC>
 __device__ __forceinline__ void rhs_body(const RhsArgs& a, unsigned lin) {
   const LevelView& fl = a.fl;
   const LevelView& cl = a.cl;
-  const uint8_t* __restrict__ cf = a.cf;
-  const uint8_t* __restrict__ cc = a.cc;
+  const gptr<const uint8_t> cf = glb(a.cf);
+  const gptr<uint8_t> cc = glb(a.cc);
   const TF* __restrict__ bf = (const TF*)a.bf;
   TC* __restrict__ bc = (TC*)a.bc;
   const int C = a.C, naive = a.naive;
@@ -265,7 +261,9 @@ __device__ __forceinline__ void rhs_body(const RhsArgs& a, unsigned lin) {
   const int Y = (int)(lin / gxn) * 4 + (threadIdx.x >> 6);
   if (X >= cl.W || Y >= cl.H) return;
   const size_t oc = (size_t)Y * cl.P + X;
-  if (!cc[oc]) {
+  const uint8_t m = pooled_mask(cf, fl, X, Y);
+  cc[oc] = m;
+  if (!m) {
     for (int ch = 0; ch < C; ++ch) bc[(size_t)ch * cl.plane + oc] = (TC)0.0f;
     return;
   }
@@ -286,7 +284,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs& a, unsigned lin) {
         const int yy = ny[d], xx = nx[d];
         if (yy < 0 || yy >= fl.H || xx < 0 || xx >= fl.W) continue;
         const bool same = (yy >> 1) == Y && (xx >> 1) == X;
-        const uint8_t k = same ? cf[(size_t)yy * fl.P + xx] : cc[(size_t)(yy >> 1) * cl.P + (xx >> 1)];
+        const uint8_t k = same ? cf[(size_t)yy * fl.P + xx] : pooled_mask(cf, fl, xx >> 1, yy >> 1);
         w += k ? 0 : 1;
       }
       wts[nk] = w;
@@ -1657,12 +1655,6 @@ __global__ void __launch_bounds__(256) k_output_b(const OutputArgs* __restrict__
   output_body(args[p], g - start[p]);
 }
 
-__global__ void __launch_bounds__(256) k_mask_down(MaskArgs a) { mask_body(a, xcd_remap(blockIdx.x, gridDim.x)); }
-__global__ void __launch_bounds__(256) k_mask_b(const MaskArgs* __restrict__ args,
-                                                const unsigned* __restrict__ start, int n) {
-  INPAINT_BATCH_LOOKUP(MaskArgs)
-  mask_body(a, lin);
-}
 
 template <class TF, class TC>
 __global__ void __launch_bounds__(256) k_rhs_down(RhsArgs a) {
@@ -1766,7 +1758,6 @@ size_t pass_tiles(const LevelView& lv) {
 // ---------------------------------------------------------------------------
 
 unsigned work_stage(const StageArgs& a) { return (unsigned)pass_tiles(a.lv) * (unsigned)a.C; }
-unsigned work_mask(const MaskArgs& a) { return px_groups(a.cl.W, a.cl.H); }
 unsigned work_rhs(const RhsArgs& a) { return px_groups(a.cl.W, a.cl.H); }
 unsigned work_pass(const PassArgs& a, int C) { return (unsigned)pass_tiles(a.lv) * (unsigned)C; }
 unsigned work_restrict(const RestrictArgs& a, int C) { return (unsigned)pass_tiles(a.cl) * (unsigned)C; }
@@ -1791,15 +1782,8 @@ hipError_t launch_stage(const float* f, const uint8_t* mask, int W, int H, int C
   return hipGetLastError();
 }
 
-hipError_t launch_mask_down(LevelView fine, const uint8_t* cf, LevelView coarse, uint8_t* cc,
-                            hipStream_t s) {
-  const MaskArgs a{fine, coarse, cf, cc};
-  hipLaunchKernelGGL(k_mask_down, dim3(work_mask(a)), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
 hipError_t launch_rhs_down(LevelView fine, const uint8_t* cf, const void* bf, LevelView coarse,
-                           const uint8_t* cc, void* bc, int C, int naive, int prec, int fine_f32,
+                           uint8_t* cc, void* bc, int C, int naive, int prec, int fine_f32,
                            hipStream_t s) {
   const RhsArgs a{fine, coarse, cf, bf, cc, bc, C, naive};
   return with_types(prec, fine_f32, [&](auto tf, auto tc) {
@@ -1893,13 +1877,6 @@ hipError_t launch_stage_b(const StageArgs* args, const unsigned* start, int n, u
                           hipStream_t s) {
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_stage_b, dim3(total), dim3(kPassThreads), 0, s, args, start, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_mask_b(const MaskArgs* args, const unsigned* start, int n, unsigned total,
-                         hipStream_t s) {
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mask_b, dim3(total), dim3(256), 0, s, args, start, n);
   return hipGetLastError();
 }
 

@@ -283,7 +283,6 @@ void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy, bool 
       Level& F = ws->lv[l];
       Level& Cl = ws->lv[l + 1];
       Cl.cur = 0;
-      R.timed(INPAINT_K_PYRAMID, l, [&] { return launch_mask_down(F.v, F.c, Cl.v, Cl.c, R.s); });
       R.timed(INPAINT_K_PYRAMID, l, [&] {
         return launch_rhs_down(F.v, F.c, F.b, Cl.v, Cl.c, Cl.b, C,
                                R.o.rhs == INPAINT_RHS_NAIVE ? 1 : 0, R.prec(), l == 0 ? 1 : 0, R.s);
