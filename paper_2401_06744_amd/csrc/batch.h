@@ -146,6 +146,8 @@ void build(Plan& P, const std::vector<Member*>& ms, Body&& body) {
   std::vector<std::array<long long, 3>> before;
   for (Member* m : ms) before.push_back({m->R->oras_iters, m->R->block_solves, m->R->finest_block_solves});
   body();
+  for (Member* m : ms)
+    if (m->R->pending()) fail(INPAINT_E_DEVICE, "a deferred update has no prolongation to take it");
   P.delta.clear();
   P.cur0.clear();
   for (size_t i = 0; i < ms.size(); ++i) {

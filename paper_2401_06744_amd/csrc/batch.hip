@@ -237,9 +237,16 @@ void step_final(Plan& P, const std::vector<Member*>& ms, bool blocks) {
 
 // One ORAS iteration on level l of every member in ms (need: a later launch
 // reads the norm its update writes).
+// One ORAS iteration on level l.  defer: its new iterate is read only by the
+// next prolongation from level l, which adds the block corrections itself
+// (no update pass).
 void step_oras(Plan& P, const std::vector<Member*>& ms, int l, bool check, bool rest,
-               bool need = true) {
+               bool need = true, bool defer = false) {
   step_block(P, ms, l);
+  if (defer) {
+    for (Member* m : ms) m->R->defer_update(l);
+    return;
+  }
   P.begin(S_PASS, -1, l);
   for (Member* m : ms) {
     const PassArgs a = m->R->make_update(l, check, rest, need);
@@ -311,9 +318,11 @@ void build_vcycle(Plan& P, const std::vector<Member*>& ms, int l0, const Opts& o
       P.add_pass(a, work_pass(a, m->C));
     }
     P.end();
-    // on coarser levels the last post-smoothing's norm is not read
+    // on coarser levels the last post-smoothing's norm is not read, and its
+    // update is left to the next prolongation
     for (int i = 0; i < o.post; ++i)
-      step_oras(P, plain, l, l == 0 && i == o.post - 1, false, l == 0 || i + 1 < o.post);
+      step_oras(P, plain, l, l == 0 && i == o.post - 1, false, l == 0 || i + 1 < o.post,
+                l > 0 && i + 1 == o.post);
     if (corr.empty()) continue;
     // precision form: the correction e of the float32 iterate gets the coarse
     // correction and the post-smoothing; the last update adds e to u and tests
@@ -359,7 +368,7 @@ void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
     if (o.schedule == INPAINT_SCHED_FMG)
       build_vcycle(P, part, l, o);
     else
-      step_oras(P, part, l, false, false, false);
+      step_oras(P, part, l, false, false, false, true);
   }
 }
 

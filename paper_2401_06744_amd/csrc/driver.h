@@ -169,6 +169,9 @@ struct Run {
   long block_solves = 0;
   long long finest_block_solves = 0;
   int top = 0;  // level whose b holds known values (a solution problem); coarser ones hold corrections
+  // Level whose last ORAS update is left to the next prolongation from it
+  // (its result is read by nothing else), per level.
+  bool pend[kMaxLevels] = {};
   struct Rec { int cls; hipEvent_t a, b; };
   std::vector<Rec> recs;
   size_t next_ev = 0;
@@ -372,6 +375,22 @@ struct Run {
     return a;
   }
 
+  // The update half of an ORAS iteration on level l >= 1 whose new iterate
+  // only the next prolongation from level l reads (no residual, no norm):
+  // that prolongation adds the block corrections itself.
+  void defer_update(int l) {
+    Level& L = ws->lv[l];
+    if (l == 0 || pend[l]) fail(INPAINT_E_DEVICE, "update cannot be deferred");
+    pend[l] = true;
+    ++oras_iters;
+    block_solves += (long)L.v.nbx * L.v.nby * C;
+  }
+  bool pending() const {
+    for (bool p : pend)
+      if (p) return true;
+    return false;
+  }
+
   PassArgs make_prolong(int l, int mode, bool check, bool need = true) {
     Level& L = ws->lv[l];
     const Level& Lc = ws->lv[l + 1];
@@ -385,6 +404,11 @@ struct Run {
       L.ezero = true;
     }
     a.uc = Lc.u[Lc.cur];
+    if (pend[l + 1]) {
+      a.ccontrib = Lc.contrib;
+      a.clv = Lc.v;
+      pend[l + 1] = false;
+    }
     // the coarse field is a solution in the cascade and a correction in a V-cycle
     a.s_uc = mode == PASS_PSOL ? sc_one() : sc_err();
     a.Wc = Lc.v.W;

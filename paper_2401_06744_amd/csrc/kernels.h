@@ -111,6 +111,11 @@ struct PassArgs {
   const void* uc;        // PASS_PSOL/PCORR: coarse field [C][Hc][Pc]
   int Wc, Hc, Pc;
   size_t planec;
+  // PASS_PSOL/PCORR: when not null, the coarse field still lacks the update of
+  // its last ORAS iteration: the prolongation reads uc + the weighted block
+  // corrections ccontrib of the coarse level (geometry clv, scale s_contrib),
+  // rounded to the coarse field's type as the update pass would have stored it.
+  const void* ccontrib;
   NormOut norm;
   const int* active;     // [C] or nullptr: skip channels already converged
   // PASS_UPD with rest != 0: instead of writing the fine residual and its norm,

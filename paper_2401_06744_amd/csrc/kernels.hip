@@ -754,6 +754,32 @@ struct Former {
   }
 };
 
+// Coarse value (X, Y) read by a prolongation whose coarse level's last ORAS
+// update was left to it: u + the (up to four) weighted block corrections of
+// the coarse level, added in the order of the update pass, and rounded to the
+// coarse field's type and scale as that pass would have stored it.
+template <class TC>
+__device__ __forceinline__ float coarse_updated(const PassArgs& a, const Fld<TC>& uc, int ch, int X, int Y) {
+  const LevelView& cl = a.clv;
+  const int B = cl.B, o = cl.o, S = B - o;
+  const float rS = 1.0f / (float)S;
+  const Fld<TC> cb(a.ccontrib, (size_t)ch * ((size_t)cl.nbx * cl.nby * B * B), a.s_contrib, a.rho, ch);
+  const BlockAxis ax = block_axis(X, S, rS, o, cl.nbx);
+  const BlockAxis ay = block_axis(Y, S, rS, o, cl.nby);
+  const int cx1 = ax.b1 * B * B + ax.l1;
+  const int cx0 = ax.h0 ? (ax.b1 - 1) * B * B + ax.l1 + S : cx1;
+  const int ry1 = ay.b1 * cl.nbx * B * B + ay.l1 * B;
+  const int ry0 = ay.h0 ? (ay.b1 - 1) * cl.nbx * B * B + (ay.l1 + S) * B : ry1;
+  const float d00 = cb.ld(ry0 + cx0), d01 = cb.ld(ry0 + cx1);
+  const float d10 = cb.ld(ry1 + cx0), d11 = cb.ld(ry1 + cx1);
+  const float d = (((ay.h0 && ax.h0 ? d00 : 0.0f) + (ay.h0 ? d01 : 0.0f)) + (ax.h0 ? d10 : 0.0f)) + d11;
+  const float un = uc.ld(Y * a.Pc + X) + d;
+  if constexpr (is_f32<TC>())
+    return un;
+  else
+    return (float)(TC)(un * uc.inv) * uc.s;
+}
+
 // One fused grid pass over a 64x32 tile of one channel.
 //   phase 1: the new iterate on the tile plus a 1-pixel halo, into LDS.  A halo
 //            pixel outside the image takes the value of the pixel it mirrors,
@@ -820,7 +846,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
       for (int i = threadIdx.x; i < kCoarseW * kCoarseH; i += kPassThreads) {
         const int py = i / kCoarseW, px = i - py * kCoarseW;
         const int X = min(cx0 + px, a.Wc - 1), Y = min(cy0 + py, a.Hc - 1);
-        cp[py][px] = F.uc.ld(Y * a.Pc + X);
+        cp[py][px] = a.ccontrib ? coarse_updated<TC>(a, F.uc, ch, X, Y) : F.uc.ld(Y * a.Pc + X);
       }
       F.cpatch = &cp[0][0];
       F.cx0 = cx0;
