@@ -380,6 +380,7 @@ void build_cycle(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
 }
 
 void add_gather(Plan& P, const std::vector<Member*>& ms, int* flags_dev) {
+  if (!flags_dev) return;  // a batch of one polls its own flag block
   P.begin(S_GATHER);
   for (Member* m : ms) P.add(GatherArgs{(const int*)m->ws->relres, flags_dev + kFlagInts * m->slot}, 1u);
   P.end();
@@ -804,7 +805,10 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
   // prepare: staging and hierarchies; members whose data is rejected leave
   HIPCHK(hipEventRecord(c.ev0, s));
   Plan prep;
-  build(prep, all, [&] { build_prepare(prep, all, o, c.flags_dev); });
+  // A batch of one reads its workspace's flag block directly: no gather launches.
+  int* const gather_to = n == 1 ? nullptr : c.flags_dev;
+  const void* const flags_src = n == 1 ? (const void*)all[0]->ws->relres : (const void*)c.flags_dev;
+  build(prep, all, [&] { build_prepare(prep, all, o, gather_to); });
   upload({&prep}, &c.call_dev, &c.call_cap, s);
   HIPCHK(issue(prep, prec, B, s, prof));
   // With plans cached for every member and the cycle count of the last solve
@@ -819,7 +823,7 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
     live = all;
     live_key = all_live;
   } else {
-    HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)n * kFlagInts * sizeof(int),
+    HIPCHK(hipMemcpyAsync(c.flags_host, flags_src, (size_t)n * kFlagInts * sizeof(int),
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (Member* m : all) {
@@ -837,7 +841,7 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
       c.live_key = live_key;
       build(c.cascade, live, [&] {
         build_cascade(c.cascade, live, o);
-        add_gather(c.cascade, live, c.flags_dev);
+        add_gather(c.cascade, live, gather_to);
       });
       const std::vector<int> s0 = level_state(live);
       c.ncycle = 0;
@@ -845,7 +849,7 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
         Plan& P = c.cycle[k];
         build(P, live, [&] {
           build_cycle(P, live, o);
-          add_gather(P, live, c.flags_dev);
+          add_gather(P, live, gather_to);
         });
         c.ncycle = k + 1;
         if (level_state(live) == s0) break;
@@ -864,7 +868,7 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
       run_plan(P, prec, B, s);
       seq.push_back(&P);
     }
-    HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)n * kFlagInts * sizeof(int),
+    HIPCHK(hipMemcpyAsync(c.flags_host, flags_src, (size_t)n * kFlagInts * sizeof(int),
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (ahead) {
@@ -889,7 +893,7 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
         run_plan(P, prec, B, s);
       seq.push_back(&P);
       ++cycles;
-      HIPCHK(hipMemcpyAsync(c.flags_host, c.flags_dev, (size_t)n * kFlagInts * sizeof(int),
+      HIPCHK(hipMemcpyAsync(c.flags_host, flags_src, (size_t)n * kFlagInts * sizeof(int),
                             hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       done = apply_counted(c.flags_host, live, seq);
