@@ -60,7 +60,11 @@ typedef enum inpaint_schedule {
                                    iteration per coarse level, then V-cycles on the finest */
   INPAINT_SCHED_FMG = 1,        /* full FMG: one V-cycle on every level of the cascade */
   INPAINT_SCHED_MULTILEVEL = 2, /* cascade, then plain ORAS iterations on the finest */
-  INPAINT_SCHED_SINGLE = 3      /* ORAS iterations on the finest grid only, from C f */
+  INPAINT_SCHED_SINGLE = 3,     /* ORAS iterations on the finest grid only, from C f */
+  INPAINT_SCHED_CG = 4          /* comparison: plain conjugate gradients on the finest grid
+                                   from C f (no multigrid, no domain decomposition), float32
+                                   only; a "cycle" is 8 CG iterations and a convergence test on
+                                   the float64 true residual */
 } inpaint_schedule;
 
 typedef enum inpaint_rhs_restriction {
@@ -82,7 +86,8 @@ typedef struct inpaint_opts {
   int max_local_iters; /* cap on local CG iterations per block (default 16) */
   int schedule;        /* inpaint_schedule (default INPAINT_SCHED_RFMG) */
   int max_cycles;      /* cap on V-cycles (or finest ORAS iterations for MULTILEVEL and
-                          SINGLE); default 30 for RFMG/FMG, 2000 otherwise */
+                          SINGLE, or blocks of 8 CG iterations for CG); default 30 for
+                          RFMG/FMG, 500 for CG, 2000 otherwise */
   int pre_smooth;      /* ORAS iterations before the coarse correction, at most 16
                           (0 = default 1; a negative value = none) */
   int post_smooth;     /* ORAS iterations after it (0 = default 1; negative = none) */

@@ -22,7 +22,7 @@ OK, NOT_CONVERGED, PENDING = 0, 1, 2
 E_INVALID, E_EMPTY_MASK, E_NOMEM, E_DEVICE, E_DIVERGED = -1, -2, -3, -4, -5
 KERNELS = ["stage", "pyramid", "block_solve", "update", "prolong", "restrict", "coarse",
            "residual", "output"]
-SCHED_RFMG, SCHED_FMG, SCHED_MULTILEVEL, SCHED_SINGLE = 0, 1, 2, 3
+SCHED_RFMG, SCHED_FMG, SCHED_MULTILEVEL, SCHED_SINGLE, SCHED_CG = 0, 1, 2, 3, 4
 RHS_MODIFIED, RHS_NAIVE = 0, 1
 PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
 

@@ -22,6 +22,8 @@ enum StepKind : int {
   S_COARSE,
   S_OUTPUT,
   S_GATHER,
+  S_CG_DIR,
+  S_CG_STEP,
 };
 
 // One batched launch: n argument structs and n + 1 work offsets, stored at

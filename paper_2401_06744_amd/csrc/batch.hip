@@ -116,6 +116,8 @@ int kernel_class(const Step& st) {
     case S_RESTRICT: return INPAINT_K_RESTRICT;
     case S_COARSE: return INPAINT_K_COARSE;
     case S_OUTPUT: return INPAINT_K_OUTPUT;
+    case S_CG_DIR:
+    case S_CG_STEP: return INPAINT_K_UPDATE;  // the CG schedule's iteration
     case S_PASS:
       switch (st.mode) {
         case PASS_RES: return INPAINT_K_RESIDUAL;
@@ -184,6 +186,8 @@ hipError_t issue_step(const Step& st, const unsigned char* dev, int prec, int B,
         e = launch_coarse_b((const CoarseArgs*)a, start, st.n, st.total, prec, st.f32, B, s);
         break;
       case S_OUTPUT: e = launch_output_b((const OutputArgs*)a, start, st.n, st.total, s); break;
+      case S_CG_DIR: e = launch_cg_dir_b((const CgArgs*)a, start, st.n, st.total, s); break;
+      case S_CG_STEP: e = launch_cg_step_b((const CgArgs*)a, start, st.n, st.total, s); break;
       default: e = hipErrorInvalidValue;
     }
     return e;
@@ -341,7 +345,40 @@ void build_vcycle(Plan& P, const std::vector<Member*>& ms, int l0, const Opts& o
 }  // namespace
 
 // The coarse-to-fine initial guess (Section 4.2) of every member.
+// Plain CG (comparison schedule): the true residual with the convergence
+// test, then iterations of the direction and step passes.
+void step_cg_residual(Plan& P, const std::vector<Member*>& ms) {
+  P.begin(S_PASS, -1, 0);
+  for (Member* m : ms) {
+    const PassArgs a = m->R->make_cg_residual();
+    P.add_pass(a, work_pass(a, m->C));
+  }
+  P.end();
+}
+
+void step_cg(Plan& P, const std::vector<Member*>& ms, bool first) {
+  P.begin(S_CG_DIR, 0, 0);
+  for (Member* m : ms) {
+    const CgArgs a = m->R->make_cg_dir(first);
+    P.add(a, work_cg(a, m->C));
+  }
+  P.end();
+  P.begin(S_CG_STEP, 0, 0);
+  for (Member* m : ms) {
+    const CgArgs a = m->R->make_cg_step();
+    P.add(a, work_cg(a, m->C));
+  }
+  P.end();
+}
+
+constexpr int kCgPerCycle = 8;
+
 void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
+  if (o.schedule == INPAINT_SCHED_CG) {
+    step_cg_residual(P, ms);
+    step_cg(P, ms, true);
+    return;
+  }
   if (o.schedule == INPAINT_SCHED_SINGLE) {
     step_residual(P, ms);
     return;
@@ -373,10 +410,14 @@ void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
 }
 
 void build_cycle(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
-  if (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG)
+  if (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG) {
     build_vcycle(P, ms, 0, o);
-  else
+  } else if (o.schedule == INPAINT_SCHED_CG) {
+    for (int i = 0; i < kCgPerCycle; ++i) step_cg(P, ms, false);
+    step_cg_residual(P, ms);
+  } else {
     step_oras_checked(P, ms);
+  }
 }
 
 void add_gather(Plan& P, const std::vector<Member*>& ms, int* flags_dev) {
@@ -394,6 +435,8 @@ std::vector<int> level_state(const std::vector<Member*>& ms) {
     for (int l = 0; l < m->ws->L; ++l) s.push_back(m->ws->lv[l].cur);
     s.push_back(m->ws->lv[0].ecur);
     s.push_back(m->ws->lv[0].ezero);
+    s.push_back(m->R->cg_slot);
+    s.push_back(m->R->cg_p);
   }
   return s;
 }
@@ -664,6 +707,7 @@ void init_member(Member& m, const inpaint_problem& p, Workspace* ws, const Opts&
   m.R.reset(new Run{m.ws, o, s, m.C, tol});
   const bool fd = is_device_ptr(p.f), md = is_device_ptr(p.mask), od = is_device_ptr(p.out);
   if (!fd || !md || !od) ensure_staging(m.ws);
+  if (o.schedule == INPAINT_SCHED_CG) ensure_cg(m.ws);
   const size_t nf = (size_t)m.W * m.H * m.C * sizeof(float);
   m.f_d = p.f;
   m.m_d = p.mask;
@@ -687,7 +731,8 @@ void init_member(Member& m, const inpaint_problem& p, Workspace* ws, const Opts&
 // its reference residual, build the coarse masks and known values level by
 // level, gather the flags (the input checks).
 void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* flags_dev) {
-  const bool single = o.schedule == INPAINT_SCHED_SINGLE;
+  // single-level schedules need no pyramid and start from u = C f
+  const bool single = o.schedule == INPAINT_SCHED_SINGLE || o.schedule == INPAINT_SCHED_CG;
   P.begin(S_RESET);
   for (Member* m : ms) P.add(ResetArgs{m->ws->active, m->ws->status, m->ws->checks, m->ws->cgstat, m->C}, 1u);
   P.end();

@@ -122,6 +122,12 @@ struct Workspace {
   float* f_dev = nullptr;
   uint8_t* m_dev = nullptr;
   float* o_dev = nullptr;
+  // plain CG (comparison schedule, allocated on first use): two directions, A p,
+  // and per channel r.r in two slots and p.q
+  void* cg_base = nullptr;
+  float* cg_p[2] = {nullptr, nullptr};
+  float* cg_q = nullptr;
+  double* cgs = nullptr;  // [3][C]
   // pinned readback
   void* host = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -153,6 +159,8 @@ size_t workspace_bytes(const Key& k);
 void acquire(Lease& lease, int W, int H, int C, int B, int o, int coarsest, int prec = PREC_F32);
 // Device buffers for host-memory inputs and outputs (allocated on first use).
 void ensure_staging(Workspace* ws);
+// Buffers of the CG schedule (directions, A p, scalars); allocated once.
+void ensure_cg(Workspace* ws);
 bool is_device_ptr(const void* p);
 
 // ---------------------------------------------------------------------------
@@ -172,6 +180,8 @@ struct Run {
   // Level whose last ORAS update is left to the next prolongation from it
   // (its result is read by nothing else), per level.
   bool pend[kMaxLevels] = {};
+  // CG schedule: slot of the current r.r in ws->cgs, buffer of the current direction
+  int cg_slot = 0, cg_p = 0;
   struct Rec { int cls; hipEvent_t a, b; };
   std::vector<Rec> recs;
   size_t next_ev = 0;
@@ -441,6 +451,56 @@ struct Run {
       block_solves += (long)L.v.nbx * L.v.nby * C;
       finest_block_solves += (long long)L.v.nbx * L.v.nby * C;
     }
+    return a;
+  }
+
+  // ---- plain CG on the finest grid (comparison schedule)
+
+  // Float64 true residual r = b - A x with the convergence test.  It replaces
+  // the recurrence's r of the same iterate, and its norm replaces that r.r in
+  // the current slot (the iteration does not advance: the next direction's
+  // beta divides by the r.r of the previous iterate).
+  PassArgs make_cg_residual() {
+    PassArgs a = make_residual(0, true);
+    a.norm.out = ws->cgs + (size_t)cg_slot * C;
+    return a;
+  }
+  CgArgs cg_args() const {
+    const Level& L = ws->lv[0];
+    CgArgs a{};
+    a.lv = L.v;
+    a.c = L.c;
+    a.x = L.u[L.cur];
+    a.r = L.r;
+    a.q = ws->cg_q;
+    a.active = ws->active;
+    return a;
+  }
+  // p = r + beta p (p = r when first), q = A p, p.q
+  CgArgs make_cg_dir(bool first) {
+    CgArgs a = cg_args();
+    a.p_in = ws->cg_p[cg_p];
+    a.p_out = ws->cg_p[cg_p ^ 1];
+    cg_p ^= 1;
+    a.rho = ws->cgs + (size_t)cg_slot * C;
+    a.rho_old = ws->cgs + (size_t)(cg_slot ^ 1) * C;
+    a.first = first ? 1 : 0;
+    a.norm = norm(0, false);
+    a.norm.mode = NORM_FULL;
+    a.norm.out = ws->cgs + 2 * (size_t)C;
+    return a;
+  }
+  // x += alpha p, r -= alpha q, r.r into the next slot
+  CgArgs make_cg_step() {
+    CgArgs a = cg_args();
+    a.p_in = ws->cg_p[cg_p];
+    a.rho = ws->cgs + (size_t)cg_slot * C;
+    a.pq = ws->cgs + 2 * (size_t)C;
+    cg_slot ^= 1;
+    a.norm = norm(0, false);
+    a.norm.mode = NORM_FULL;
+    a.norm.out = ws->cgs + (size_t)cg_slot * C;
+    ++oras_iters;
     return a;
   }
 

@@ -16,6 +16,11 @@ constexpr int kMaxLevels = 24;
 // Tile of the grid passes: 64 columns x 32 rows, 256 threads (8 rows each).
 constexpr int kTileW = 64;
 constexpr int kTileH = 32;
+// Bit pattern of an unset norm partial: a NaN with a payload no arithmetic
+// produces (partials may be negative: CG's p.q), compared bit for bit.
+constexpr unsigned long long kUnsetPartialBits = 0xFFF7C0FFEE5E7A11ull;
+inline double unset_partial() { return __builtin_bit_cast(double, kUnsetPartialBits); }
+
 // Ints per flag block of a problem: relres[4] doubles, active[4], status[4],
 // checks[4] ints, spare.  One block is copied to the host per poll.
 constexpr int kFlagInts = 32;
@@ -61,7 +66,7 @@ struct NormOut {
   int mode;
   double* dpart;      // NORM_DEFER: [C][dstride]
   int dstride;
-  double* partials;   // [C][ntiles], every entry < 0 (unset) between passes
+  double* partials;   // [C][ntiles], every entry kUnsetPartial between passes
   unsigned* counter;  // [C][kCounterLines][32]: 64 group counters + 1 total, one
                       // 128-byte line each, all 0 between passes
   int* status;        // bit 2 (value 4) set if a partial never arrived
@@ -203,6 +208,27 @@ struct RhsArgs {
   int C, naive;
 };
 
+// Plain conjugate gradients on the finest grid (the comparison schedule): the
+// direction pass p = r + beta p, q = A p and p.q, then the step pass
+// x += alpha p, r -= alpha q and r.r.  A is the masked 5-point operator
+// (identity rows at known pixels, where r, p and q are 0); scalars are
+// float64 per channel, fields float32.
+struct CgArgs {
+  LevelView lv;
+  const uint8_t* c;
+  float* x;
+  float* r;
+  const float* p_in;      // direction pass: previous direction (not read when first); step: p
+  float* p_out;           // direction pass: new direction
+  float* q;               // A p
+  const double* rho;      // [C] current r.r
+  const double* rho_old;  // [C] previous r.r (direction pass)
+  const double* pq;       // [C] p.q (step pass)
+  int first;              // direction pass: p = r
+  const int* active;
+  NormOut norm;           // p.q (direction pass) or r.r (step pass)
+};
+
 struct OutputArgs {
   LevelView lv;
   const uint8_t* c;
@@ -240,6 +266,11 @@ hipError_t launch_coarse_b(const CoarseArgs* args, const unsigned* start, int n,
                            int prec, int level0, int B, hipStream_t s);
 hipError_t launch_output_b(const OutputArgs* args, const unsigned* start, int n, unsigned total,
                            hipStream_t s);
+unsigned work_cg(const CgArgs& a, int C);
+hipError_t launch_cg_dir_b(const CgArgs* args, const unsigned* start, int n, unsigned total,
+                           hipStream_t s);
+hipError_t launch_cg_step_b(const CgArgs* args, const unsigned* start, int n, unsigned total,
+                            hipStream_t s);
 
 // Launchers (all enqueue on `s`, return hipError_t of the launch).
 // Stage f and mask into level 0 (b = C f, c, and u = C f when u != nullptr),

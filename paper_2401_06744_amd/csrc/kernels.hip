@@ -320,11 +320,16 @@ __device__ __forceinline__ void rhs_body(const RhsArgs& a, unsigned lin) {
 // through to the coherent level) and then increments a per-channel counter
 // with an agent-scope atomic.  The workgroup that sees the count reach
 // ntiles - 1 reads the partials with agent-scope atomic loads; an entry is
-// "unset" while negative (partials are sums of squares), so it waits for the
-// few that may still be in flight, adds them in index order (a result that does
-// not depend on which workgroup came last), resets every entry to -1 and the
-// counter to 0 for the next pass, and runs the optional convergence test.
+// "unset" while it holds the kUnsetPartialBits pattern (a NaN payload that no
+// arithmetic produces; partials may be negative), so it waits for the few that
+// may still be in flight, adds them in index order (a result that does not
+// depend on which workgroup came last), resets every entry to the pattern and
+// the counter to 0 for the next pass, and runs the optional convergence test.
 constexpr int kSpinBudget = 1 << 20;
+
+__device__ __forceinline__ bool unset(double v) {
+  return (unsigned long long)__builtin_bit_cast(long long, v) == kUnsetPartialBits;
+}
 
 __device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, const NormOut& no) {
   constexpr int NW = kPassThreads / kWave;
@@ -383,12 +388,12 @@ __device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, 
     for (int j = 0; j < U; ++j) {
       const unsigned i = base + j * kPassThreads;
       if (i >= ntiles) continue;
-      while (v[j] < 0.0 && spins < kSpinBudget) {
+      while (unset(v[j]) && spins < kSpinBudget) {
         __builtin_amdgcn_s_sleep(1);
         ++spins;
         v[j] = __hip_atomic_load(part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      if (v[j] < 0.0) {
+      if (unset(v[j])) {
         lost = true;
         v[j] = 0.0;
       }
@@ -397,7 +402,9 @@ __device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, 
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const unsigned i = base + j * kPassThreads;
-      if (i < ntiles) __hip_atomic_store(part + i, -1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (i < ntiles)
+        __hip_atomic_store(part + i, __builtin_bit_cast(double, kUnsetPartialBits), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   s = wave_sum_d(s);
@@ -465,7 +472,7 @@ __global__ void __launch_bounds__(kPassThreads) k_cg_stats(LevelView lv, const i
   }
 }
 
-// Sets every norm partial to -1 ("unset") once per workspace.
+// Sets every norm partial to the unset pattern once per workspace.
 __global__ void k_fill(double* p, size_t n, double v) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -980,6 +987,121 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
           acc += (double)vf * (double)vf;
         }
       }
+    }
+  }
+  reduce_norm(acc, ch, tile, ntiles, a.norm);
+}
+
+// ---------------------------------------------------------------------------
+// plain conjugate gradients on the finest grid (comparison schedule)
+// ---------------------------------------------------------------------------
+
+// Direction pass over a 64x32 tile: p = r + beta p on the tile and a one-pixel
+// halo (a halo pixel outside the image mirrors its neighbour, so the 5-point
+// stencil sees the reflecting boundary), then q = A p at the tile's unknown
+// pixels (0 at known ones), p.q per channel.
+__device__ __forceinline__ void cg_dir_body(const CgArgs& a, unsigned lin) {
+  constexpr int TW = kTileW + 2, TH = kTileH + 2;
+  constexpr int NG = kPassThreads / kTileW;
+  constexpr int RJ = (TH + NG - 1) / NG;
+  constexpr int RK = kTileH / NG;
+  const LevelView& lv = a.lv;
+  const unsigned tiles_x = (unsigned)((lv.W + kTileW - 1) / kTileW);
+  const unsigned ntiles = tiles_x * (unsigned)((lv.H + kTileH - 1) / kTileH);
+  const int ch = lin / ntiles;
+  const unsigned tile = lin - (unsigned)ch * ntiles;
+  const bool act = channel_active(a.active, ch);
+  const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
+  __shared__ float t[TH][TW];
+  const size_t po = (size_t)ch * lv.plane;
+  const gptr<const float> r = glb((const float*)a.r + po);
+  const gptr<const float> pin = glb((a.first ? (const float*)a.r : a.p_in) + po);
+  const float beta = a.first ? 0.0f : (float)(glb(a.rho)[ch] / glb(a.rho_old)[ch]);
+  const int c = threadIdx.x & (kTileW - 1), g = threadIdx.x / kTileW;
+  const int gx = x0 + c, gxc = min(gx, lv.W - 1);
+  uint8_t mk[RK];
+#pragma unroll
+  for (int k = 0; k < RK; ++k) mk[k] = glb(a.c)[min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc];
+  float rv[RJ], pv[RJ];
+#pragma unroll
+  for (int j = 0; j < RJ; ++j) {
+    const int ty = min(g + NG * j, TH - 1);
+    const int off = min(max(y0 - 1 + ty, 0), lv.H - 1) * lv.P + gxc;
+    rv[j] = r[off];
+    pv[j] = pin[off];
+  }
+  float hr = 0.0f, hp = 0.0f;
+  const int side = threadIdx.x / TH, hty = threadIdx.x - side * TH;
+  if (threadIdx.x < 2 * TH) {
+    const int hx = side == 0 ? max(x0 - 1, 0) : min(x0 + kTileW, lv.W - 1);
+    const int off = min(max(y0 - 1 + hty, 0), lv.H - 1) * lv.P + hx;
+    hr = r[off];
+    hp = pin[off];
+  }
+  if (!act) return;  // the whole workgroup: one channel
+#pragma unroll
+  for (int j = 0; j < RJ; ++j) {
+    const int ty = g + NG * j;
+    if (ty < TH) t[ty][c + 1] = a.first ? rv[j] : rv[j] + beta * pv[j];
+  }
+  if (threadIdx.x < 2 * TH) t[hty][side == 0 ? 0 : TW - 1] = a.first ? hr : hr + beta * hp;
+  __syncthreads();
+  const size_t base = po;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < RK; ++k) {
+    const int ty = g * RK + k, gy = y0 + ty;
+    if (gx < lv.W && gy < lv.H) {
+      const float p = t[ty + 1][c + 1];
+      const float nb = (t[ty + 1][c] + t[ty + 1][c + 2]) + (t[ty][c + 1] + t[ty + 2][c + 1]);
+      const float q = mk[k] ? 0.0f : 4.0f * p - nb;
+      const size_t off = base + (size_t)gy * lv.P + gx;
+      glb(a.p_out)[off] = p;
+      glb(a.q)[off] = q;
+      acc += (double)p * (double)q;
+    }
+  }
+  reduce_norm(acc, ch, tile, ntiles, a.norm);
+}
+
+// Step pass over the same tiles: x += alpha p, r -= alpha q, r.r per channel.
+__device__ __forceinline__ void cg_step_body(const CgArgs& a, unsigned lin) {
+  constexpr int NG = kPassThreads / kTileW;
+  constexpr int RK = kTileH / NG;
+  const LevelView& lv = a.lv;
+  const unsigned tiles_x = (unsigned)((lv.W + kTileW - 1) / kTileW);
+  const unsigned ntiles = tiles_x * (unsigned)((lv.H + kTileH - 1) / kTileH);
+  const int ch = lin / ntiles;
+  const unsigned tile = lin - (unsigned)ch * ntiles;
+  const bool act = channel_active(a.active, ch);
+  const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
+  const int c = threadIdx.x & (kTileW - 1), g = threadIdx.x / kTileW;
+  const int gx = x0 + c, gxc = min(gx, lv.W - 1);
+  const size_t po = (size_t)ch * lv.plane;
+  const gptr<float> x = glb(a.x + po), r = glb(a.r + po);
+  const gptr<const float> p = glb(a.p_in + po), q = glb((const float*)a.q + po);
+  const double pq = glb(a.pq)[ch];
+  const float alpha = pq > 0.0 ? (float)(glb(a.rho)[ch] / pq) : 0.0f;
+  float xv[RK], rv[RK], pv[RK], qv[RK];
+#pragma unroll
+  for (int k = 0; k < RK; ++k) {
+    const int off = min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc;
+    xv[k] = x[off];
+    rv[k] = r[off];
+    pv[k] = p[off];
+    qv[k] = q[off];
+  }
+  if (!act) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < RK; ++k) {
+    const int gy = y0 + g * RK + k;
+    if (gx < lv.W && gy < lv.H) {
+      const int off = gy * lv.P + gx;
+      const float rn = rv[k] - alpha * qv[k];
+      x[off] = xv[k] + alpha * pv[k];
+      r[off] = rn;
+      acc += (double)rn * (double)rn;
     }
   }
   reduce_norm(acc, ch, tile, ntiles, a.norm);
@@ -1756,6 +1878,17 @@ __global__ void __launch_bounds__(kWave) k_coarse_b(const CoarseArgs* __restrict
   coarse_body<B, T>(a, g - start[p]);
 }
 
+__global__ void __launch_bounds__(kPassThreads) k_cg_dir_b(const CgArgs* __restrict__ args,
+                                                         const unsigned* __restrict__ start, int n) {
+  INPAINT_BATCH_LOOKUP(CgArgs)
+  cg_dir_body(a, lin);
+}
+__global__ void __launch_bounds__(kPassThreads) k_cg_step_b(const CgArgs* __restrict__ args,
+                                                          const unsigned* __restrict__ start, int n) {
+  INPAINT_BATCH_LOOKUP(CgArgs)
+  cg_step_body(a, lin);
+}
+
 #undef INPAINT_BATCH_LOOKUP
 
 dim3 px_grid(int W, int H) { return dim3((W + 63) / 64, (H + 3) / 4); }
@@ -1990,6 +2123,22 @@ hipError_t launch_output_b(const OutputArgs* args, const unsigned* start, int n,
                            hipStream_t s) {
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_output_b, dim3(total), dim3(256), 0, s, args, start, n);
+  return hipGetLastError();
+}
+
+unsigned work_cg(const CgArgs& a, int C) { return (unsigned)pass_tiles(a.lv) * (unsigned)C; }
+
+hipError_t launch_cg_dir_b(const CgArgs* args, const unsigned* start, int n, unsigned total,
+                           hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_dir_b, dim3(total), dim3(kPassThreads), 0, s, args, start, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_step_b(const CgArgs* args, const unsigned* start, int n, unsigned total,
+                            hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_step_b, dim3(total), dim3(kPassThreads), 0, s, args, start, n);
   return hipGetLastError();
 }
 

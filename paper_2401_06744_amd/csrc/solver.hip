@@ -44,15 +44,19 @@ Opts resolve(const inpaint_opts* p) {
   if (!(o.gamma > 0.0f && o.gamma <= 1.0f)) fail(INPAINT_E_INVALID, "gamma must lie in (0, 1]");
   if (!(o.tau >= 0.0f) || !std::isfinite(o.tau)) fail(INPAINT_E_INVALID, "tau must be finite and >= 0");
   if (o.maxit < 0 || o.coarse_maxit < 0) fail(INPAINT_E_INVALID, "iteration caps must be >= 0");
-  if (o.schedule < INPAINT_SCHED_RFMG || o.schedule > INPAINT_SCHED_SINGLE)
+  if (o.schedule < INPAINT_SCHED_RFMG || o.schedule > INPAINT_SCHED_CG)
     fail(INPAINT_E_INVALID, "unknown schedule");
+  if (o.schedule == INPAINT_SCHED_CG && o.prec != PREC_F32)
+    fail(INPAINT_E_INVALID, "the CG schedule runs in float32 only");
   if (o.rhs != INPAINT_RHS_MODIFIED && o.rhs != INPAINT_RHS_NAIVE)
     fail(INPAINT_E_INVALID, "unknown rhs_restriction");
   if (o.pre > 16 || o.post > 16) fail(INPAINT_E_INVALID, "smoothing counts must be at most 16");
   if (!(o.coarse_tau >= 0.0f)) fail(INPAINT_E_INVALID, "coarse_tau must be >= 0");
   if (o.max_cycles < 0) fail(INPAINT_E_INVALID, "max_cycles must be >= 0");
   if (o.max_cycles == 0)
-    o.max_cycles = (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG) ? 30 : 2000;
+    o.max_cycles = (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG) ? 30
+                   : o.schedule == INPAINT_SCHED_CG                                       ? 500
+                                                                                          : 2000;
   return o;
 }
 
@@ -62,6 +66,7 @@ Workspace::~Workspace() {
     (void)hipSetDevice(key.dev);
     if (base) (void)hipFree(base);
     if (stage_base) (void)hipFree(stage_base);
+    if (cg_base) (void)hipFree(cg_base);
     if (host) (void)hipHostFree(host);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
@@ -168,7 +173,7 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
   ws->partials = (double*)(base + o_part);
   ws->counters = (unsigned*)(base + o_cnt);
   HIPCHK(hipMemset(ws->counters, 0, (size_t)C * kCounterLines * 32 * sizeof(unsigned)));
-  HIPCHK(launch_fill(ws->partials, (size_t)C * maxtiles, -1.0, nullptr));
+  HIPCHK(launch_fill(ws->partials, (size_t)C * maxtiles, unset_partial(), nullptr));
   HIPCHK(hipDeviceSynchronize());
   ws->snorm = (double*)(base + o_sn);
   ws->den = (double*)(base + o_den);
@@ -229,6 +234,18 @@ void ensure_staging(Workspace* ws) {
   ws->f_dev = (float*)ws->stage_base;
   ws->o_dev = (float*)((char*)ws->stage_base + fb);
   ws->m_dev = (uint8_t*)((char*)ws->stage_base + 2 * fb);
+}
+
+void ensure_cg(Workspace* ws) {
+  if (ws->cg_base) return;
+  const Level& L0 = ws->lv[0];
+  const size_t fb = round_up((size_t)ws->key.C * L0.v.plane * sizeof(float), 256);
+  HIPCHK(hipMalloc(&ws->cg_base, 3 * fb + 256));
+  char* b = (char*)ws->cg_base;
+  ws->cg_p[0] = (float*)b;
+  ws->cg_p[1] = (float*)(b + fb);
+  ws->cg_q = (float*)(b + 2 * fb);
+  ws->cgs = (double*)(b + 3 * fb);
 }
 
 bool is_device_ptr(const void* p) {

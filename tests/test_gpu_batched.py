@@ -26,23 +26,29 @@ def _mix(seed=0):
     return probs
 
 
+def _tol(kw):
+    # plain FP32 CG stalls between 1e-6 and 1e-5 on the 1-2 % masks of this mix
+    # (rounding of its updates against |u|), so it is held to 1e-5 here
+    return 1e-5 if kw.get("schedule") == binding.SCHED_CG else TOL
+
+
 def _solo(probs, **kw):
     opts = binding.make_opts(**kw) if kw else None
-    return [binding.inpaint_solve_ex(f, m, TOL, opts=opts)[0] for f, m in probs]
+    return [binding.inpaint_solve_ex(f, m, _tol(kw), opts=opts)[0] for f, m in probs]
 
 
 @pytest.mark.parametrize("kw", [
     {}, {"schedule": binding.SCHED_FMG}, {"schedule": binding.SCHED_MULTILEVEL},
     {"schedule": binding.SCHED_SINGLE}, {"pre_smooth": 2, "post_smooth": -1},
     {"pre_smooth": -1, "post_smooth": 2}, {"block": 16, "overlap": 4},
-    {"precision": binding.PREC_FP16}, {"precision": binding.PREC_BF16},
+    {"precision": binding.PREC_FP16}, {"precision": binding.PREC_BF16}, {"schedule": binding.SCHED_CG},
 ])
 def test_batched_equals_solo_bitwise(kw):
     probs = _mix()
     if kw.get("schedule") == binding.SCHED_SINGLE:
         probs = [probs[0], probs[2], probs[4], probs[6]]
     opts = binding.make_opts(**kw) if kw else None
-    outs, st, stats = binding.inpaint_solve_batched(probs, TOL, opts=opts)
+    outs, st, stats = binding.inpaint_solve_batched(probs, _tol(kw), opts=opts)
     assert st == binding.OK
     solo = _solo(probs, **kw)
     for k, (o, s) in enumerate(zip(outs, solo)):

@@ -118,6 +118,12 @@ def test_server_errors_and_rejections():
         binding.inpaint_server_destroy(srv)
 
 
+def test_server_rejects_the_cg_schedule():
+    with pytest.raises(binding.InpaintError) as e:
+        binding.inpaint_server_create(opts=binding.make_opts(schedule=binding.SCHED_CG))
+    assert e.value.code == binding.E_INVALID
+
+
 def test_destroy_finishes_submitted_requests():
     reqs = _reqs(4, seed=100)
     outs = [np.zeros_like(f) for f, _ in reqs]

@@ -74,6 +74,33 @@ def test_local_residuals_reaching_subnormal_range():
     assert np.all(rr <= TOL), rr
 
 
+CG_TOL = 1e-5
+
+
+@pytest.mark.parametrize("W,H,C,dens,seed", [
+    (77, 53, 1, 0.05, 1), (300, 17, 3, 0.05, 4), (129, 257, 2, 0.02, 5), (1, 100, 1, 0.1, 6),
+    (256, 256, 1, 0.05, 2),
+])
+def test_cg_schedule_matches_oracle(W, H, C, dens, seed):
+    """The comparison schedule (plain CG on the finest grid) reaches the oracle's
+    solution within the 0.5 grey-level bound.  Its gate is 1e-5: in FP32, CG's
+    updates round away against |u| once the relative residual nears 1e-6 (more
+    so the sparser the mask), so it can stall between 1e-6 and 1e-5."""
+    f = synth.frame_image(W, H, C, seed=seed)
+    m = synth.bernoulli_mask(W, H, dens, seed=seed + 100)
+    out, st, stats = _solve(f, m, tol=CG_TOL, schedule=binding.SCHED_CG)
+    assert st == binding.OK
+    assert stats["cycles"] >= 1 and stats["oras_iters"] == C * (8 * stats["cycles"] + 1)
+    _check(out, f, m, rr_tol=CG_TOL)
+
+
+def test_cg_schedule_is_float32_only():
+    f, m = synth.config_small()
+    with pytest.raises(binding.InpaintError) as e:
+        _solve(f, m, schedule=binding.SCHED_CG, precision=binding.PREC_FP16)
+    assert e.value.code == binding.E_INVALID
+
+
 def test_single_pixel_and_all_known():
     f = synth.plain_image(40, 30, seed=3)
     m = np.zeros((30, 40), np.uint8)
