@@ -18,9 +18,10 @@ Legs:
              batched    64 uneven problems: one at a time (plain float32) vs one
                         autotuned batched solve
              solvers    the 4K frame under reduced full multigrid, full multigrid,
-                        multilevel ORAS and plain float32 CG, at rel-res 1e-3 and 1e-6
+                        multilevel ORAS, plain float32 CG and the multilevel and
+                        multigrid CG counterparts, at rel-res 1e-3 and 1e-6
              sweeps     resolution 480x270 ... 4K at 5 % and density 0.5-10 % at 4K,
-                        the method vs multilevel ORAS vs CG at rel-res 1e-3
+                        the ORAS solvers vs the CG ones at rel-res 1e-3
              serving    Poisson arrivals of 720p/1080p/4K RGB requests at fixed QPS
                         and a saturating burst: frames/s, p50/p99 latency, vs the
                         same requests solved one at a time
@@ -458,31 +459,39 @@ def precision_leg(binding, torch, synth, args, fd4, md4, pending):
 def solvers_leg(binding, torch, args, fd, md, pending):
     """The headline frame under each schedule: reduced full multigrid (the
     method), full multigrid, multilevel ORAS (coarse-to-fine start, no
-    V-cycles) and plain float32 CG on the finest grid, at rel-res 1e-3 (the
+    V-cycles), plain float32 CG on the finest grid and the multilevel and
+    multigrid CG counterparts (CG in place of ORAS), at rel-res 1e-3 (the
     stopping rule of the paper's runtime comparison) and at the headline 1e-6
-    for the method and CG (CG's status and rel-res are reported as they come:
-    in float32 it can stall near 1e-6)."""
+    for the method, CG and multigrid CG (CG's status and rel-res are reported
+    as they come: in float32 it can stall near 1e-6)."""
     scheds = [("rfmg", binding.SCHED_RFMG), ("fmg", binding.SCHED_FMG),
-              ("multilevel", binding.SCHED_MULTILEVEL), ("cg", binding.SCHED_CG)]
+              ("multilevel", binding.SCHED_MULTILEVEL), ("cg", binding.SCHED_CG),
+              ("cg_multilevel", binding.SCHED_CG_MULTILEVEL),
+              ("cg_multigrid", binding.SCHED_CG_MULTIGRID)]
     out = {"workload": "3840x2160 RGB frame (seed 10), 4 % Bernoulli mask; max error on "
                        "channel 0 against the oracle"}
     od = torch.empty_like(fd)
-    for tol, names in ((1e-3, [n for n, _ in scheds]), (args.tol, ["rfmg", "cg"])):
+    for tol, names in ((1e-3, [n for n, _ in scheds]), (args.tol, ["rfmg", "cg", "cg_multigrid"])):
         row = {}
         for name, sc in scheds:
             if name not in names:
                 continue
             o = binding.make_opts(schedule=sc)
-            reps = 3 if sc == binding.SCHED_CG else max(5, args.steps // 2)
+            reps = 3 if name.startswith("cg") else max(5, args.steps // 2)
             sec = _timed(torch, lambda: binding.inpaint_solve_ex(fd, md, tol, out=od, opts=o), reps)
             _, st, stats = binding.inpaint_solve_ex(fd, md, tol, out=od, opts=o)
             rr = binding.inpaint_rel_res(od, fd, md)
             row[name] = {"fps": round(1.0 / sec, 2), "ms": round(1e3 * sec, 3), "status": st,
                          "cycles": stats["cycles"], "rel_res_max": float(rr.max())}
-            if sc == binding.SCHED_CG:
+            if name.startswith("cg"):
                 row[name]["cg_iterations"] = stats["oras_iters"] // fd.shape[0]
             pending[f"solvers/tol_{tol:g}/{name}"] = (("4k", args.density), od[0].cpu().numpy())
+        # the paper's pairs: each ORAS solver against its CG counterpart
         row["rfmg_over_cg"] = round(row["rfmg"]["fps"] / row["cg"]["fps"], 2)
+        row["rfmg_over_cg_multigrid"] = round(row["rfmg"]["fps"] / row["cg_multigrid"]["fps"], 2)
+        if "multilevel" in row:
+            row["multilevel_over_cg_multilevel"] = round(
+                row["multilevel"]["fps"] / row["cg_multilevel"]["fps"], 2)
         out[f"tol_{tol:g}"] = row
     return out
 
@@ -491,8 +500,8 @@ def sweep_leg(binding, torch, synth, args, fd4):
     """The paper's two runtime sweeps on synthetic stand-ins, at its stopping
     rule (rel-res 1e-3) and at 1e-6: RGB frames of 480x270 to 3840x2160 with a
     5 % Bernoulli mask (resolution scaling), and the 4K frame with 0.5-10 %
-    Bernoulli masks (density scaling), under the method, multilevel ORAS and
-    float32 CG."""
+    Bernoulli masks (density scaling), under the method, multilevel ORAS,
+    float32 CG and the multilevel and multigrid CG counterparts."""
     out = {"workload": "RGB frames (seed 10) 480x270 ... 3840x2160 with a 5 % Bernoulli mask "
                        "(seed 20), and the 4K frame with 0.5/1/2/5/10 % Bernoulli masks (seed 40); "
                        "rel-res 1e-3 unless named"}
@@ -500,7 +509,7 @@ def sweep_leg(binding, torch, synth, args, fd4):
     def run(fd, md, tol, sc):
         o = binding.make_opts(schedule=sc)
         od = torch.empty_like(fd)
-        reps = 2 if sc == binding.SCHED_CG else 4
+        reps = 2 if sc in (binding.SCHED_CG, binding.SCHED_CG_MULTILEVEL) else 4
         sec = _timed(torch, lambda: binding.inpaint_solve_ex(fd, md, tol, out=od, opts=o), reps)
         _, st, stats = binding.inpaint_solve_ex(fd, md, tol, out=od, opts=o)
         return {"ms": round(1e3 * sec, 3), "fps": round(1.0 / sec, 1), "status": st,
@@ -513,7 +522,9 @@ def sweep_leg(binding, torch, synth, args, fd4):
         res[f"{W}x{H}"] = {"rfmg": run(fd, md, 1e-3, binding.SCHED_RFMG),
                            "rfmg_1e-6": run(fd, md, args.tol, binding.SCHED_RFMG),
                            "multilevel": run(fd, md, 1e-3, binding.SCHED_MULTILEVEL),
-                           "cg": run(fd, md, 1e-3, binding.SCHED_CG)}
+                           "cg": run(fd, md, 1e-3, binding.SCHED_CG),
+                           "cg_multilevel": run(fd, md, 1e-3, binding.SCHED_CG_MULTILEVEL),
+                           "cg_multigrid": run(fd, md, 1e-3, binding.SCHED_CG_MULTIGRID)}
     out["resolution_5pct"] = res
     res = {}
     for d in (0.005, 0.01, 0.02, 0.05, 0.10):
@@ -521,7 +532,9 @@ def sweep_leg(binding, torch, synth, args, fd4):
         res[f"{d:g}"] = {"rfmg": run(fd4, md, 1e-3, binding.SCHED_RFMG),
                          "rfmg_1e-6": run(fd4, md, args.tol, binding.SCHED_RFMG),
                          "multilevel": run(fd4, md, 1e-3, binding.SCHED_MULTILEVEL),
-                         "cg": run(fd4, md, 1e-3, binding.SCHED_CG)}
+                         "cg": run(fd4, md, 1e-3, binding.SCHED_CG),
+                         "cg_multilevel": run(fd4, md, 1e-3, binding.SCHED_CG_MULTILEVEL),
+                         "cg_multigrid": run(fd4, md, 1e-3, binding.SCHED_CG_MULTIGRID)}
     out["density_4k"] = res
     return out
 

@@ -61,10 +61,17 @@ typedef enum inpaint_schedule {
   INPAINT_SCHED_FMG = 1,        /* full FMG: one V-cycle on every level of the cascade */
   INPAINT_SCHED_MULTILEVEL = 2, /* cascade, then plain ORAS iterations on the finest */
   INPAINT_SCHED_SINGLE = 3,     /* ORAS iterations on the finest grid only, from C f */
-  INPAINT_SCHED_CG = 4          /* comparison: plain conjugate gradients on the finest grid
-                                   from C f (no multigrid, no domain decomposition), float32
-                                   only; a "cycle" is 8 CG iterations and a convergence test on
-                                   the float64 true residual */
+  INPAINT_SCHED_CG = 4,         /* comparison (Section 5.1): plain conjugate gradients on the
+                                   finest grid from C f (no multigrid, no domain decomposition),
+                                   float32 only; a "cycle" is 8 CG iterations and a convergence
+                                   test on the float64 true residual */
+  INPAINT_SCHED_CG_MULTILEVEL = 5, /* comparison (Section 5.1): the MULTILEVEL cascade with CG
+                                   in place of ORAS (pre_smooth CG iterations per coarse level,
+                                   default 8), then CG on the finest grid as in SCHED_CG */
+  INPAINT_SCHED_CG_MULTIGRID = 6   /* comparison (Section 5.1): the RFMG cascade and V-cycles
+                                   with CG in place of ORAS as pre- and post-smoother
+                                   (pre_smooth / post_smooth CG iterations, default 2 each,
+                                   each smoothing restarting CG from the current residual) */
 } inpaint_schedule;
 
 typedef enum inpaint_rhs_restriction {
@@ -86,11 +93,14 @@ typedef struct inpaint_opts {
   int max_local_iters; /* cap on local CG iterations per block (default 16) */
   int schedule;        /* inpaint_schedule (default INPAINT_SCHED_RFMG) */
   int max_cycles;      /* cap on V-cycles (or finest ORAS iterations for MULTILEVEL and
-                          SINGLE, or blocks of 8 CG iterations for CG); default 30 for
-                          RFMG/FMG, 500 for CG, 2000 otherwise */
+                          SINGLE, or blocks of 8 CG iterations for CG and CG_MULTILEVEL);
+                          default 30 for RFMG/FMG/CG_MULTIGRID, 500 for CG and
+                          CG_MULTILEVEL, 2000 otherwise */
   int pre_smooth;      /* ORAS iterations before the coarse correction, at most 16
-                          (0 = default 1; a negative value = none) */
-  int post_smooth;     /* ORAS iterations after it (0 = default 1; negative = none) */
+                          (0 = default 1; a negative value = none); CG iterations for the
+                          CG_MULTILEVEL and CG_MULTIGRID schedules (default 8 and 2) */
+  int post_smooth;     /* ORAS iterations after it (0 = default 1; negative = none); CG
+                          iterations for CG_MULTIGRID (default 2) */
   int rhs_restriction; /* inpaint_rhs_restriction (default MODIFIED) */
   float coarse_tau;    /* relative stop of the CG solve on the coarsest grid, on squared
                           norms (default 1e-8) */

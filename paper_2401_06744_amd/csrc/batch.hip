@@ -345,33 +345,96 @@ void build_vcycle(Plan& P, const std::vector<Member*>& ms, int l0, const Opts& o
 }  // namespace
 
 // The coarse-to-fine initial guess (Section 4.2) of every member.
-// Plain CG (comparison schedule): the true residual with the convergence
-// test, then iterations of the direction and step passes.
-void step_cg_residual(Plan& P, const std::vector<Member*>& ms) {
-  P.begin(S_PASS, -1, 0);
+// Plain CG (comparison schedules): the true residual of level l (with the
+// convergence test on the finest grid), and iterations of the direction and
+// step passes.
+void step_cg_residual(Plan& P, const std::vector<Member*>& ms, int l = 0, bool check = true) {
+  P.begin(S_PASS, -1, l);
   for (Member* m : ms) {
-    const PassArgs a = m->R->make_cg_residual();
+    const PassArgs a = m->R->make_cg_residual(l, check);
     P.add_pass(a, work_pass(a, m->C));
   }
   P.end();
 }
 
-void step_cg(Plan& P, const std::vector<Member*>& ms, bool first) {
-  P.begin(S_CG_DIR, 0, 0);
+void step_cg(Plan& P, const std::vector<Member*>& ms, bool first, int l = 0) {
+  P.begin(S_CG_DIR, 0, l);
   for (Member* m : ms) {
-    const CgArgs a = m->R->make_cg_dir(first);
+    const CgArgs a = m->R->make_cg_dir(l, first);
     P.add(a, work_cg(a, m->C));
   }
   P.end();
-  P.begin(S_CG_STEP, 0, 0);
+  P.begin(S_CG_STEP, 0, l);
   for (Member* m : ms) {
-    const CgArgs a = m->R->make_cg_step();
+    const CgArgs a = m->R->make_cg_step(l);
     P.add(a, work_cg(a, m->C));
   }
   P.end();
 }
 
+// n CG iterations on level l, restarted from the residual the previous pass
+// left there (the problem changed: a prolongation or a restriction).
+void smooth_cg(Plan& P, const std::vector<Member*>& ms, int l, int n) {
+  for (int i = 0; i < n; ++i) step_cg(P, ms, i == 0, l);
+}
+
+// A prolongation to level l of every member in ms whose residual norm starts
+// the CG smoothing of level l.
+void step_cg_prolong(Plan& P, const std::vector<Member*>& ms, int l, int mode, bool check) {
+  P.begin(S_PASS, -1, l);
+  for (Member* m : ms) {
+    const PassArgs a = m->R->make_cg_prolong(l, mode, check);
+    P.add_pass(a, work_pass(a, m->C));
+  }
+  P.end();
+}
+
 constexpr int kCgPerCycle = 8;
+
+// The multigrid CG counterpart's V-cycle: the ORAS V-cycle's structure with
+// CG as pre- and post-smoother on every level; the residual after
+// pre-smoothing is evaluated in float64 and restricted by the plain
+// restriction.
+void build_vcycle_cg(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
+  const int maxLc = max_coarsest(ms);
+  for (int l = 0; l < maxLc; ++l) {
+    const auto part = subset(ms, [&](Member* m) { return l < m->Lc(); });
+    smooth_cg(P, part, l, o.pre);
+    P.begin(S_PASS, -1, l);
+    for (Member* m : part) {
+      const PassArgs a = m->R->make_cg_pre_residual(l);
+      P.add_pass(a, work_pass(a, m->C));
+    }
+    P.end();
+    P.begin(S_RESTRICT, 0, l);
+    for (Member* m : part) {
+      const RestrictArgs a = m->R->make_cg_restrict(l);
+      P.add(a, work_restrict(a, m->C), a.level0);
+    }
+    P.end();
+  }
+  P.begin(S_COARSE, 0, maxLc);
+  for (Member* m : ms)
+    if (m->Lc() > 0) {
+      const CoarseArgs a = m->R->make_coarse(m->Lc(), true);
+      P.add(a, work_coarse(a, m->C), a.level0);
+    }
+  P.end();
+  const auto flat = subset(ms, [](Member* m) { return m->Lc() == 0; });
+  P.begin(S_COARSE, 0, 0);
+  for (Member* m : flat) {
+    const CoarseArgs a = m->R->make_coarse(0, false);
+    P.add(a, work_coarse(a, m->C), a.level0);
+  }
+  P.end();
+  step_cg_residual(P, flat);
+  for (int l = maxLc - 1; l >= 0; --l) {
+    const auto part = subset(ms, [&](Member* m) { return l < m->Lc(); });
+    step_cg_prolong(P, part, l, PASS_PCORR, l == 0 && o.post == 0);
+    smooth_cg(P, part, l, o.post);
+    if (l == 0 && o.post > 0) step_cg_residual(P, part);
+  }
+}
 
 void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
   if (o.schedule == INPAINT_SCHED_CG) {
@@ -383,7 +446,12 @@ void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
     step_residual(P, ms);
     return;
   }
-  step_residual(P, subset(ms, [](Member* m) { return m->Lc() == 0; }));
+  const bool cg = cg_schedule(o.schedule);
+  const auto flat = subset(ms, [](Member* m) { return m->Lc() == 0; });
+  if (cg)
+    step_cg_residual(P, flat);
+  else
+    step_residual(P, flat);
   const auto deep = subset(ms, [](Member* m) { return m->Lc() > 0; });
   P.begin(S_COARSE, 0, max_coarsest(deep));
   for (Member* m : deep) {
@@ -394,9 +462,15 @@ void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
   P.end();
   for (int l = max_coarsest(deep) - 1; l >= 0; --l) {
     const auto part = subset(deep, [&](Member* m) { return l < m->Lc(); });
+    for (Member* m : part) m->R->top = l;
+    if (cg) {
+      step_cg_prolong(P, part, l, PASS_PSOL, l == 0);
+      if (l == 0) break;
+      smooth_cg(P, part, l, o.pre);
+      continue;
+    }
     P.begin(S_PASS, -1, l);
     for (Member* m : part) {
-      m->R->top = l;
       const PassArgs a = m->R->make_prolong(l, PASS_PSOL, l == 0);
       P.add_pass(a, work_pass(a, m->C));
     }
@@ -407,12 +481,16 @@ void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
     else
       step_oras(P, part, l, false, false, false, true);
   }
+  // the multilevel CG counterpart continues with plain CG on the finest grid
+  if (o.schedule == INPAINT_SCHED_CG_MULTILEVEL) step_cg(P, ms, true);
 }
 
 void build_cycle(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
   if (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG) {
     build_vcycle(P, ms, 0, o);
-  } else if (o.schedule == INPAINT_SCHED_CG) {
+  } else if (o.schedule == INPAINT_SCHED_CG_MULTIGRID) {
+    build_vcycle_cg(P, ms, o);
+  } else if (cg_schedule(o.schedule)) {
     for (int i = 0; i < kCgPerCycle; ++i) step_cg(P, ms, false);
     step_cg_residual(P, ms);
   } else {
@@ -707,7 +785,7 @@ void init_member(Member& m, const inpaint_problem& p, Workspace* ws, const Opts&
   m.R.reset(new Run{m.ws, o, s, m.C, tol});
   const bool fd = is_device_ptr(p.f), md = is_device_ptr(p.mask), od = is_device_ptr(p.out);
   if (!fd || !md || !od) ensure_staging(m.ws);
-  if (o.schedule == INPAINT_SCHED_CG) ensure_cg(m.ws);
+  if (cg_schedule(o.schedule)) ensure_cg(m.ws);
   const size_t nf = (size_t)m.W * m.H * m.C * sizeof(float);
   m.f_d = p.f;
   m.m_d = p.mask;

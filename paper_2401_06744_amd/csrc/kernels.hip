@@ -1016,7 +1016,10 @@ __device__ __forceinline__ void cg_dir_body(const CgArgs& a, unsigned lin) {
   const size_t po = (size_t)ch * lv.plane;
   const gptr<const float> r = glb((const float*)a.r + po);
   const gptr<const float> pin = glb((a.first ? (const float*)a.r : a.p_in) + po);
-  const float beta = a.first ? 0.0f : (float)(glb(a.rho)[ch] / glb(a.rho_old)[ch]);
+  // A level whose pixels are all known (coarse levels of a dense mask) has
+  // r = 0 and r.r = 0: then beta = 0 keeps p = 0 instead of 0/0.
+  const double rho_old = a.first ? 0.0 : glb(a.rho_old)[ch];
+  const float beta = rho_old > 0.0 ? (float)(glb(a.rho)[ch] / rho_old) : 0.0f;
   const int c = threadIdx.x & (kTileW - 1), g = threadIdx.x / kTileW;
   const int gx = x0 + c, gxc = min(gx, lv.W - 1);
   uint8_t mk[RK];

@@ -295,7 +295,7 @@ INPAINT_EXPORT int inpaint_server_create(const inpaint_server_cfg* cfg, inpaint_
     std::unique_ptr<inpaint_server> sv(new inpaint_server());
     sv->o = resolve(cfg && cfg->opts.struct_size ? &cfg->opts : nullptr);
     sv->o.profile = 0;
-    if (sv->o.schedule == INPAINT_SCHED_CG)
+    if (cg_schedule(sv->o.schedule))
       fail(INPAINT_E_INVALID, "the server runs the multigrid schedules (CG is a comparison schedule)");
     if (cfg && cfg->max_batch) sv->max_batch = cfg->max_batch;
     if (sv->max_batch < 1 || sv->max_batch > 1024) fail(INPAINT_E_INVALID, "max_batch must lie in [1, 1024]");

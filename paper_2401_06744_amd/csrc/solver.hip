@@ -44,19 +44,26 @@ Opts resolve(const inpaint_opts* p) {
   if (!(o.gamma > 0.0f && o.gamma <= 1.0f)) fail(INPAINT_E_INVALID, "gamma must lie in (0, 1]");
   if (!(o.tau >= 0.0f) || !std::isfinite(o.tau)) fail(INPAINT_E_INVALID, "tau must be finite and >= 0");
   if (o.maxit < 0 || o.coarse_maxit < 0) fail(INPAINT_E_INVALID, "iteration caps must be >= 0");
-  if (o.schedule < INPAINT_SCHED_RFMG || o.schedule > INPAINT_SCHED_CG)
+  if (o.schedule < INPAINT_SCHED_RFMG || o.schedule > INPAINT_SCHED_CG_MULTIGRID)
     fail(INPAINT_E_INVALID, "unknown schedule");
-  if (o.schedule == INPAINT_SCHED_CG && o.prec != PREC_F32)
-    fail(INPAINT_E_INVALID, "the CG schedule runs in float32 only");
+  if (cg_schedule(o.schedule) && o.prec != PREC_F32)
+    fail(INPAINT_E_INVALID, "the CG schedules run in float32 only");
+  if (o.schedule == INPAINT_SCHED_CG_MULTILEVEL || o.schedule == INPAINT_SCHED_CG_MULTIGRID) {
+    const int nu = o.schedule == INPAINT_SCHED_CG_MULTILEVEL ? kCgSmoothMultilevel : kCgSmoothMultigrid;
+    if (!p || !p->pre_smooth) o.pre = nu;
+    if (!p || !p->post_smooth) o.post = nu;
+  }
   if (o.rhs != INPAINT_RHS_MODIFIED && o.rhs != INPAINT_RHS_NAIVE)
     fail(INPAINT_E_INVALID, "unknown rhs_restriction");
   if (o.pre > 16 || o.post > 16) fail(INPAINT_E_INVALID, "smoothing counts must be at most 16");
   if (!(o.coarse_tau >= 0.0f)) fail(INPAINT_E_INVALID, "coarse_tau must be >= 0");
   if (o.max_cycles < 0) fail(INPAINT_E_INVALID, "max_cycles must be >= 0");
   if (o.max_cycles == 0)
-    o.max_cycles = (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG) ? 30
-                   : o.schedule == INPAINT_SCHED_CG                                       ? 500
-                                                                                          : 2000;
+    o.max_cycles = (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG ||
+                    o.schedule == INPAINT_SCHED_CG_MULTIGRID)
+                       ? 30
+                   : cg_schedule(o.schedule) ? 500
+                                             : 2000;
   return o;
 }
 

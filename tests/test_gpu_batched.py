@@ -29,7 +29,8 @@ def _mix(seed=0):
 def _tol(kw):
     # plain FP32 CG stalls between 1e-6 and 1e-5 on the 1-2 % masks of this mix
     # (rounding of its updates against |u|), so it is held to 1e-5 here
-    return 1e-5 if kw.get("schedule") == binding.SCHED_CG else TOL
+    cg = (binding.SCHED_CG, binding.SCHED_CG_MULTILEVEL, binding.SCHED_CG_MULTIGRID)
+    return 1e-5 if kw.get("schedule") in cg else TOL
 
 
 def _solo(probs, **kw):
@@ -42,6 +43,7 @@ def _solo(probs, **kw):
     {"schedule": binding.SCHED_SINGLE}, {"pre_smooth": 2, "post_smooth": -1},
     {"pre_smooth": -1, "post_smooth": 2}, {"block": 16, "overlap": 4},
     {"precision": binding.PREC_FP16}, {"precision": binding.PREC_BF16}, {"schedule": binding.SCHED_CG},
+    {"schedule": binding.SCHED_CG_MULTILEVEL}, {"schedule": binding.SCHED_CG_MULTIGRID},
 ])
 def test_batched_equals_solo_bitwise(kw):
     probs = _mix()

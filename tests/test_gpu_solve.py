@@ -94,10 +94,44 @@ def test_cg_schedule_matches_oracle(W, H, C, dens, seed):
     _check(out, f, m, rr_tol=CG_TOL)
 
 
+@pytest.mark.parametrize("sched", ["CG_MULTILEVEL", "CG_MULTIGRID"])
+@pytest.mark.parametrize("W,H,C,dens,seed", [
+    (77, 53, 1, 0.05, 1), (300, 17, 3, 0.05, 4), (129, 257, 2, 0.02, 5), (1, 100, 1, 0.1, 6),
+    (20, 24, 1, 0.2, 7), (256, 256, 1, 0.05, 2), (2048, 64, 1, 0.04, 8),
+])
+def test_cg_counterparts_match_oracle(sched, W, H, C, dens, seed):
+    """The multilevel and multigrid CG counterparts (CG in place of ORAS in
+    the same cascade and V-cycles; 20x24 is a single-level problem) reach the
+    oracle's solution, held to the same gate as plain CG.  On 2048x64 the
+    max-pooled masks of the deepest levels are fully known, so CG there starts
+    from r = 0."""
+    f = synth.frame_image(W, H, C, seed=seed)
+    m = synth.bernoulli_mask(W, H, dens, seed=seed + 100)
+    out, st, stats = _solve(f, m, tol=CG_TOL, schedule=getattr(binding, "SCHED_" + sched))
+    assert st == binding.OK
+    _check(out, f, m, rr_tol=CG_TOL)
+
+
+@pytest.mark.parametrize("sched", ["CG_MULTILEVEL", "CG_MULTIGRID"])
+@pytest.mark.parametrize("nu", [1, 2, 8])
+def test_cg_counterparts_smoothing_counts(sched, nu):
+    """Any number of CG iterations per smoothing, on a frame deep enough
+    (960x540, six levels) that its coarse levels are fully known."""
+    f = synth.frame_image(960, 540, 1, seed=9)
+    m = synth.bernoulli_mask(960, 540, 0.04, seed=109)
+    out, st, stats = _solve(f, m, tol=CG_TOL, schedule=getattr(binding, "SCHED_" + sched),
+                            pre_smooth=nu, post_smooth=nu)
+    assert st == binding.OK
+    _check(out, f, m, rr_tol=CG_TOL)
+
+
 def test_cg_schedule_is_float32_only():
     f, m = synth.config_small()
     with pytest.raises(binding.InpaintError) as e:
         _solve(f, m, schedule=binding.SCHED_CG, precision=binding.PREC_FP16)
+    assert e.value.code == binding.E_INVALID
+    with pytest.raises(binding.InpaintError) as e:
+        _solve(f, m, schedule=binding.SCHED_CG_MULTIGRID, precision=binding.PREC_BF16)
     assert e.value.code == binding.E_INVALID
 
 
