@@ -482,7 +482,7 @@ __global__ void k_fill(double* p, size_t n, double v) {
 // staging of the finest level
 // ---------------------------------------------------------------------------
 
-// One 64x16 tile of one channel: b = C f, c and (optionally) u = C f for the
+// One 64x32 tile of one channel: b = C f, c and (optionally) u = C f for the
 // tile, input checks, and the residual of C f (the reference residual of the
 // relative residual):  at an unknown pixel it is the sum of the known
 // neighbours' values, at a known pixel 0.

@@ -54,3 +54,22 @@ def test_opts_struct_layout_matches_header():
                                                    + 4 + 4 + 3 * 8)
     assert ctypes.sizeof(binding.InpaintProblem) == 8 + 8 + 3 * 4 + 4 + 8
     assert ctypes.sizeof(binding.InpaintServerCfg) == 4 + 4 + 8 + 15 * 4 + 4
+
+
+def test_binding_constants_match_the_header():
+    """Every status, schedule, restriction and precision value of the header
+    has the same value under the binding's name for it."""
+    src = ""
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src += re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+    consts = {m.group(1): int(m.group(2)) for m in re.finditer(r"\bINPAINT_(\w+)\s*=\s*(-?\d+)", src)}
+    checked = 0
+    for name, value in consts.items():
+        if name.startswith(("K_", "NUM_")):
+            continue
+        assert getattr(binding, name) == value, name
+        checked += 1
+    assert checked >= 20
+    assert len(binding.KERNELS) == consts["NUM_KERNELS"]
+    for i, k in enumerate(binding.KERNELS):
+        assert consts["K_" + k.upper()] == i, k

@@ -118,9 +118,10 @@ def test_server_errors_and_rejections():
         binding.inpaint_server_destroy(srv)
 
 
-def test_server_rejects_the_cg_schedule():
+@pytest.mark.parametrize("sched", ["CG", "CG_MULTILEVEL", "CG_MULTIGRID"])
+def test_server_rejects_the_cg_schedules(sched):
     with pytest.raises(binding.InpaintError) as e:
-        binding.inpaint_server_create(opts=binding.make_opts(schedule=binding.SCHED_CG))
+        binding.inpaint_server_create(opts=binding.make_opts(schedule=getattr(binding, "SCHED_" + sched)))
     assert e.value.code == binding.E_INVALID
 
 
