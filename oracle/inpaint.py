@@ -377,8 +377,9 @@ def restrict_residual(r: np.ndarray, c_coarse: np.ndarray) -> np.ndarray:
     4.1 and 4.4) and keeps ``L`` scaled by ``1/h^2`` with ``H = 2h``.  Written
     with the integer stencil ``h^2 L`` on every level, the coarse right-hand
     side is ``H^2/h^2 = 4`` times the mean of the existing children.  It is 0
-    at coarse mask pixels, where the coarse error is 0.
-    parity unpinned (scaling reading): only the 2x2 mean itself is pinned.
+    at coarse mask pixels, where the coarse error is 0.  The factor is pinned
+    by two-grid consistency: for a quadratic error the restricted fine
+    residual equals the coarse residual of the same function.
     """
     r = np.asarray(r, dtype=np.float64)
     cc = np.asarray(c_coarse) != 0

@@ -119,3 +119,30 @@ def test_restrict_residual_closed_forms():
     r2 = np.arange(9 * 12, dtype=np.float64).reshape(9, 12)
     out2 = oracle.restrict_residual(r2, np.zeros((5, 6), np.uint8))
     assert out2[4, 0] == pytest.approx(4.0 * (r2[8, 0] + r2[8, 1]) / 2)
+
+
+@pytest.mark.parametrize("coef", [(1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.3, -0.7, 0.5), (2.0, 1.5, -1.0)])
+def test_restricted_residual_is_the_coarse_residual_of_a_quadratic(coef):
+    """Two-grid consistency, independent of the restriction's own definition:
+    for a quadratic error e(x, y) (pixel-centre coordinates, cell-centred
+    grids, so a coarse centre sits at fine coordinate 2X + 1/2), the fine
+    integer-stencil residual of e, restricted, equals the coarse
+    integer-stencil residual of e sampled at the coarse centres.  The
+    quadratic part makes the fine residual a constant -2(a + b); on the
+    coarse grid the same function is 4 times as curved per cell, so any
+    other factor than 4 (reading A2: H^2/h^2) fails."""
+    a, b, c = coef
+    Hf, Wf = 24, 32
+
+    def e(x, y):
+        return a * x * x + b * y * y + c * x * y + 0.25 * x - 3.0 * y + 1.0
+
+    yf, xf = np.mgrid[0:Hf, 0:Wf].astype(np.float64)
+    Yc, Xc = np.mgrid[0:Hf // 2, 0:Wf // 2].astype(np.float64)
+    rf = oracle.apply_L(e(xf, yf))
+    rc = oracle.apply_L(e(2 * Xc + 0.5, 2 * Yc + 0.5))
+    out = oracle.restrict_residual(rf, np.zeros((Hf // 2, Wf // 2), np.uint8))
+    # interior coarse cells: their children and the children's neighbours are
+    # inside the image, where the reflecting boundary does not enter
+    np.testing.assert_allclose(out[1:-1, 1:-1], rc[1:-1, 1:-1], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(rc[1:-1, 1:-1], -8.0 * (a + b), rtol=0, atol=1e-9)
