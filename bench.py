@@ -182,9 +182,9 @@ def main() -> int:
                     help="also run a plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "frames and requests shard across GPUs without communication, see DESIGN.md",
-              file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU (asked for --gpus {args.gpus}); frames and "
+              "requests would shard across GPUs without communication, one process per GPU, "
+              "which is not implemented", file=sys.stderr)
         return 2
     full = (args.width, args.height) == (3840, 2160)
     forms = not args.no_forms and full

@@ -150,6 +150,20 @@ def test_single_pixel_and_all_known():
     assert s1 == binding.OK and o1[0, 0, 0] == 5.0
 
 
+@pytest.mark.parametrize("sched", ["CG", "CG_MULTILEVEL", "CG_MULTIGRID"])
+def test_cg_schedules_all_known_and_one_pixel(sched):
+    """Degenerate inputs of the comparison schedules: with every pixel known
+    the residual and every CG scalar are 0 from the start (no 0/0 may leak
+    into the output), and a 1x1 image is its own coarsest level."""
+    kw = {"schedule": getattr(binding, "SCHED_" + sched)}
+    f = synth.plain_image(40, 30, seed=3)
+    out1, st1, _ = _solve(f, np.ones((30, 40), np.uint8), tol=CG_TOL, **kw)
+    assert st1 == binding.OK and np.array_equal(out1, f)
+    one = np.array([[[5.0]]], np.float32)
+    o1, s1, _ = _solve(one, np.ones((1, 1), np.uint8), tol=CG_TOL, **kw)
+    assert s1 == binding.OK and o1[0, 0, 0] == 5.0
+
+
 def test_ramp_with_known_border():
     H, W = 96, 130
     y, x = np.mgrid[0:H, 0:W].astype(np.float64)
