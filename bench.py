@@ -5,7 +5,7 @@ seeded synthetic image) to a relative residual of 1e-6 through the C ABI,
 with f, mask and out resident in HBM.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--no-forms] [--serve-qps 240] [--serve-requests 2000]
+                  [--no-forms] [--serve-qps 60,120,240,480] [--serve-requests 2000]
 
 Legs:
   timed      K solves between two device synchronisations -> frames/s, p50/p99
@@ -173,7 +173,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--serve-qps", type=str, default="240")
+    ap.add_argument("--serve-qps", type=str, default="60,120,240,480")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--width", type=int, default=3840)
     ap.add_argument("--height", type=int, default=2160)
@@ -676,7 +676,8 @@ def serving_leg(binding, torch, args, pending):
         points = {}
         keep = {}
         for q in [float(x) for x in args.serve_qps.split(",") if x]:
-            r, kp = run(srv, requests(q, args.serve_requests))
+            # each point: --serve-requests arrivals, at most 8 s of them
+            r, kp = run(srv, requests(q, max(50, min(args.serve_requests, int(8 * q)))))
             points[f"{q:g}"] = r
             keep.update({j: v for j, v in kp.items() if j not in keep})
         burst_reqs = requests(1000.0, min(args.serve_requests, 600), seed=51)
