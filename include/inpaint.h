@@ -72,6 +72,10 @@ typedef enum inpaint_schedule {
                                    with CG in place of ORAS as pre- and post-smoother
                                    (pre_smooth / post_smooth CG iterations, default 2 each,
                                    each smoothing restarting CG from the current residual) */
+  /* The three CG schedules run in float32 only (another precision is E_INVALID)
+     and are not accepted by inpaint_server_create.  Float32 CG can stall with a
+     relative residual between 1e-6 and 1e-5 on sparse (1-2 %) masks: a tolerance
+     below that ends in NOT_CONVERGED at the cycle cap. */
 } inpaint_schedule;
 
 typedef enum inpaint_rhs_restriction {

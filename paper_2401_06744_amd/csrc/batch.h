@@ -132,10 +132,13 @@ struct Member {
 // Prepare: reset flags, stage (f, mask) into level 0 with the reference
 // residual, coarse masks and known values level by level, gather the flags.
 void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* flags_dev);
-// The coarse-to-fine initial guess (Section 4.2).
+// The coarse-to-fine initial guess (Section 4.2); for the CG schedules the
+// first CG step (plain CG) or the cascade with CG smoothing.
 void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o);
 // One V-cycle on the finest grid (one finest ORAS iteration for the
-// multilevel and single-level schedules).
+// multilevel and single-level schedules; 8 CG iterations and a convergence
+// test for plain and multilevel CG; a V-cycle with CG smoothing for
+// multigrid CG).
 void build_cycle(Plan& P, const std::vector<Member*>& ms, const Opts& o);
 void build_output(Plan& P, const std::vector<Member*>& ms);
 // Copy of each member's flag block to flags_dev + kFlagInts * member.slot.

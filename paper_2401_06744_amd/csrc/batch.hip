@@ -344,7 +344,6 @@ void build_vcycle(Plan& P, const std::vector<Member*>& ms, int l0, const Opts& o
 
 }  // namespace
 
-// The coarse-to-fine initial guess (Section 4.2) of every member.
 // Plain CG (comparison schedules): the true residual of level l (with the
 // convergence test on the finest grid), and iterations of the direction and
 // step passes.
@@ -436,6 +435,7 @@ void build_vcycle_cg(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
   }
 }
 
+// The coarse-to-fine initial guess (Section 4.2) of every member.
 void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
   if (o.schedule == INPAINT_SCHED_CG) {
     step_cg_residual(P, ms);
