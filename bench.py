@@ -86,11 +86,19 @@ def measured_traffic(kernel: str):
     return float(kv[key]) if key in kv else None
 
 
+def _blocks(n: int, B: int = 32, o: int = 6) -> int:
+    """ORAS blocks along an axis of n pixels (stride B - o, the last one clipped)."""
+    return max(1, -(-(n - o) // (B - o)))
+
+
 def algorithmic_bytes(cls: str, W: int, H: int, C: int) -> float:
     """Bytes one finest-grid launch of a kernel class must move (each input read
     once, each output written once; halo and overlap re-reads not counted)."""
     N = float(W * H)
     f4 = 4.0 * C * N
+    # level 1's weighted block corrections: its last update of a cycle (and of
+    # the cascade) is done by the prolongation to the finest grid
+    contrib1 = 4.0 * C * _blocks((W + 1) // 2) * _blocks((H + 1) // 2) * 32 * 32
     return {
         "block_solve": 2 * f4 + N,            # read r, mask; write D_i v_i (once per pixel)
         # read u, corrections, mask; write u and r (16C + 1 B/px: the finest grid
@@ -98,7 +106,8 @@ def algorithmic_bytes(cls: str, W: int, H: int, C: int) -> float:
         # also restricts (one per V-cycle), write u and the coarse b, u, r instead
         # of r (15C + 1.25 B/px); a launch averages the two
         "update": 0.5 * ((4 * f4 + N) + (3.75 * f4 + 1.25 * N)),
-        "prolong": 3 * f4 + f4 / 4 + N,       # read u, mask, coarse e (N/4); write u, r
+        # read u, mask, coarse e (N/4) and level 1's block corrections; write u, r
+        "prolong": 3 * f4 + f4 / 4 + N + contrib1,
         "restrict": f4 + 3 * f4 / 4 + N / 4,  # read r, coarse mask; write coarse b, u, r
         "residual": 2 * f4 + N,               # read u, mask; write r
         "stage": 2 * f4 + 2 * N,              # read f, mask; write b, mask
