@@ -306,6 +306,13 @@ def main() -> int:
         roof = {"bound": "hbm", "achieved": dk["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_frac, 4), "traffic": None, "kernel": dom}
     roof["traffic"] = measured_traffic(dom)
+    # the whole frame against HBM: algorithmic bytes of the finest-grid launches
+    # (the coarser levels add about a third more) over the frame time
+    frame_bytes = sum(k["calls_per_frame"] * k["alg_bytes_per_launch"] for k in kernels.values())
+    frame = {"alg_bytes_finest": frame_bytes,
+             "alg_GBps": round(frame_bytes * fps / 1e9, 1),
+             "hbm_frac": round(frame_bytes * fps / 1e9 / HBM_PEAK_GBS, 4),
+             "hbm_floor_ms": round(frame_bytes / (HBM_PEAK_GBS * 1e9) * 1e3, 4)}
     log(f"timed and profiled legs done: {fps:.1f} frames/s")
 
     # achievable bandwidth of a plain device copy (secondary denominator), and
@@ -412,6 +419,7 @@ def main() -> int:
         "cycles": int(np.median(cycles)),
         "local_cg_mean": round(float(np.mean(cg_mean)), 3),
         "roofline": roof,
+        "frame_roofline": frame,
         "kernels": kernels,
         "accuracy": acc,
         "forms": form_res,
