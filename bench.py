@@ -5,7 +5,8 @@ seeded synthetic image) to a relative residual of 1e-6 through the C ABI,
 with f, mask and out resident in HBM.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--no-forms] [--serve-qps 60,120,240,480] [--serve-requests 2000]
+                  [--no-forms | --forms precision,solvers,sweeps,batched,serving]
+                  [--serve-qps 60,120,240,480] [--serve-requests 2000]
 
 Legs:
   timed      K solves between two device synchronisations -> frames/s, p50/p99
@@ -182,6 +183,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--forms", type=str, default=",".join(FORM_LEGS),
+                    help="comma-separated form legs to run (default: all)")
     ap.add_argument("--serve-qps", type=str, default="60,120,240,480")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--width", type=int, default=3840)
@@ -196,7 +199,12 @@ def main() -> int:
               "which is not implemented", file=sys.stderr)
         return 2
     full = (args.width, args.height) == (3840, 2160)
-    forms = not args.no_forms and full
+    legs = [x for x in args.forms.split(",") if x]
+    for x in legs:
+        if x not in FORM_LEGS:
+            print(f"bench.py: unknown form leg {x!r} (known: {', '.join(FORM_LEGS)})", file=sys.stderr)
+            return 2
+    forms = not args.no_forms and full and bool(legs)
     check = not args.no_oracle_check
 
     # oracle worker processes, started before this process touches the GPU;
@@ -205,9 +213,12 @@ def main() -> int:
     jobs = []
     if check:
         jobs = [("4k", args.density)] if full else []
-        if forms:
-            jobs += [("prec", "bernoulli"), ("prec", "bluenoise"), ("serve", (0, 0)),
-                     ("serve", (0, 1))] + [("4kq", d) for d in QUALITY_DENSITIES]
+        if forms and "precision" in legs:
+            jobs += [("prec", "bernoulli"), ("prec", "bluenoise")]
+        if forms and "serving" in legs:
+            jobs += [("serve", (0, 0)), ("serve", (0, 1))]
+        if forms and "sweeps" in legs:
+            jobs += [("4kq", d) for d in QUALITY_DENSITIES]
     nproc = max(len(jobs), 0 if args.no_cpu_baseline else 3)
     pool = mp.get_context("spawn").Pool(nproc) if nproc else None
 
@@ -342,16 +353,21 @@ def main() -> int:
     pending = {}   # name -> (job, ch0 output) compared with the oracle below
     if forms:
         form_res = {}
-        form_res["precision"] = precision_leg(binding, torch, synth, args, fd, md, pending)
-        log("precision forms done")
-        form_res["solvers"] = solvers_leg(binding, torch, args, fd, md, pending)
-        log("solver comparison done")
-        form_res["sweeps"] = sweep_leg(binding, torch, synth, args, fd, pending)
-        log("resolution and density sweeps done")
-        form_res["batched"] = batched_leg(binding, torch, synth, args)
-        log("batched form done")
-        form_res["serving"] = serving_leg(binding, torch, args, pending)
-        log("serving form done")
+        if "precision" in legs:
+            form_res["precision"] = precision_leg(binding, torch, synth, args, fd, md, pending)
+            log("precision forms done")
+        if "solvers" in legs:
+            form_res["solvers"] = solvers_leg(binding, torch, args, fd, md, pending)
+            log("solver comparison done")
+        if "sweeps" in legs:
+            form_res["sweeps"] = sweep_leg(binding, torch, synth, args, fd, pending)
+            log("resolution and density sweeps done")
+        if "batched" in legs:
+            form_res["batched"] = batched_leg(binding, torch, synth, args)
+            log("batched form done")
+        if "serving" in legs:
+            form_res["serving"] = serving_leg(binding, torch, args, pending)
+            log("serving form done")
     if check and full:
         pending["headline"] = (("4k", args.density), out0)
 
@@ -519,6 +535,7 @@ def solvers_leg(binding, torch, args, fd, md, pending):
 
 
 QUALITY_DENSITIES = (0.005, 0.01, 0.02, 0.05, 0.10)
+FORM_LEGS = ("precision", "solvers", "sweeps", "batched", "serving")
 
 
 def sweep_leg(binding, torch, synth, args, fd4, pending):
