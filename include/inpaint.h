@@ -74,8 +74,10 @@ typedef enum inpaint_schedule {
                                    each smoothing restarting CG from the current residual) */
   /* The three CG schedules run in float32 only (another precision is E_INVALID)
      and are not accepted by inpaint_server_create.  Float32 CG can stall with a
-     relative residual between 1e-6 and 1e-5 on sparse (1-2 %) masks: a tolerance
-     below that ends in NOT_CONVERGED at the cycle cap. */
+     relative residual between 1e-6 and 1e-5 on sparse (1-2 %) masks: a CG solve
+     whose largest relative residual still above tol has not improved by 1 % in
+     16 convergence tests stops there with NOT_CONVERGED (out holds the last
+     iterate), as at the cycle cap. */
 } inpaint_schedule;
 
 typedef enum inpaint_rhs_restriction {

@@ -125,6 +125,20 @@ def test_cg_counterparts_smoothing_counts(sched, nu):
     _check(out, f, m, rr_tol=CG_TOL)
 
 
+def test_cg_schedule_stops_when_it_stalls():
+    """On a 1 % mask float32 CG stalls above 1e-6: the solve gives up after 16
+    tests without a 1 % improvement (long before the 500-cycle cap), reports
+    NOT_CONVERGED with the relative residual it reached, and its output still
+    meets the grey-level bound."""
+    f = synth.frame_image(640, 360, 1, seed=71)
+    m = synth.bernoulli_mask(640, 360, 0.01, seed=72)
+    out, st, stats = _solve(f, m, tol=TOL, schedule=binding.SCHED_CG)
+    assert st == binding.NOT_CONVERGED
+    assert 16 < stats["cycles"] < 120
+    assert TOL < stats["rel_res"] <= CG_TOL
+    _check(out, f, m, rr_tol=CG_TOL)
+
+
 def test_cg_schedule_is_float32_only():
     f, m = synth.config_small()
     with pytest.raises(binding.InpaintError) as e:
