@@ -184,6 +184,22 @@ int inpaint_solve_ex(const float* f, const uint8_t* mask, int W, int H, int chan
                      inpaint_stats* stats);
 
 /*
+ * Bound on the device memory that single and batched solves keep cached
+ * between calls: the grid hierarchy of each problem shape (block, overlap and
+ * precision) already solved is kept for the next call of that shape, and idle
+ * hierarchies are freed, least recently used first, whenever the cache would
+ * otherwise exceed the limit (at the end of a call, and before a new
+ * hierarchy is allocated).  A hierarchy in use by a call is never freed, so a
+ * single call may exceed the limit while it runs.  The default limit is
+ * 16 GiB, or INPAINT_CACHE_LIMIT_MB mebibytes when that variable is set at
+ * the first call.  Servers keep their own pool, bounded by their budget.
+ *   limit_bytes   new limit; 0 = keep the current one (and just trim)
+ *   cached_bytes  NULL, or receives the bytes still cached after trimming
+ * Always returns INPAINT_OK.
+ */
+int inpaint_cache_limit(size_t limit_bytes, size_t* cached_bytes);
+
+/*
  * Relative residual (float64, per channel, see above) of u for the problem
  * (f, mask).  u, f: [channels][H][W] float32; rel_res_out: channels doubles
  * (host memory).  Computed on the device.

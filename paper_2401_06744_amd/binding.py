@@ -33,6 +33,7 @@ EXPORTED = [
     "inpaint_debug_oras_step", "inpaint_debug_restrict", "inpaint_debug_prolong",
     "inpaint_solve_batched", "inpaint_server_create", "inpaint_server_submit",
     "inpaint_server_poll", "inpaint_server_wait", "inpaint_server_destroy", "inpaint_autotune",
+    "inpaint_cache_limit",
 ]
 
 
@@ -117,6 +118,7 @@ def lib() -> ct.CDLL:
         L.inpaint_server_wait.argtypes = [vp, ct.c_uint64, ct.POINTER(InpaintStats)]
         L.inpaint_server_destroy.argtypes = [vp]
         L.inpaint_server_destroy.restype = None
+        L.inpaint_cache_limit.argtypes = [ct.c_size_t, ct.POINTER(ct.c_size_t)]
         for name in EXPORTED:
             fn = getattr(L, name)
             if name != "inpaint_server_destroy" and (fn.restype is ct.c_int or fn.restype is None):
@@ -314,6 +316,14 @@ def inpaint_rel_res(u, f, mask) -> np.ndarray:
     res = np.zeros(C, dtype=np.float64)
     _check(lib().inpaint_rel_res(_ptr(u), _ptr(f), _ptr(mask), W, H, C, _ptr(res)))
     return res
+
+
+def inpaint_cache_limit(limit_bytes: int = 0) -> int:
+    """Set the byte limit of the solves' workspace cache (0: keep it) and
+    return the bytes still cached after trimming."""
+    n = ct.c_size_t(0)
+    _check(lib().inpaint_cache_limit(limit_bytes, ct.byref(n)))
+    return n.value
 
 
 def inpaint_last_error() -> str:

@@ -11,6 +11,7 @@
 #include <fstream>
 #include <map>
 #include <sstream>
+#include <tuple>
 
 #include "batch.h"
 
@@ -31,21 +32,66 @@ std::mutex g_tmu;
 std::map<std::string, Choice> g_tcache;
 bool g_tloaded = false;
 
-std::string signature(const inpaint_problem* p, int n, double tol, const Opts& o) {
-  std::vector<std::tuple<int, int, int>> shapes;
-  for (int i = 0; i < n; ++i) shapes.emplace_back(p[i].W, p[i].H, p[i].channels);
+// Fraction of known pixels of a mask in host or device memory.
+double mask_density(const uint8_t* m, int W, int H, hipStream_t s) {
+  const size_t n = (size_t)W * H;
+  std::vector<uint8_t> h;
+  const uint8_t* p = m;
+  if (is_device_ptr(m)) {
+    h.resize(n);
+    HIPCHK(hipMemcpyAsync(h.data(), m, n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    p = h.data();
+  }
+  size_t k = 0;
+  for (size_t i = 0; i < n; ++i) k += p[i] != 0;
+  return (double)k / (double)n;
+}
+
+// Workload signature: the device, every resolved option, the tolerance, and
+// per problem its shape and mask density (in half-octave buckets: the local
+// problems' difficulty follows the size of the unknown regions).
+std::string signature(const inpaint_problem* p, int n, double tol, const Opts& o, int dev,
+                      hipStream_t s) {
+  std::vector<std::tuple<int, int, int, int>> shapes;
+  for (int i = 0; i < n; ++i) {
+    const double d = mask_density(p[i].mask, p[i].W, p[i].H, s);
+    const int bucket = d > 0.0 ? (int)std::floor(2.0 * std::log2(d)) : -1000;
+    shapes.emplace_back(p[i].W, p[i].H, p[i].channels, bucket);
+  }
   std::sort(shapes.begin(), shapes.end());
   std::ostringstream k;
-  char t[32];
-  std::snprintf(t, sizeof t, "%.3g", tol);
-  k << "prec=" << o.prec << ";tol=" << t << ";pre=" << o.pre << ";post=" << o.post << ";n=" << n;
-  for (auto& s : shapes) k << ";" << std::get<0>(s) << "x" << std::get<1>(s) << "x" << std::get<2>(s);
+  char t[160];
+  std::snprintf(t, sizeof t,
+                "dev=%d;prec=%d;tol=%.17g;B=%d;o=%d;gamma=%.9g;tau=%.9g;maxit=%d;sched=%d;cycles=%d;"
+                "pre=%d;post=%d;rhs=%d;ctau=%.9g;cmaxit=%d;n=%d",
+                dev, o.prec, tol, o.B, o.o, (double)o.gamma, (double)o.tau, o.maxit, o.schedule,
+                o.max_cycles, o.pre, o.post, o.rhs, (double)o.coarse_tau, o.coarse_maxit, n);
+  k << t;
+  for (auto& v : shapes)
+    k << ";" << std::get<0>(v) << "x" << std::get<1>(v) << "x" << std::get<2>(v) << "d" << std::get<3>(v);
   return k.str();
 }
 
 const char* cache_file() {
   const char* f = std::getenv("INPAINT_AUTOTUNE_CACHE");
   return (f && *f) ? f : nullptr;
+}
+
+inpaint_opts to_opts(const inpaint_opts& base, const Choice& c);
+
+bool valid(const Choice& c) {
+  inpaint_opts o{};
+  o.struct_size = sizeof(inpaint_opts);
+  const inpaint_opts t = to_opts(o, c);
+  const std::string keep = g_err;
+  try {
+    (void)resolve(&t);
+  } catch (const Fail&) {
+    g_err = keep;
+    return false;
+  }
+  return (c.schedule == INPAINT_SCHED_RFMG || c.schedule == INPAINT_SCHED_FMG) && c.ms > 0.0;
 }
 
 void load_file() {
@@ -60,8 +106,10 @@ void load_file() {
     if (tab == std::string::npos) continue;
     Choice c{};
     std::istringstream v(line.substr(tab + 1));
-    if (v >> c.block >> c.overlap >> c.gamma >> c.tau >> c.schedule >> c.ms)
-      g_tcache[line.substr(0, tab)] = c;
+    if (!(v >> c.block >> c.overlap >> c.gamma >> c.tau >> c.schedule >> c.ms)) continue;
+    // an entry the current library would reject (a stale or edited file) is skipped
+    if (!valid(c)) continue;
+    g_tcache[line.substr(0, tab)] = c;
   }
 }
 
@@ -93,7 +141,11 @@ int autotune_impl(const inpaint_problem* probs, int n, double tol, const inpaint
   inpaint_opts base{};
   if (base_p) base = *base_p;
   base.struct_size = sizeof(inpaint_opts);
-  const std::string key = signature(probs, n, tol, ob);
+  if (!probs || n < 1) fail(INPAINT_E_INVALID, "no problems to tune on");
+  for (int i = 0; i < n; ++i) validate_problem(probs[i], i, ob);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  const std::string key = signature(probs, n, tol, ob, dev, (hipStream_t)stream);
   {
     std::lock_guard<std::mutex> g(g_tmu);
     load_file();

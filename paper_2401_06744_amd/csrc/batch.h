@@ -171,8 +171,9 @@ void upload(std::vector<Plan*> plans, unsigned char** buf, size_t* cap, hipStrea
 // output buffer.  m.idx and m.slot are set by the caller.
 void init_member(Member& m, const inpaint_problem& p, Workspace* ws, const Opts& o, double tol,
                  hipStream_t s);
-// Throws Fail (E_INVALID) for a bad problem; i >= 0 names it in the message.
-void validate_problem(const inpaint_problem& p, int i);
+// Throws Fail (E_INVALID) for a bad problem (including sizes the kernels
+// cannot address with options o); i >= 0 names it in the message.
+void validate_problem(const inpaint_problem& p, int i, const Opts& o);
 // Input checks read back after a prepare plan; sets m->status on rejection.
 void check_prepared(const int* flags_host, Member* m);
 // Apply gathered flags after plan P ran over ms; returns true when all are done.

@@ -554,7 +554,9 @@ std::string ctx_key(int dev, const std::vector<Member*>& ms, const Opts& o, doub
   put(&dev, sizeof dev);
   put(&o, sizeof o);
   put(&tol, sizeof tol);
-  for (const Member* m : ms) put(&m->ws, sizeof m->ws);
+  // workspace serials, never reused: a plan cached for a workspace that has
+  // since been freed can never match again
+  for (const Member* m : ms) put(&m->ws->serial, sizeof m->ws->serial);
   return k;
 }
 
@@ -759,9 +761,10 @@ void check_prepared(const int* flags_host, Member* m) {
   }
 }
 
-void validate_problem(const inpaint_problem& p, int i) {
+void validate_problem(const inpaint_problem& p, int i, const Opts& o) {
   try {
     check_dims(p.f, p.mask, p.W, p.H, p.channels);
+    check_geometry(p.W, p.H, o.B, o.o);
     if (!p.out) fail(INPAINT_E_INVALID, "NULL pointer argument");
     const size_t nf = (size_t)p.W * p.H * p.channels * sizeof(float);
     if (p.out != p.f && overlap(p.out, nf, p.f, nf)) fail(INPAINT_E_INVALID, "out partially overlaps f");
@@ -874,7 +877,7 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
   if (!(tol > 0.0 && tol < 1.0)) fail(INPAINT_E_INVALID, "tol must lie in (0, 1)");
   Opts o = resolve(opts);
   o.profile = 0;
-  for (int i = 0; i < n; ++i) validate_problem(probs[i], i);
+  for (int i = 0; i < n; ++i) validate_problem(probs[i], i, o);
   {
     std::vector<std::pair<const char*, const char*>> spans;
     for (int i = 0; i < n; ++i) {

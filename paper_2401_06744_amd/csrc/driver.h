@@ -141,6 +141,10 @@ struct Workspace {
   void* host = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool busy = false;
+  // cache bookkeeping: a serial number never reused by another workspace (it
+  // keys cached batch plans), the last lease, and the lazily added buffers' sizes
+  unsigned long long serial = 0, last_use = 0;
+  size_t stage_bytes = 0, cg_bytes = 0;
 
   ~Workspace();
 };
@@ -163,9 +167,12 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc = true);
 size_t workspace_bytes(const Key& k);
 
 // Lease a free workspace for (device, sizes, channels, block, overlap,
-// coarsest side, precision), creating it on first use.  Workspaces are kept
-// for the life of the process.
+// coarsest side, precision), creating it on first use.  Idle workspaces stay
+// cached for later calls within a byte limit (least recently used freed first).
 void acquire(Lease& lease, int W, int H, int C, int B, int o, int coarsest, int prec = PREC_F32);
+// Set the cache's byte limit (0: keep it), free idle workspaces above it, and
+// return the bytes still cached.
+size_t set_cache_limit(size_t limit);
 // Device buffers for host-memory inputs and outputs (allocated on first use).
 void ensure_staging(Workspace* ws);
 // Buffers of the CG schedule (directions, A p, scalars); allocated once.
@@ -625,6 +632,9 @@ struct Run {
 // input checks have been read back.
 void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy, bool write_u);
 void check_dims(const void* a, const void* b, int W, int H, int C);
+// Throws Fail (E_INVALID) for an image whose fields or block corrections
+// would overflow the kernels' 32-bit offsets for block side B and overlap o.
+void check_geometry(int W, int H, int B, int o);
 bool overlap(const void* a, size_t na, const void* b, size_t nb);
 
 template <class Fn>

@@ -423,7 +423,8 @@ __device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, 
       const double den = no.den[ch];
       const double rel = den > 0.0 ? sqrt(tot / den) : (tot > 0.0 ? INFINITY : 0.0);
       no.relres[ch] = rel;
-      if (rel <= no.tol) no.active[ch] = 0;
+      // converged, or diverged (a non-finite residual): the channel stops
+      if (rel <= no.tol || !(rel < INFINITY)) no.active[ch] = 0;
       if (no.checks) no.checks[ch] += 1;
     }
   }

@@ -318,7 +318,7 @@ INPAINT_EXPORT int inpaint_server_submit(inpaint_server* srv, const inpaint_prob
                                          uint64_t* ticket) {
   return guarded([&] {
     if (!srv || !p || !ticket) fail(INPAINT_E_INVALID, "NULL pointer argument");
-    validate_problem(*p, -1);
+    validate_problem(*p, -1, srv->o);
     if (!(tol > 0.0 && tol < 1.0)) fail(INPAINT_E_INVALID, "tol must lie in (0, 1)");
     auto r = std::make_shared<Request>();
     r->p = *p;

@@ -2,7 +2,9 @@
 // the cycle driver of Section 4.2 and the C ABI of include/inpaint.h.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 
 #include "batch.h"
@@ -92,6 +94,7 @@ std::vector<std::pair<int, int>> level_sizes(int W, int H, int coarsest) {
 }
 
 std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
+  check_geometry(k.W, k.H, k.B, k.o);
   auto ws = std::make_unique<Workspace>();
   ws->key = k;
   const auto sizes = level_sizes(k.W, k.H, k.coarsest);
@@ -201,8 +204,63 @@ size_t workspace_bytes(const Key& k) { return create_workspace(k, false)->bytes;
 
 namespace {
 
+// Workspaces of single and batched solves, cached between calls per key and
+// bounded in total device bytes: an idle workspace is freed, least recently
+// used first, when a new one (or a lease's end) would leave the cache above
+// the limit.  A workspace in use is never freed.
 std::mutex g_mu;
 std::map<Key, std::vector<std::unique_ptr<Workspace>>> g_cache;
+unsigned long long g_serial = 0, g_tick = 0;
+size_t g_limit = 0;  // 0 until first use: then INPAINT_CACHE_LIMIT_MB or the default
+
+constexpr size_t kDefaultCacheLimit = (size_t)16 << 30;
+
+size_t cache_limit_locked() {
+  if (g_limit == 0) {
+    g_limit = kDefaultCacheLimit;
+    if (const char* e = std::getenv("INPAINT_CACHE_LIMIT_MB")) {
+      const long long mb = std::atoll(e);
+      if (mb > 0) g_limit = (size_t)mb << 20;
+    }
+  }
+  return g_limit;
+}
+
+size_t footprint(const Workspace& w) {
+  size_t b = w.bytes;
+  if (w.stage_base) b += w.stage_bytes;
+  if (w.cg_base) b += w.cg_bytes;
+  return b;
+}
+
+size_t cached_bytes_locked() {
+  size_t t = 0;
+  for (auto& kv : g_cache)
+    for (auto& w : kv.second) t += footprint(*w);
+  return t;
+}
+
+// Free idle workspaces, least recently used first, until `need` more bytes
+// fit under the limit (or nothing idle is left).
+void trim_locked(size_t need) {
+  const size_t limit = cache_limit_locked();
+  size_t total = cached_bytes_locked();
+  while (total + need > limit) {
+    Workspace* lru = nullptr;
+    for (auto& kv : g_cache)
+      for (auto& w : kv.second)
+        if (!w->busy && (!lru || w->last_use < lru->last_use)) lru = w.get();
+    if (!lru) return;
+    total -= footprint(*lru);
+    auto& vec = g_cache[lru->key];
+    for (auto it = vec.begin(); it != vec.end(); ++it)
+      if (it->get() == lru) {
+        vec.erase(it);  // frees the device memory (every call has synchronised its stream)
+        break;
+      }
+    if (vec.empty()) g_cache.erase(lru->key);
+  }
+}
 
 }  // namespace
 
@@ -210,6 +268,7 @@ Lease::~Lease() {
   if (ws) {
     std::lock_guard<std::mutex> g(g_mu);
     ws->busy = false;
+    trim_locked(0);
   }
 }
 
@@ -219,18 +278,31 @@ void acquire(Lease& lease, int W, int H, int C, int B, int o, int coarsest, int 
   const Key k{dev, W, H, C, B, o, coarsest, prec};
   {
     std::lock_guard<std::mutex> g(g_mu);
-    for (auto& w : g_cache[k])
-      if (!w->busy) {
-        w->busy = true;
-        lease.ws = w.get();
-        return;
-      }
+    auto it = g_cache.find(k);
+    if (it != g_cache.end())
+      for (auto& w : it->second)
+        if (!w->busy) {
+          w->busy = true;
+          w->last_use = ++g_tick;
+          lease.ws = w.get();
+          return;
+        }
+    trim_locked(workspace_bytes(k));
   }
   auto ws = create_workspace(k);
   std::lock_guard<std::mutex> g(g_mu);
   ws->busy = true;
+  ws->serial = ++g_serial;
+  ws->last_use = ++g_tick;
   lease.ws = ws.get();
   g_cache[k].push_back(std::move(ws));
+}
+
+size_t set_cache_limit(size_t limit) {
+  std::lock_guard<std::mutex> g(g_mu);
+  if (limit) g_limit = limit;
+  trim_locked(0);
+  return cached_bytes_locked();
 }
 
 void ensure_staging(Workspace* ws) {
@@ -238,6 +310,7 @@ void ensure_staging(Workspace* ws) {
   const size_t n = (size_t)ws->key.W * ws->key.H;
   const size_t fb = round_up(n * ws->key.C * sizeof(float), 256);
   HIPCHK(hipMalloc(&ws->stage_base, 2 * fb + round_up(n, 256)));
+  ws->stage_bytes = 2 * fb + round_up(n, 256);
   ws->f_dev = (float*)ws->stage_base;
   ws->o_dev = (float*)((char*)ws->stage_base + fb);
   ws->m_dev = (uint8_t*)((char*)ws->stage_base + 2 * fb);
@@ -248,6 +321,7 @@ void ensure_cg(Workspace* ws) {
   const Level& L0 = ws->lv[0];
   const size_t fb = round_up((size_t)ws->key.C * L0.v.plane * sizeof(float), 256);
   HIPCHK(hipMalloc(&ws->cg_base, 3 * fb + 256));
+  ws->cg_bytes = 3 * fb + 256;
   char* b = (char*)ws->cg_base;
   ws->cg_p[0] = (float*)b;
   ws->cg_p[1] = (float*)(b + fb);
@@ -327,6 +401,19 @@ void check_dims(const void* a, const void* b, int W, int H, int C) {
   if ((long long)W * H > (1LL << 31)) fail(INPAINT_E_INVALID, "image too large");
 }
 
+void check_geometry(int W, int H, int B, int o) {
+  // Offsets inside one channel's fields and inside one channel's weighted
+  // block corrections are 32-bit in the kernels, and a pixel index is split
+  // into blocks through a float reciprocal that is exact below 2^24.
+  if (std::max(W, H) >= (1 << 24)) fail(INPAINT_E_INVALID, "image sides must be below 2^24 pixels");
+  const long long P = (long long)round_up((size_t)W, 64);
+  if ((long long)H * P > (long long)INT32_MAX)
+    fail(INPAINT_E_INVALID, "image too large: a channel's padded plane exceeds 32-bit offsets");
+  const long long nb = (long long)num_blocks_axis(W, B, o) * num_blocks_axis(H, B, o) * B * B;
+  if (nb > (long long)INT32_MAX)
+    fail(INPAINT_E_INVALID, "image too large: a channel's block corrections exceed 32-bit offsets");
+}
+
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = (const char*)a;
   const char* pb = (const char*)b;
@@ -339,6 +426,7 @@ int solve_impl(const float* f, const uint8_t* mask, int W, int H, int C, double 
   if (!out) fail(INPAINT_E_INVALID, "NULL pointer argument");
   if (!(tol > 0.0 && tol < 1.0)) fail(INPAINT_E_INVALID, "tol must lie in (0, 1)");
   const Opts o = resolve(opts);
+  check_geometry(W, H, o.B, o.o);
   const size_t nf = (size_t)W * H * C * sizeof(float);
   if (out != f && overlap(out, nf, f, nf)) fail(INPAINT_E_INVALID, "out partially overlaps f");
   if (overlap(out, nf, mask, (size_t)W * H)) fail(INPAINT_E_INVALID, "out overlaps mask");
@@ -426,6 +514,14 @@ INPAINT_EXPORT int inpaint_solve(const float* f, const uint8_t* mask, int W, int
 INPAINT_EXPORT int inpaint_solve_ex(const float* f, const uint8_t* mask, int W, int H, int channels, double tol,
                      float* out, const inpaint_opts* opts, void* stream, inpaint_stats* stats) {
   return guarded([&] { return solve_impl(f, mask, W, H, channels, tol, out, opts, stream, stats); });
+}
+
+INPAINT_EXPORT int inpaint_cache_limit(size_t limit_bytes, size_t* cached_bytes) {
+  return guarded([&] {
+    const size_t b = set_cache_limit(limit_bytes);
+    if (cached_bytes) *cached_bytes = b;
+    return INPAINT_OK;
+  });
 }
 
 INPAINT_EXPORT const char* inpaint_last_error(void) { return g_err.c_str(); }

@@ -22,7 +22,7 @@ import numpy as np
 __all__ = [
     "smooth_field", "voronoi_field", "plain_image", "frame_image",
     "bernoulli_mask", "blue_noise_mask", "config_small", "config_4k",
-    "config_precision", "batched_problems", "poisson_trace",
+    "config_precision", "batched_specs", "batched_problem", "batched_problems", "poisson_trace",
 ]
 
 
@@ -193,18 +193,30 @@ def config_precision(kind: str = "bernoulli", W: int = 3840, H: int = 2160):
     return img, m
 
 
-def batched_problems(n: int = 64, seed: int = 40, wmax: int = 1920, hmax: int = 1080):
-    """``n`` problems of uneven size: W in [128, wmax], H in [128, hmax], C in {1, 3}, 1-10 % masks."""
+def batched_specs(n: int = 64, seed: int = 40, wmax: int = 1920, hmax: int = 1080):
+    """Shapes of ``batched_problems``: ``(W, H, C, density, image_seed)`` per problem."""
     rng = np.random.default_rng(seed)
-    probs = []
-    for i in range(n):
+    specs = []
+    for _ in range(n):
         W = int(rng.integers(128, wmax + 1))
         H = int(rng.integers(128, hmax + 1))
         C = 1 if rng.random() < 0.5 else 3
         dens = float(rng.uniform(0.01, 0.10))
         s = int(rng.integers(1 << 30))
-        probs.append((frame_image(W, H, C, seed=s), bernoulli_mask(W, H, dens, seed=s + 1)))
-    return probs
+        specs.append((W, H, C, dens, s))
+    return specs
+
+
+def batched_problem(i: int, n: int = 64, seed: int = 40, wmax: int = 1920, hmax: int = 1080):
+    """Problem ``i`` of ``batched_problems(n, seed, wmax, hmax)`` alone."""
+    W, H, C, dens, s = batched_specs(n, seed, wmax, hmax)[i]
+    return frame_image(W, H, C, seed=s), bernoulli_mask(W, H, dens, seed=s + 1)
+
+
+def batched_problems(n: int = 64, seed: int = 40, wmax: int = 1920, hmax: int = 1080):
+    """``n`` problems of uneven size: W in [128, wmax], H in [128, hmax], C in {1, 3}, 1-10 % masks."""
+    return [(frame_image(W, H, C, seed=s), bernoulli_mask(W, H, dens, seed=s + 1))
+            for W, H, C, dens, s in batched_specs(n, seed, wmax, hmax)]
 
 
 def poisson_trace(qps: float, n: int, seed: int = 50):

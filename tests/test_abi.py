@@ -73,3 +73,32 @@ def test_binding_constants_match_the_header():
     assert len(binding.KERNELS) == consts["NUM_KERNELS"]
     for i, k in enumerate(binding.KERNELS):
         assert consts["K_" + k.upper()] == i, k
+
+
+def _fake_solve(W, H, C=1, **opts):
+    """inpaint_solve_ex on fake, never dereferenced addresses: the size checks
+    run before any pointer is used and before any device call."""
+    lib = binding.lib()
+    o = binding.make_opts(**opts) if opts else None
+    code = lib.inpaint_solve_ex(ctypes.c_void_p(1 << 44), ctypes.c_void_p(2 << 44), W, H, C, 1e-6,
+                                ctypes.c_void_p(3 << 44), ctypes.byref(o) if o is not None else None,
+                                None, None)
+    return code, binding.inpaint_last_error()
+
+
+def test_sizes_beyond_32_bit_offsets_are_rejected_before_any_work():
+    """The kernels address one channel's fields and block corrections with
+    32-bit offsets and split pixel indices exactly only below 2^24: larger
+    problems are rejected as invalid, before any allocation or device call."""
+    # 1.6 Gpx: the plane fits, the weighted block corrections (about 1.5 planes
+    # at block 32, overlap 6) do not
+    code, msg = _fake_solve(40000, 40000)
+    assert code == binding.E_INVALID and "32-bit" in msg, (code, msg)
+    # 0.54 Gpx at block 16, overlap 8: four planes of corrections
+    code, msg = _fake_solve(23200, 23200, block=16, overlap=8)
+    assert code == binding.E_INVALID and "32-bit" in msg, (code, msg)
+    # one side of 2^24 pixels
+    code, msg = _fake_solve(1 << 24, 2)
+    assert code == binding.E_INVALID and "2^24" in msg, (code, msg)
+    code, msg = _fake_solve(3, 1 << 24)
+    assert code == binding.E_INVALID and "2^24" in msg, (code, msg)

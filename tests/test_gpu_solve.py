@@ -244,6 +244,39 @@ def test_unknown_values_never_read_and_channels_independent():
         assert np.array_equal(single[0], out[ch])
 
 
+def _overflowing(f, m, ch):
+    """f with the known pixels of channel ch set to +-3e38 in a checkerboard:
+    finite data whose residual overflows float32 (and whose squares overflow
+    the float32 dot products of the block and coarse solves)."""
+    g = f.copy()
+    ys, xs = np.nonzero(m)
+    g[ch, ys, xs] = np.where((ys + xs) % 2 == 0, 3e38, -3e38).astype(np.float32)
+    return g
+
+
+def test_overflowing_known_values_diverge_alone():
+    """A channel whose residual becomes non-finite stops as diverged: the solve
+    returns E_DIVERGED with rel_res NaN, while the problem's other channels and
+    the other problems of a batch are solved exactly as alone."""
+    f = synth.frame_image(150, 90, 3, seed=41)
+    m = synth.bernoulli_mask(150, 90, 0.05, seed=42)
+    g = _overflowing(f, m, 1)
+    with pytest.raises(binding.InpaintError) as e:
+        binding.inpaint_solve_ex(g, m, TOL)
+    assert e.value.code == binding.E_DIVERGED
+    a = (synth.frame_image(97, 61, 1, seed=43), synth.bernoulli_mask(97, 61, 0.03, seed=44))
+    outs, st, stats = binding.inpaint_solve_batched([a, (g, m)], TOL, raise_on_error=False)
+    assert st == binding.E_DIVERGED
+    assert stats[0]["status"] == binding.OK and stats[1]["status"] == binding.E_DIVERGED
+    assert np.isnan(stats[1]["rel_res"])
+    assert np.array_equal(outs[0], _solve(*a)[0])
+    for ch in (0, 2):
+        single, st1, _ = _solve(np.ascontiguousarray(f[ch:ch + 1]), m)
+        assert st1 == binding.OK and np.array_equal(outs[1][ch], single[0]), ch
+    # the diverged channel stops at its first non-finite test, not at the cycle cap
+    assert stats[1]["cycles"] < 30
+
+
 def test_repeatable_and_device_pointers_and_alias():
     torch = _torch()
     f = synth.frame_image(200, 120, 3, seed=31)
@@ -317,3 +350,29 @@ def test_precision_forms_are_repeatable_and_channel_independent():
         assert np.array_equal(a, b)
         single, _, _ = _solve(np.ascontiguousarray(f[1:2]), m, precision=prec)
         assert np.array_equal(single[0], a[1])
+
+
+def test_workspace_cache_is_bounded():
+    """Idle hierarchies beyond the cache limit are freed (least recently used
+    first) and rebuilt when needed again; results do not change."""
+    shapes = [(300, 200, 1), (400, 300, 3), (500, 250, 1)]
+    probs = [(synth.frame_image(W, H, C, seed=90 + k), synth.bernoulli_mask(W, H, 0.04, seed=95 + k))
+             for k, (W, H, C) in enumerate(shapes)]
+    ref = [_solve(f, m)[0] for f, m in probs]
+    try:
+        assert binding.inpaint_cache_limit(1 << 20) <= 1 << 20  # idle hierarchies are freed now
+        for _ in range(2):
+            for (f, m), r in zip(probs, ref):
+                assert np.array_equal(_solve(f, m)[0], r)
+                assert binding.inpaint_cache_limit(0) == 0  # nothing idle stays above the limit
+        outs, st, _ = binding.inpaint_solve_batched(probs, TOL)
+        assert st == binding.OK and all(np.array_equal(o, r) for o, r in zip(outs, ref))
+        assert binding.inpaint_cache_limit(0) == 0
+        # a limit that holds one of them: the most recent stays
+        binding.inpaint_cache_limit(64 << 20)
+        for f, m in probs:
+            _solve(f, m)
+        left = binding.inpaint_cache_limit(0)
+        assert 0 < left <= 64 << 20
+    finally:
+        binding.inpaint_cache_limit(16 << 30)
