@@ -15,18 +15,12 @@
 #include <tuple>
 #include <vector>
 
+#include "errors.h"
 #include "inpaint.h"
 #include "kernels.h"
 
 namespace inpaint {
 
-extern thread_local std::string g_err;
-
-struct Fail {
-  int code;
-};
-
-[[noreturn]] void fail(int code, const std::string& msg);
 
 #define HIPCHK(expr)                                                              \
   do {                                                                            \
@@ -636,21 +630,5 @@ void check_dims(const void* a, const void* b, int W, int H, int C);
 // would overflow the kernels' 32-bit offsets for block side B and overlap o.
 void check_geometry(int W, int H, int B, int o);
 bool overlap(const void* a, size_t na, const void* b, size_t nb);
-
-template <class Fn>
-int guarded(Fn&& fn) {
-  g_err.clear();
-  try {
-    return fn();
-  } catch (const Fail& e) {
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    g_err = "host allocation failed";
-    return INPAINT_E_NOMEM;
-  } catch (...) {
-    g_err = "unexpected exception";
-    return INPAINT_E_DEVICE;
-  }
-}
 
 }  // namespace inpaint

@@ -12,13 +12,6 @@
 
 namespace inpaint {
 
-thread_local std::string g_err;
-
-[[noreturn]] void fail(int code, const std::string& msg) {
-  g_err = msg;
-  throw Fail{code};
-}
-
 Opts resolve(const inpaint_opts* p) {
   Opts o;
   if (p) {
