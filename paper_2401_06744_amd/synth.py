@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = [
     "smooth_field", "voronoi_field", "plain_image", "frame_image",
-    "bernoulli_mask", "blue_noise_mask", "config_small", "config_4k",
+    "bernoulli_mask", "blue_noise_mask", "region_edges", "edge_mask", "config_small", "config_4k",
     "config_precision", "batched_specs", "batched_problem", "batched_problems", "poisson_trace",
 ]
 
@@ -168,6 +168,39 @@ def blue_noise_mask(W: int, H: int, density: float, seed: int, iters: int = 12) 
     if not m.any():
         m[0, 0] = 1
     return m, float(m.mean())
+
+
+def region_edges(W: int, H: int, region_seed: int) -> np.ndarray:
+    """Pixels on the border of the piecewise-constant regions of
+    ``frame_image(..., seed=region_seed)``: a 4-neighbour has another label."""
+    labels = voronoi_field(np.random.default_rng(region_seed + 1_000_003), W, H)
+    e = np.zeros((H, W), dtype=bool)
+    dx = labels[:, 1:] != labels[:, :-1]
+    dy = labels[1:, :] != labels[:-1, :]
+    e[:, 1:] |= dx
+    e[:, :-1] |= dx
+    e[1:, :] |= dy
+    e[:-1, :] |= dy
+    return e
+
+
+def edge_mask(W: int, H: int, density: float, seed: int, region_seed: int,
+              edge_share: float = 0.8) -> np.ndarray:
+    """Mask concentrated on the region borders of a ``frame_image``: about
+    ``edge_share`` of its ``density * W * H`` known pixels lie on border pixels
+    (each border pixel known with one probability, every other pixel with
+    another), as masks optimised for such images place their points along
+    edges.  Never empty."""
+    e = region_edges(W, H, region_seed)
+    n = density * W * H
+    ne = max(int(e.sum()), 1)
+    p_e = min(1.0, edge_share * n / ne)
+    p_f = max(0.0, (n - p_e * ne) / max(W * H - ne, 1))
+    r = np.random.default_rng(seed).random((H, W))
+    m = np.where(e, r < p_e, r < p_f).astype(np.uint8)
+    if not m.any():
+        m[0, 0] = 1
+    return m
 
 
 # --------------------------------------------------------------------------

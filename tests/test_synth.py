@@ -37,3 +37,20 @@ def test_batched_and_trace_recipes():
     assert abs(np.diff(t).mean() - 0.01) < 0.001
     assert {(w, h) for _, w, h, _ in tr} == {(1280, 720), (1920, 1080), (3840, 2160)}
     assert all(0.005 <= d <= 0.10 for *_, d in tr)
+
+
+def test_edge_mask_concentrates_on_region_borders():
+    W, H = 480, 270
+    e = synth.region_edges(W, H, region_seed=10)
+    f = synth.frame_image(W, H, 1, seed=10)
+    # region borders are where the piecewise-constant part of the image jumps
+    jump = np.zeros((H, W), bool)
+    d = np.abs(np.diff(f[0], axis=1)) > 8.0
+    jump[:, 1:] |= d
+    jump[:, :-1] |= d
+    assert (jump & e).sum() > 0.5 * jump.sum()
+    m = synth.edge_mask(W, H, 0.02, seed=5, region_seed=10)
+    assert abs(m.mean() - 0.02) < 0.004
+    share = (m.astype(bool) & e).sum() / m.sum()
+    assert 0.7 < share < 0.9
+    assert np.array_equal(m, synth.edge_mask(W, H, 0.02, seed=5, region_seed=10))
