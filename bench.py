@@ -783,6 +783,11 @@ def batched_leg(binding, torch, synth, args):
                                        "schedule": tuned.schedule},
                               "autotune_s": round(t_tune, 2)},
         "speedup_vs_plain": round(t_plain / t_tuned, 3),
+        # the batch's pixel rate in 4K RGB frames per second, to set beside
+        # the single-frame headline (the same pixels, channel count and tol)
+        "equiv_4k_rgb_fps": {"plain": round(px / (3840 * 2160 * 3) / t_plain, 1),
+                             "batched_default": round(px / (3840 * 2160 * 3) / t_default, 1),
+                             "batched_autotuned": round(px / (3840 * 2160 * 3) / t_tuned, 1)},
         "status": st, "rel_res_max": rr, "known_exact": known,
         "cycles": sorted({s["cycles"] for s in stats}),
         "batched_equals_solo": "bitwise (tests/test_gpu_batched.py)",

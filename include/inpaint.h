@@ -92,7 +92,8 @@ typedef enum inpaint_rhs_restriction {
 typedef struct inpaint_opts {
   int struct_size;     /* sizeof(inpaint_opts) */
   int block;           /* ORAS block side B: 16 or 32 (default 32, Section 3.1) */
-  int overlap;         /* overlap o in pixels between neighbouring blocks, 2 <= o <= B/2 (default 6) */
+  int overlap;         /* overlap o in pixels between neighbouring blocks: even (twice the
+                          per-side halo), 2 <= o <= B/2 (default 6) */
   float gamma;         /* Robin term added per cut block edge, 0 < gamma <= 1 (gamma = 1 is
                           Dirichlet RAS); the paper leaves alpha open (default 0.5) */
   float tau;           /* local CG stop: ||rho_i||^2 <= tau * ||r||^2 * |block| / N (default 0.005) */
@@ -123,7 +124,11 @@ typedef struct inpaint_opts {
    refinement whose correction is computed from 16-bit fields. */
 typedef enum inpaint_precision {
   INPAINT_PREC_FP32 = 0,
-  INPAINT_PREC_FP16 = 1, /* IEEE half, stored scaled by the reference residual's rms */
+  INPAINT_PREC_FP16 = 1, /* IEEE half: residuals and corrections stored scaled by the
+                            reference residual's rms, the coarse levels' known values and
+                            iterates of the cascade unscaled, so known values must lie within
+                            the half range (|f| <= 65504; beyond it the fields overflow and
+                            the solve ends with INPAINT_E_DIVERGED) */
   INPAINT_PREC_BF16 = 2  /* bfloat16 */
 } inpaint_precision;
 

@@ -628,9 +628,6 @@ __device__ __forceinline__ double bilinear(double a, double b, double c, double 
   return __dadd_rn(s, __dmul_rn(0.0625, d));
 }
 
-// New iterate at (gx, gy) (inside the image) for one pass mode.  Column data
-// is computed once per thread, row data per row.  TU: element type of this
-// level's iterate and known values; TC: corrections and the coarse field.
 // what a pass mode reads and writes
 __host__ __device__ constexpr bool mode_upd(int m) {
   return m == PASS_UPD || m == PASS_UPD0 || m == PASS_FIN || m == PASS_FIN0;
@@ -647,6 +644,52 @@ __host__ __device__ constexpr bool mode_rest(int m) { return m == PASS_UPD || m 
 // span at most 34 coarse columns and 18 coarse rows.
 constexpr int kCoarseW = kTileW / 2 + 2, kCoarseH = kTileH / 2 + 2;
 
+// Two horizontally adjacent pixels (an even column and the next one).
+struct Px2 {
+  float v[2];
+};
+
+// Pair loads and stores of a field: element i must be even (i.e. the pair is
+// 2-element aligned); one 8-byte (float32) or 4-byte (16-bit) access.
+template <class T>
+__device__ __forceinline__ Px2 ld2(const Fld<T>& f, int i) {
+  Px2 r;
+  if constexpr (is_f32<T>()) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *(const __attribute__((address_space(1))) v2*)(f.p + i);
+    r.v[0] = v.x;
+    r.v[1] = v.y;
+  } else {
+    const unsigned w = *(const __attribute__((address_space(1))) unsigned*)(f.p + i);
+    const T lo = __builtin_bit_cast(T, (unsigned short)(w & 0xffffu));
+    const T hi = __builtin_bit_cast(T, (unsigned short)(w >> 16));
+    r.v[0] = (float)lo * f.s;
+    r.v[1] = (float)hi * f.s;
+  }
+  return r;
+}
+template <class T>
+__device__ __forceinline__ void st2(const Fld<T>& f, int i, float a, float b) {
+  if constexpr (is_f32<T>()) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    *(__attribute__((address_space(1))) v2*)(f.p + i) = v2{a, b};
+  } else {
+    const T ta = (T)(a * f.inv), tb = (T)(b * f.inv);
+    *(__attribute__((address_space(1))) unsigned*)(f.p + i) =
+        (unsigned)__builtin_bit_cast(unsigned short, ta) | ((unsigned)__builtin_bit_cast(unsigned short, tb) << 16);
+  }
+}
+// Known flags of the pixel pair at an even offset.
+__device__ __forceinline__ unsigned short ld_mask2(const uint8_t* c, int i) {
+  return *(const __attribute__((address_space(1))) unsigned short*)(c + i);
+}
+
+// New iterate of a pixel (or of an aligned pixel pair) for one pass mode.
+// Column data is computed once per thread, row data per row.  TU: element
+// type of this level's iterate and known values; TC: corrections and the
+// coarse field.  The pair functions rely on an even block stride and overlap:
+// both pixels of an aligned pair then lie in the same blocks at the same
+// overlap side, so that their four weighted corrections are four pair loads.
 template <int MODE, class TU, class TC>
 struct Former {
   const PassArgs& a;
@@ -681,7 +724,7 @@ struct Former {
     int gx;
     int cx1, cx0;  // UPD: column part of the correction offsets of blocks bx1, bx1 - 1
     bool h0;
-    int xn, xf;    // PSOL/PCORR: coarse columns
+    int xn, xf;    // PSOL/PCORR: coarse columns (of the pair's first pixel)
   };
   __device__ Col col(int gx) const {
     Col c;
@@ -696,11 +739,22 @@ struct Former {
     return c;
   }
 
-  __device__ float value(const Col& c, int gy) const {
-    bool known;
-    return value(c, gy, known);
+  // Row offsets of the (up to) four blocks covering row gy: ry1 (block by1) and
+  // ry0 (block by1 - 1, or ry1 when absent); h0y: the upper block is present.
+  __device__ void rows(int gy, int& ry0, int& ry1, bool& h0y) const {
+    const BlockAxis ay = block_axis(gy, S, rS, o, nby);
+    ry1 = ay.b1 * nbx * B * B + ay.l1 * B;
+    ry0 = ay.h0 ? (ay.b1 - 1) * nbx * B * B + (ay.l1 + S) * B : ry1;
+    h0y = ay.h0;
   }
-  __device__ float value(const Col& c, int gy, bool& known_out) const {
+
+  // the same additions, in the same order, as adding only the present corrections
+  static __device__ __forceinline__ float sum4(float d00, float d01, float d10, float d11, bool hy, bool hx) {
+    return (((hy && hx ? d00 : 0.0f) + (hy ? d01 : 0.0f)) + (hx ? d10 : 0.0f)) + d11;
+  }
+
+  // single pixel (the halo columns)
+  __device__ float value(const Col& c, int gy) const {
     const LevelView& lv = a.lv;
     const int off = gy * lv.P + c.gx;
     if constexpr (MODE == PASS_RES) {
@@ -708,17 +762,16 @@ struct Former {
     } else if constexpr (mode_upd(MODE)) {
       float d = 0.0f;
       if constexpr (mode_contrib(MODE)) {
-        // the (up to) four blocks covering the pixel: all four slots are read,
-        // absent ones at a valid stand-in address and then dropped, so that
-        // the loads issue together rather than behind per-pixel branches
-        const BlockAxis ay = block_axis(gy, S, rS, o, nby);
-        const int ry1 = ay.b1 * nbx * B * B + ay.l1 * B;
-        const int ry0 = ay.h0 ? (ay.b1 - 1) * nbx * B * B + (ay.l1 + S) * B : ry1;
+        // all four slots are read, absent ones at a valid stand-in address and
+        // then dropped, so that the loads issue together rather than behind
+        // per-pixel branches
+        int ry0, ry1;
+        bool hy;
+        rows(gy, ry0, ry1, hy);
         const int cx0 = c.h0 ? c.cx0 : c.cx1;
         const float d00 = cb.ld(ry0 + cx0), d01 = cb.ld(ry0 + c.cx1);
         const float d10 = cb.ld(ry1 + cx0), d11 = cb.ld(ry1 + c.cx1);
-        // the same additions, in the same order, as adding only the present ones
-        d = (((ay.h0 && c.h0 ? d00 : 0.0f) + (ay.h0 ? d01 : 0.0f)) + (c.h0 ? d10 : 0.0f)) + d11;
+        d = sum4(d00, d01, d10, d11, hy, c.h0);
       }
       if constexpr (mode_fin(MODE)) d = ea.ld(off) + d;
       if constexpr (mode_zero(MODE))
@@ -726,39 +779,84 @@ struct Former {
       else
         return uin.ld(off) + d;
     } else {
-      const Pre pr = pre(c, gy);
-      known_out = pr.known;
-      return fin(c, gy, pr);
+      const bool known = glb(a.c)[off] != 0;
+      const float x = MODE == PASS_PSOL ? bb.ld(off) : (mode_zero(MODE) ? 0.0f : uin.ld(off));
+      int yn, yf;
+      prolong_axis(gy, a.Hc, yn, yf);
+      return fin1(c.xn, c.xf, yn, yf, known, x);
     }
   }
 
-  // Prolongations in two steps: the pixel's global inputs (known flag, and
-  // its known value (PSOL) or iterate (PCORR)), then the value from the
+  // the aligned pair at column c.gx (even): UPD and RES modes
+  __device__ Px2 value2(const Col& c, int gy) const {
+    const LevelView& lv = a.lv;
+    const int off = gy * lv.P + c.gx;
+    if constexpr (MODE == PASS_RES) {
+      return ld2(uin, off);
+    } else {
+      Px2 d{{0.0f, 0.0f}};
+      if constexpr (mode_contrib(MODE)) {
+        int ry0, ry1;
+        bool hy;
+        rows(gy, ry0, ry1, hy);
+        const int cx0 = c.h0 ? c.cx0 : c.cx1;
+        const Px2 d00 = ld2(cb, ry0 + cx0), d01 = ld2(cb, ry0 + c.cx1);
+        const Px2 d10 = ld2(cb, ry1 + cx0), d11 = ld2(cb, ry1 + c.cx1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) d.v[h] = sum4(d00.v[h], d01.v[h], d10.v[h], d11.v[h], hy, c.h0);
+      }
+      if constexpr (mode_fin(MODE)) {
+        const Px2 e = ld2(ea, off);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) d.v[h] = e.v[h] + d.v[h];
+      }
+      if constexpr (!mode_zero(MODE)) {
+        const Px2 u = ld2(uin, off);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) d.v[h] = u.v[h] + d.v[h];
+      }
+      return d;
+    }
+  }
+
+  // Prolongations in two steps: the pair's global inputs (known flags, and
+  // the known values (PSOL) or iterate (PCORR)), then the values from the
   // coarse patch in LDS.
-  struct Pre {
-    bool known;
-    float x;
+  struct Pre2 {
+    unsigned short known;  // byte h: known flag of pixel h
+    Px2 x;
   };
-  __device__ Pre pre(const Col& c, int gy) const {
+  __device__ Pre2 pre2(const Col& c, int gy) const {
     const int off = gy * a.lv.P + c.gx;
-    Pre p;
-    p.known = glb(a.c)[off] != 0;
+    Pre2 p;
+    p.known = ld_mask2(a.c, off);
     if constexpr (MODE == PASS_PSOL)
-      p.x = bb.ld(off);  // read unconditionally: no branch around the load
+      p.x = ld2(bb, off);  // read unconditionally: no branch around the load
+    else if constexpr (mode_zero(MODE))
+      p.x = Px2{{0.0f, 0.0f}};
     else
-      p.x = mode_zero(MODE) ? 0.0f : uin.ld(off);
+      p.x = ld2(uin, off);
     return p;
   }
-  __device__ float fin(const Col& c, int gy, const Pre& pr) const {
-    int yn, yf;
-    prolong_axis(gy, a.Hc, yn, yf);
+  __device__ float fin1(int xn, int xf, int yn, int yf, bool known, float x) const {
     const float* rn = cpatch + (yn - cy0) * kCoarseW - cx0;
     const float* rf = cpatch + (yf - cy0) * kCoarseW - cx0;
-    const double p = bilinear(rn[c.xn], rn[c.xf], rf[c.xn], rf[c.xf]);
+    const double p = bilinear(rn[xn], rn[xf], rf[xn], rf[xf]);
     if constexpr (MODE == PASS_PSOL)
-      return pr.known ? pr.x : (float)p;
+      return known ? x : (float)p;
     else
-      return pr.known ? pr.x : (float)((double)pr.x + p);
+      return known ? x : (float)((double)x + p);
+  }
+  __device__ Px2 fin2(const Col& c, int gy, const Pre2& pr) const {
+    int yn, yf;
+    prolong_axis(gy, a.Hc, yn, yf);
+    // the pair's first pixel is even: its second coarse column lies to the
+    // left, the odd pixel's to the right (both clamped at the edge)
+    const int xf1 = min(c.xn + 1, a.Wc - 1);
+    Px2 r;
+    r.v[0] = fin1(c.xn, c.xf, yn, yf, (pr.known & 0xffu) != 0, pr.x.v[0]);
+    r.v[1] = fin1(c.xn, xf1, yn, yf, (pr.known >> 8) != 0, pr.x.v[1]);
+    return r;
   }
 };
 
@@ -788,7 +886,9 @@ __device__ __forceinline__ float coarse_updated(const PassArgs& a, const Fld<TC>
     return (float)(TC)(un * uc.inv) * uc.s;
 }
 
-// One fused grid pass over a 64x32 tile of one channel.
+// One fused grid pass over a 64x32 tile of one channel.  Thread (pair column
+// q, row group g) works on columns x0 + 2q and x0 + 2q + 1: every field access
+// is a pair access.
 //   phase 1: the new iterate on the tile plus a 1-pixel halo, into LDS.  A halo
 //            pixel outside the image takes the value of the pixel it mirrors,
 //            so that the reflecting boundary needs no special case below.
@@ -797,56 +897,59 @@ __device__ __forceinline__ float coarse_updated(const PassArgs& a, const Fld<TC>
 //            (or keep it in LDS for the fused restriction); norm partial.
 template <int MODE, class TU, class TC>
 __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
-  constexpr int TW = kTileW + 2, TH = kTileH + 2;
-  constexpr int NG = kPassThreads / kTileW;  // row groups
+  constexpr int QW = kTileW / 2;             // pair columns per tile
+  constexpr int NG = kPassThreads / QW;      // row groups
+  constexpr int TH = kTileH + 2;
+  // LDS row: halo column at index 1, tile column x at x + 2, halo at kTileW + 2
+  // (pairs start at even indices)
+  constexpr int TW = kTileW + 4;
   constexpr int RJ = (TH + NG - 1) / NG;     // phase-1 rows per thread
+  constexpr int RK = kTileH / NG;            // phase-2 rows per thread
   const unsigned tiles_x = (unsigned)((a.lv.W + kTileW - 1) / kTileW);
   const unsigned ntiles = tiles_x * (unsigned)((a.lv.H + kTileH - 1) / kTileH);
   const int ch = lin / ntiles;
   const unsigned tile = lin - (unsigned)ch * ntiles;
   const bool act = channel_active(a.active, ch);  // tested after the first loads
   const LevelView& lv = a.lv;
+  const int W = lv.W, H = lv.H;
   const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
-  __shared__ float t[TH][TW];
   constexpr bool kProlong = MODE == PASS_PSOL || mode_pcorr(MODE);
-  __shared__ uint8_t kt[kProlong ? TH : 1][kProlong ? TW : 1];  // known flags (prolongations)
+  __shared__ float t[TH][TW];
   __shared__ float cp[kProlong ? kCoarseH : 1][kProlong ? kCoarseW : 1];
   Former<MODE, TU, TC> F(a, ch);
-  const int c = threadIdx.x & (kTileW - 1), g = threadIdx.x / kTileW;
-  constexpr int RK = kTileH / NG;  // phase-2 rows per thread
-  const int gx = x0 + c;
-  const int gxc = min(gx, lv.W - 1);
+  const int q = threadIdx.x % QW, g = threadIdx.x / QW;
+  const int gx = x0 + 2 * q;
+  // the pair that is read: this thread's, or for columns past the image the
+  // last in-image pair (its pixel W - 1 is the mirror of column W)
+  const int gxe = min(gx, (W - 1) & ~1);
+  const bool lastodd = ((W - 1) & 1) != 0;  // column W - 1 is the pair's second pixel
   // Phase-2 inputs that do not depend on phase 1 (masks and right-hand sides
   // of this thread's rows) are loaded first, from clamped addresses, so that
-  // their latency overlaps phase 1's.
-  // (The final pass of the correction form holds more phase-1 state and
-  // loads them for phase 2 instead.)
-  uint8_t mk[RK];
-  float bvv[RK];
-  if constexpr (!kProlong && !mode_fin(MODE)) {
-#pragma unroll
-    for (int k = 0; k < RK; ++k) mk[k] = glb(a.c)[min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc];
-  }
+  // their latency overlaps phase 1's.  (The final pass of the correction form
+  // holds more phase-1 state and loads them for phase 2 instead.)
+  unsigned short mk[RK];
+  Px2 bvv[RK];
   if constexpr (!mode_fin(MODE)) {
+#pragma unroll
+    for (int k = 0; k < RK; ++k) mk[k] = ld_mask2(a.c, min(y0 + g * RK + k, H - 1) * lv.P + gxe);
     if (MODE == PASS_RES || !a.solution) {
 #pragma unroll
-      for (int k = 0; k < RK; ++k) bvv[k] = F.bb.ld(min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc);
+      for (int k = 0; k < RK; ++k) bvv[k] = ld2(F.bb, min(y0 + g * RK + k, H - 1) * lv.P + gxe);
     } else {
 #pragma unroll
-      for (int k = 0; k < RK; ++k) bvv[k] = 0.0f;
+      for (int k = 0; k < RK; ++k) bvv[k] = Px2{{0.0f, 0.0f}};
     }
   }
   {
-    const auto col = F.col(min(x0 + c, lv.W - 1));
-    float v[RJ];
-    bool kv[RJ];
+    const auto col = F.col(gxe);
+    Px2 v[RJ];
     if constexpr (kProlong) {
       // the rows' own inputs first, then the coarse patch
-      typename Former<MODE, TU, TC>::Pre pr[RJ];
+      typename Former<MODE, TU, TC>::Pre2 pr[RJ];
 #pragma unroll
       for (int j = 0; j < RJ; ++j) {
         const int ty = min(g + NG * j, TH - 1);
-        pr[j] = F.pre(col, min(max(y0 - 1 + ty, 0), lv.H - 1));
+        pr[j] = F.pre2(col, min(max(y0 - 1 + ty, 0), H - 1));
       }
       if (!act) return;  // the whole workgroup: one channel
       // coarse cells (x0/2 - 1 .. x0/2 + 32) x (y0/2 - 1 .. y0/2 + 16), clamped
@@ -863,16 +966,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
 #pragma unroll
       for (int j = 0; j < RJ; ++j) {
         const int ty = min(g + NG * j, TH - 1);
-        v[j] = F.fin(col, min(max(y0 - 1 + ty, 0), lv.H - 1), pr[j]);
-        kv[j] = pr[j].known;
+        v[j] = F.fin2(col, min(max(y0 - 1 + ty, 0), H - 1), pr[j]);
       }
     } else {
 #pragma unroll
       for (int j = 0; j < RJ; ++j) {
         // rows past the halo repeat a valid row (their value is not stored)
         const int ty = min(g + NG * j, TH - 1);
-        const int gy = min(max(y0 - 1 + ty, 0), lv.H - 1);
-        v[j] = F.value(col, gy, kv[j]);
+        v[j] = F.value2(col, min(max(y0 - 1 + ty, 0), H - 1));
       }
       if (!act) return;  // the whole workgroup: one channel
     }
@@ -880,78 +981,97 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
     for (int j = 0; j < RJ; ++j) {
       const int ty = g + NG * j;
       if (ty < TH) {
-        t[ty][c + 1] = v[j];
-        if constexpr (kProlong) kt[ty][c + 1] = kv[j];
+        const float vl = lastodd ? v[j].v[1] : v[j].v[0];  // column W - 1
+        const float v0 = gx <= W - 1 ? v[j].v[0] : vl;
+        const float v1 = gx + 1 <= W - 1 ? v[j].v[1] : vl;
+        typedef float v2 __attribute__((ext_vector_type(2)));
+        *(v2*)&t[ty][2 * q + 2] = v2{v0, v1};
       }
     }
   }
   if (threadIdx.x < 2 * TH) {
-    // halo columns tx = 0 and tx = TW - 1
+    // halo columns x0 - 1 and x0 + 64 (clamped: the mirror at the image edge)
     const int side = threadIdx.x / TH, ty = threadIdx.x - side * TH;
-    const int gx = side == 0 ? max(x0 - 1, 0) : min(x0 + kTileW, lv.W - 1);
-    const int gy = min(max(y0 - 1 + ty, 0), lv.H - 1);
-    t[ty][side == 0 ? 0 : TW - 1] = F.value(F.col(gx), gy);
+    const int hx = side == 0 ? max(x0 - 1, 0) : min(x0 + kTileW, W - 1);
+    const int gy = min(max(y0 - 1 + ty, 0), H - 1);
+    // (a prolongation's coarse patch covers the halo columns' stencils too)
+    t[ty][side == 0 ? 1 : kTileW + 2] = F.value(F.col(hx), gy);
   }
   __syncthreads();
-  const bool colin = gx < lv.W;
   const bool rest = mode_rest(MODE) && a.rest;
   __shared__ float rt[mode_rest(MODE) ? kTileH : 1][mode_rest(MODE) ? kTileW : 1];
   const Fld<TU> uo(a.u_out, (size_t)ch * lv.plane, a.s_u, a.rho, ch);
   const Fld<TU> ro(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);
   const Fld<TC> rlo(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);  // r_tc
   double acc = 0.0;
-  if constexpr (kProlong) {
-    // the known flags were read in phase 1
-#pragma unroll
-    for (int k = 0; k < RK; ++k) mk[k] = kt[g * RK + k + 1][c + 1];
-  }
   if constexpr (mode_fin(MODE)) {
 #pragma unroll
-    for (int k = 0; k < RK; ++k) mk[k] = glb(a.c)[min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc];
+    for (int k = 0; k < RK; ++k) mk[k] = ld_mask2(a.c, min(y0 + g * RK + k, H - 1) * lv.P + gxe);
     if (!a.solution) {
 #pragma unroll
-      for (int k = 0; k < RK; ++k) bvv[k] = F.bb.ld(min(y0 + g * RK + k, lv.H - 1) * lv.P + gxc);
+      for (int k = 0; k < RK; ++k) bvv[k] = ld2(F.bb, min(y0 + g * RK + k, H - 1) * lv.P + gxe);
     } else {
 #pragma unroll
-      for (int k = 0; k < RK; ++k) bvv[k] = 0.0f;
+      for (int k = 0; k < RK; ++k) bvv[k] = Px2{{0.0f, 0.0f}};
     }
   }
-
+  const bool in0 = gx < W, in1 = gx + 1 < W;
+  const bool r_small = mode_fin(MODE) || ((MODE == PASS_PSOL || MODE == PASS_RES) && a.r_tc);
 #pragma unroll
   for (int k = 0; k < RK; ++k) {
     const int ty = g * RK + k;
     const int gy = y0 + ty;
-    if (colin && gy < lv.H) {
-      const int off = gy * lv.P + gx;
-      const float u = t[ty + 1][c + 1];
-      if constexpr (MODE != PASS_RES) uo.st(off, u);
-      const double ud = u;
-      const double nb = ((double)t[ty + 1][c] + (double)t[ty + 1][c + 2]) +
-                        ((double)t[ty][c + 1] + (double)t[ty + 2][c + 1]);
-      const bool known = mk[k] != 0;
-      const double bv = bvv[k];
-      double r;
+    if (!(in0 && gy < H)) continue;
+    const int off = gy * lv.P + gx;
+    const float* row = &t[ty + 1][0];
+    const float u0 = row[2 * q + 2], u1 = row[2 * q + 3];
+    const float ul = row[2 * q + 1], ur = row[2 * q + 4];
+    const float up0 = t[ty][2 * q + 2], up1 = t[ty][2 * q + 3];
+    const float dn0 = t[ty + 2][2 * q + 2], dn1 = t[ty + 2][2 * q + 3];
+    if constexpr (MODE != PASS_RES) {
+      if (in1)
+        st2(uo, off, u0, u1);
+      else
+        uo.st(off, u0);
+    }
+    double r[2];
+    {
+      const double nb0 = ((double)ul + (double)u1) + ((double)up0 + (double)dn0);
+      const double nb1 = ((double)u0 + (double)ur) + ((double)up1 + (double)dn1);
+      const bool kn0 = (mk[k] & 0xffu) != 0, kn1 = (mk[k] >> 8) != 0;
+      const double b0 = bvv[k].v[0], b1 = bvv[k].v[1];
       if constexpr (MODE == PASS_RES) {
-        r = known ? bv - ud : bv - fma(4.0, ud, -nb);
+        r[0] = kn0 ? b0 - (double)u0 : b0 - fma(4.0, (double)u0, -nb0);
+        r[1] = kn1 ? b1 - (double)u1 : b1 - fma(4.0, (double)u1, -nb1);
       } else {
         // Every pass but the residual-only one leaves u == b at known pixels, so
         // the residual there is exactly 0; and b is 0 at the unknown pixels of a
         // solution problem, so it is read only for correction problems.
-        r = known ? 0.0 : bv - fma(4.0, ud, -nb);
+        r[0] = kn0 ? 0.0 : b0 - fma(4.0, (double)u0, -nb0);
+        r[1] = kn1 ? 0.0 : b1 - fma(4.0, (double)u1, -nb1);
       }
-      const float rf = (float)r;
-      if constexpr (mode_rest(MODE)) {
-        if (rest) {
-          rt[ty][c] = rf;
-          continue;
-        }
-      }
-      if (mode_fin(MODE) || ((MODE == PASS_PSOL || MODE == PASS_RES) && a.r_tc))
-        rlo.st(off, rf);
-      else
-        ro.st(off, rf);
-      acc += r * r;
     }
+    const float rf0 = (float)r[0], rf1 = (float)r[1];
+    if constexpr (mode_rest(MODE)) {
+      if (rest) {
+        rt[ty][2 * q] = rf0;
+        rt[ty][2 * q + 1] = rf1;
+        continue;
+      }
+    }
+    if (r_small) {
+      if (in1)
+        st2(rlo, off, rf0, rf1);
+      else
+        rlo.st(off, rf0);
+    } else {
+      if (in1)
+        st2(ro, off, rf0, rf1);
+      else
+        ro.st(off, rf0);
+    }
+    acc += r[0] * r[0];
+    if (in1) acc += r[1] * r[1];
   }
   if constexpr (mode_rest(MODE)) {
     if (rest) {
@@ -963,8 +1083,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
       const Fld<TC> uco(a.uc0, (size_t)ch * cl.plane, a.s_cr, a.rho, ch);
       constexpr int CW = kTileW / 2, CH = kTileH / 2;
 #pragma unroll
-      for (int q = threadIdx.x; q < CW * CH; q += kPassThreads) {
-        const int X = (x0 >> 1) + (q % CW), Y = (y0 >> 1) + (q / CW);
+      for (int qq = threadIdx.x; qq < CW * CH; qq += kPassThreads) {
+        const int X = (x0 >> 1) + (qq % CW), Y = (y0 >> 1) + (qq / CW);
         if (X < cl.W && Y < cl.H) {
           const int occ = Y * cl.P + X;
           double v = 0.0;
@@ -974,7 +1094,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
             for (int dy = 0; dy < 2; ++dy)
               for (int dx = 0; dx < 2; ++dx) {
                 const int y = 2 * Y + dy, x = 2 * X + dx;
-                if (y < lv.H && x < lv.W) {
+                if (y < H && x < W) {
                   sr += (double)rt[y - y0][x - x0];
                   ++n;
                 }
@@ -1301,21 +1421,22 @@ struct BlockCG2 {
     c = lane & (C - 1);
     g = lane / C;
     float dl[2], dr[2];
-    int cx[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int lx = 2 * c + h;
       dl[h] = lx > 0 ? 1.0f : (x0 > 0 ? gamma : 0.0f);
       dr[h] = lx < bw - 1 ? 1.0f : (x0 + bw < W ? gamma : 0.0f);
-      cx[h] = x0 + min(lx, bw - 1);
     }
+    // the lane's two columns as one 2-byte load (the block's last pair when
+    // the lane lies past a clipped block: those pixels are not used)
+    const int pe = x0 + min(2 * c, (bw - 1) & ~1);
     uint8_t cm[2][R];
-    const gptr<const uint8_t> mg = glb(m);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const unsigned row = (unsigned)(y0 + min(g * R + k, bh - 1)) * (unsigned)P;
-      cm[0][k] = mg[row + cx[0]];
-      cm[1][k] = mg[row + cx[1]];
+      const unsigned short w = ld_mask2(m, (int)(row + pe));
+      cm[0][k] = (uint8_t)(w & 0xffu);
+      cm[1][k] = (uint8_t)(w >> 8);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -1407,21 +1528,22 @@ struct BlockCGh2 {
     c = lane & (C - 1);
     g = lane / C;
     float dl[2], dr[2];
-    int cx[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int lx = 2 * c + h;
       dl[h] = lx > 0 ? 1.0f : (x0 > 0 ? gamma : 0.0f);
       dr[h] = lx < bw - 1 ? 1.0f : (x0 + bw < W ? gamma : 0.0f);
-      cx[h] = x0 + min(lx, bw - 1);
     }
+    // the lane's two columns as one 2-byte load (the block's last pair when
+    // the lane lies past a clipped block: those pixels are not used)
+    const int pe = x0 + min(2 * c, (bw - 1) & ~1);
     uint8_t cm[2][R];
-    const gptr<const uint8_t> mg = glb(m);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const unsigned row = (unsigned)(y0 + min(g * R + k, bh - 1)) * (unsigned)P;
-      cm[0][k] = mg[row + cx[0]];
-      cm[1][k] = mg[row + cx[1]];
+      const unsigned short w = ld_mask2(m, (int)(row + pe));
+      cm[0][k] = (uint8_t)(w & 0xffu);
+      cm[1][k] = (uint8_t)(w >> 8);
     }
 #pragma unroll
     for (int k = 0; k < R; ++k) {
@@ -1560,14 +1682,15 @@ __device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsig
   BlockCG2 cg;
   cg.setup(x0, y0, bw, bh, lv.W, lv.H, a.gamma, a.c, lv.P);
   float rho[2][R], v[2][R];
-  const gptr<const float> r = glb((const float*)a.r + (size_t)ch * lv.plane);
   {
-    const unsigned cx0 = x0 + min(2 * cg.c, bw - 1), cx1 = x0 + min(2 * cg.c + 1, bw - 1);
+    // pair loads (pixels outside the block are zeroed by the solve)
+    const Fld<float> r(a.r, (size_t)ch * lv.plane, Sc{1.0f, 0}, a.rho, ch);
+    const int pe = x0 + min(2 * cg.c, (bw - 1) & ~1);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const unsigned row = (unsigned)(y0 + min(cg.g * R + k, bh - 1)) * (unsigned)lv.P;
-      rho[0][k] = r[row + cx0];
-      rho[1][k] = r[row + cx1];
+      const Px2 v = ld2(r, (y0 + min(cg.g * R + k, bh - 1)) * lv.P + pe);
+      rho[0][k] = v.v[0];
+      rho[1][k] = v.v[1];
     }
   }
   const float thr = block_threshold(a, ch, bw, bh);
@@ -1583,9 +1706,11 @@ __device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsig
     const int ly = cg.g * R + k;
     if (ly >= bh) continue;
     const float wy = pou_weight(ly, lv.nby, by, B, lv.o, a.inv_o1);
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-      if (2 * cg.c + h < bw) out.st(ly * B + 2 * cg.c + h, wx[h] * wy * v[h][k]);
+    const float c0 = wx[0] * wy * v[0][k], c1 = wx[1] * wy * v[1][k];
+    if (2 * cg.c + 1 < bw)
+      st2(out, ly * B + 2 * cg.c, c0, c1);
+    else if (2 * cg.c < bw)
+      out.st(ly * B + 2 * cg.c, c0);
   }
   count_iterations(a, (size_t)ch * nblk + bi, it);
 }
@@ -1606,13 +1731,14 @@ __device__ __forceinline__ void block_body_h(const BlockArgs& a, int ch, unsigne
   const Fld<TR> rf(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);
   float raw[2][R];
   {
-    const gptr<const TR> r = glb((const TR*)a.r + (size_t)ch * lv.plane);
-    const unsigned cx0 = x0 + min(2 * cg.c, bw - 1), cx1 = x0 + min(2 * cg.c + 1, bw - 1);
+    // pair loads of the stored values (unit scale: rs is applied below)
+    const Fld<TR> r(a.r, (size_t)ch * lv.plane, Sc{1.0f, 0}, a.rho, ch);
+    const int pe = x0 + min(2 * cg.c, (bw - 1) & ~1);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const unsigned row = (unsigned)(y0 + min(cg.g * R + k, bh - 1)) * (unsigned)lv.P;
-      raw[0][k] = (float)r[row + cx0];
-      raw[1][k] = (float)r[row + cx1];
+      const Px2 v = ld2(r, (y0 + min(cg.g * R + k, bh - 1)) * lv.P + pe);
+      raw[0][k] = v.v[0];
+      raw[1][k] = v.v[1];
     }
   }
   float ss = 0.0f;

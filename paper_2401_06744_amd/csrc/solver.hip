@@ -36,6 +36,10 @@ Opts resolve(const inpaint_opts* p) {
     fail(INPAINT_E_INVALID, "unknown precision");
   if (o.B != 16 && o.B != 32) fail(INPAINT_E_INVALID, "block must be 16 or 32");
   if (o.o < 2 || 2 * o.o > o.B) fail(INPAINT_E_INVALID, "overlap must satisfy 2 <= overlap <= block/2");
+  // the overlap is twice the per-side halo of a block; with an even overlap
+  // (and block) every block starts at an even column, which the grid passes'
+  // pixel-pair accesses rely on
+  if (o.o % 2 != 0) fail(INPAINT_E_INVALID, "overlap must be even (twice the per-side halo)");
   if (!(o.gamma > 0.0f && o.gamma <= 1.0f)) fail(INPAINT_E_INVALID, "gamma must lie in (0, 1]");
   if (!(o.tau >= 0.0f) || !std::isfinite(o.tau)) fail(INPAINT_E_INVALID, "tau must be finite and >= 0");
   if (o.maxit < 0 || o.coarse_maxit < 0) fail(INPAINT_E_INVALID, "iteration caps must be >= 0");

@@ -39,6 +39,21 @@ def pytest_configure(config):
     if _refs is None and _selects_fullsize(config):
         import oracle_refs
         _refs = oracle_refs.RefPool(oracle_refs.full_size_jobs())
+        _refs.report = _live_printer(config)
+
+
+def _live_printer(config):
+    """A print that reaches the terminal while pytest captures output (the
+    progress of long waits for oracle references)."""
+    capman = config.pluginmanager.getplugin("capturemanager")
+
+    def report(msg):
+        if capman is None:
+            print(msg, flush=True)
+            return
+        with capman.global_and_fixture_disabled():
+            print(msg, flush=True)
+    return report
 
 
 def pytest_unconfigure(config):
@@ -49,13 +64,14 @@ def pytest_unconfigure(config):
 
 
 @pytest.fixture(scope="session")
-def oracle_refs():
+def oracle_refs(pytestconfig):
     """The session's pool of oracle reference solutions (started on demand
     when the session did not start it up front)."""
     global _refs
     if _refs is None:
         import oracle_refs as mod
         _refs = mod.RefPool(mod.full_size_jobs())
+        _refs.report = _live_printer(pytestconfig)
     return _refs
 
 

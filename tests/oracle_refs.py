@@ -94,13 +94,26 @@ class RefPool:
         self._pool = mp.get_context("spawn").Pool(workers, initializer=_init_worker)
         self._res = {job: self._pool.apply_async(solve_job, (job,)) for job in jobs}
         self._cache = {}
+        self.report = lambda msg: print(msg, flush=True)
 
     def get(self, job, timeout=1800.0):
         if job not in self._cache:
             if job not in self._res:
                 self._res[job] = self._pool.apply_async(solve_job, (job,))
             t = time.perf_counter()
-            self._cache[job] = self._res[job].get(timeout)
+            res = self._res[job]
+            # wait in slices with a progress line, so that a long wait is
+            # visibly a wait and not a hang
+            while not res.ready():
+                waited = time.perf_counter() - t
+                if waited > timeout:
+                    raise TimeoutError(f"oracle reference {job}: no result after {waited:.0f} s")
+                res.wait(min(30.0, timeout - waited))
+                if not res.ready():
+                    done = sum(r.ready() for r in self._res.values())
+                    self.report(f"oracle reference {job}: waiting {time.perf_counter() - t:.0f} s "
+                                f"({done}/{len(self._res)} references done)")
+            self._cache[job] = res.get(0)
             waited = time.perf_counter() - t
             if waited > 1.0:
                 print(f"oracle reference {job}: waited {waited:.1f} s", flush=True)

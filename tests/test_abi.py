@@ -102,3 +102,11 @@ def test_sizes_beyond_32_bit_offsets_are_rejected_before_any_work():
     assert code == binding.E_INVALID and "2^24" in msg, (code, msg)
     code, msg = _fake_solve(3, 1 << 24)
     assert code == binding.E_INVALID and "2^24" in msg, (code, msg)
+
+
+def test_odd_overlaps_are_rejected_before_any_work():
+    """The overlap is twice the per-side halo of a block (even): an odd one is
+    an invalid option, rejected before any pointer is used."""
+    for o in (3, 5, 7):
+        code, msg = _fake_solve(64, 64, overlap=o)
+        assert code == binding.E_INVALID and "even" in msg, (o, code, msg)

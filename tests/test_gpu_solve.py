@@ -213,7 +213,7 @@ def test_errors():
     with pytest.raises(binding.InpaintError) as e:
         _solve(g, m)
     assert e.value.code == binding.E_INVALID
-    for bad in ({"block": 24}, {"overlap": 1}, {"overlap": 17}, {"gamma": 1.5}, {"schedule": 9}):
+    for bad in ({"block": 24}, {"overlap": 1}, {"overlap": 3}, {"overlap": 17}, {"gamma": 1.5}, {"schedule": 9}):
         with pytest.raises(binding.InpaintError) as e:
             _solve(f, m, **bad)
         assert e.value.code == binding.E_INVALID
@@ -244,37 +244,44 @@ def test_unknown_values_never_read_and_channels_independent():
         assert np.array_equal(single[0], out[ch])
 
 
-def _overflowing(f, m, ch):
-    """f with the known pixels of channel ch set to +-3e38 in a checkerboard:
-    finite data whose residual overflows float32 (and whose squares overflow
-    the float32 dot products of the block and coarse solves)."""
+def _overflowing(f, m, ch, value=1e6):
+    """f with the known pixels of channel ch set to +-value in a checkerboard:
+    finite data beyond the float16 range (65504), which the float16 form's
+    coarse known values and iterates (stored unscaled) cannot hold."""
     g = f.copy()
     ys, xs = np.nonzero(m)
-    g[ch, ys, xs] = np.where((ys + xs) % 2 == 0, 3e38, -3e38).astype(np.float32)
+    g[ch, ys, xs] = np.where((ys + xs) % 2 == 0, value, -value).astype(np.float32)
     return g
 
 
 def test_overflowing_known_values_diverge_alone():
-    """A channel whose residual becomes non-finite stops as diverged: the solve
-    returns E_DIVERGED with rel_res NaN, while the problem's other channels and
-    the other problems of a batch are solved exactly as alone."""
+    """A channel whose residual becomes non-finite stops as diverged: in the
+    float16 form, known values beyond the float16 range overflow the coarse
+    levels' 16-bit fields, and the solve returns E_DIVERGED with rel_res NaN,
+    while the problem's other channels and the other problems of a batch are
+    solved exactly as alone."""
+    opts = binding.make_opts(precision=binding.PREC_FP16)
     f = synth.frame_image(150, 90, 3, seed=41)
     m = synth.bernoulli_mask(150, 90, 0.05, seed=42)
     g = _overflowing(f, m, 1)
     with pytest.raises(binding.InpaintError) as e:
-        binding.inpaint_solve_ex(g, m, TOL)
+        binding.inpaint_solve_ex(g, m, TOL, opts=opts)
     assert e.value.code == binding.E_DIVERGED
     a = (synth.frame_image(97, 61, 1, seed=43), synth.bernoulli_mask(97, 61, 0.03, seed=44))
-    outs, st, stats = binding.inpaint_solve_batched([a, (g, m)], TOL, raise_on_error=False)
+    outs, st, stats = binding.inpaint_solve_batched([a, (g, m)], TOL, opts=opts, raise_on_error=False)
     assert st == binding.E_DIVERGED
     assert stats[0]["status"] == binding.OK and stats[1]["status"] == binding.E_DIVERGED
     assert np.isnan(stats[1]["rel_res"])
-    assert np.array_equal(outs[0], _solve(*a)[0])
+    assert np.array_equal(outs[0], binding.inpaint_solve_ex(*a, TOL, opts=opts)[0])
     for ch in (0, 2):
-        single, st1, _ = _solve(np.ascontiguousarray(f[ch:ch + 1]), m)
+        single, st1, _ = binding.inpaint_solve_ex(np.ascontiguousarray(f[ch:ch + 1]), m, TOL, opts=opts)
         assert st1 == binding.OK and np.array_equal(outs[1][ch], single[0]), ch
     # the diverged channel stops at its first non-finite test, not at the cycle cap
     assert stats[1]["cycles"] < 30
+    # the same values are within float32's range: the float32 form does not diverge
+    out32, st32, _ = binding.inpaint_solve_ex(g, m, TOL)
+    assert st32 in (binding.OK, binding.NOT_CONVERGED)
+    assert np.array_equal(out32[:, m != 0], g[:, m != 0])
 
 
 def test_repeatable_and_device_pointers_and_alias():
