@@ -189,6 +189,35 @@ int inpaint_solve_ex(const float* f, const uint8_t* mask, int W, int H, int chan
                      inpaint_stats* stats);
 
 /*
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the solve of inpaint_solve_ex with no
+ * device allocation.  The grid hierarchy and the launch arguments live in one
+ * fixed device array of INPAINT_NOALLOC_SCRATCH_BYTES bytes per GPU, which
+ * the library holds from its load until the process ends; the call allocates
+ * no device or pinned host memory and creates no graph, stream or event.
+ *   f, mask, out  device memory only (host pointers: E_INVALID), with the
+ *                 layout, ownership and aliasing rules of inpaint_solve_ex
+ *   opts          as for inpaint_solve_ex; the CG schedules are rejected
+ *                 (E_INVALID); opts.profile is ignored
+ *   stream        hipStream_t as void*, NULL = the null stream
+ *   stats         as for inpaint_solve_ex, except that gpu_ms is the host time
+ *                 of the call and the local CG and kernel profile fields are 0
+ * A problem whose hierarchy and launch arguments need more than the array
+ * holds is rejected before any device work (E_INVALID, the message gives the
+ * bytes needed): with the default block and overlap, float32 fields fit up to
+ * 1920x1080 with 3 channels or 3840x2160 with 1 channel.  Every call on a GPU
+ * uses that GPU's one array, whose contents are the last call's: the library
+ * serialises calls on the same device (a second caller waits), so calls that
+ * would overlap in time run one after the other.  Returns after the result is
+ * in out.  Results are bit-identical to inpaint_solve_ex with the same
+ * options.
+ */
+#define INPAINT_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int inpaint_solve_noalloc(const float* f, const uint8_t* mask, int W, int H, int channels,
+                          double tol, float* out, const inpaint_opts* opts, void* stream,
+                          inpaint_stats* stats);
+
+/*
  * Bound on the device memory that single and batched solves keep cached
  * between calls: the grid hierarchy of each problem shape (block, overlap and
  * precision) already solved is kept for the next call of that shape, and idle

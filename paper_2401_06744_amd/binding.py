@@ -33,8 +33,10 @@ EXPORTED = [
     "inpaint_debug_oras_step", "inpaint_debug_restrict", "inpaint_debug_prolong",
     "inpaint_solve_batched", "inpaint_server_create", "inpaint_server_submit",
     "inpaint_server_poll", "inpaint_server_wait", "inpaint_server_destroy", "inpaint_autotune",
-    "inpaint_cache_limit",
+    "inpaint_cache_limit", "inpaint_solve_noalloc",
 ]
+# device bytes of the fixed array behind inpaint_solve_noalloc (INPAINT_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 class InpaintOpts(ct.Structure):
@@ -99,6 +101,8 @@ def lib() -> ct.CDLL:
         L.inpaint_solve.argtypes = [vp, vp, i, i, i, d, vp]
         L.inpaint_solve_ex.argtypes = [vp, vp, i, i, i, d, vp, ct.POINTER(InpaintOpts), vp,
                                        ct.POINTER(InpaintStats)]
+        L.inpaint_solve_noalloc.argtypes = [vp, vp, i, i, i, d, vp, ct.POINTER(InpaintOpts), vp,
+                                             ct.POINTER(InpaintStats)]
         L.inpaint_rel_res.argtypes = [vp, vp, vp, i, i, i, vp]
         L.inpaint_last_error.restype = ct.c_char_p
         L.inpaint_version.restype = ct.c_char_p
@@ -206,6 +210,19 @@ def inpaint_solve_ex(f, mask, tol: float = 1e-6, out=None, opts: InpaintOpts | N
     st = _check(lib().inpaint_solve_ex(_ptr(f), _ptr(mask), W, H, C, tol, _ptr(out),
                                        ct.byref(opts) if opts is not None else None,
                                        _stream_handle(stream), ct.byref(stats)))
+    return out, st, stats.as_dict()
+
+
+def inpaint_solve_noalloc(f, mask, tol: float = 1e-6, out=None, opts: InpaintOpts | None = None,
+                          stream=None):
+    """As inpaint_solve_ex, without device allocation in the library (device
+    tensors only); returns (out, status, stats dict)."""
+    C, H, W = _shape(f)
+    out = _empty_like(f) if out is None else out
+    stats = InpaintStats()
+    st = _check(lib().inpaint_solve_noalloc(_ptr(f), _ptr(mask), W, H, C, tol, _ptr(out),
+                                            ct.byref(opts) if opts is not None else None,
+                                            _stream_handle(stream), ct.byref(stats)))
     return out, st, stats.as_dict()
 
 

@@ -15,8 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libinpaint.so")
-SOURCES = ["kernels.hip", "solver.hip", "batch.hip", "server.hip", "autotune.hip", "errors.cpp",
-           "serve_core.cpp"]
+SOURCES = ["kernels.hip", "solver.hip", "batch.hip", "server.hip", "autotune.hip", "noalloc.hip",
+           "errors.cpp", "serve_core.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -163,6 +163,10 @@ void build(Plan& P, const std::vector<Member*>& ms, Body&& body) {
   }
 }
 
+// Host-side iteration state of the members (which buffer of each level holds
+// the iterate, CG slots): cycle plans alternate until it repeats.
+std::vector<int> level_state(const std::vector<Member*>& ms);
+
 // Copy the plans' argument arrays into one device buffer owned by `*buf`
 // (grown as needed) and point each plan at its part.
 void upload(std::vector<Plan*> plans, unsigned char** buf, size_t* cap, hipStream_t s);

@@ -505,8 +505,6 @@ void add_gather(Plan& P, const std::vector<Member*>& ms, int* flags_dev) {
   P.end();
 }
 
-namespace {
-
 std::vector<int> level_state(const std::vector<Member*>& ms) {
   std::vector<int> s;
   for (Member* m : ms) {
@@ -518,8 +516,6 @@ std::vector<int> level_state(const std::vector<Member*>& ms) {
   }
   return s;
 }
-
-}  // namespace
 
 // ---------------------------------------------------------------------------
 // batch contexts (device copies of the plans, graphs, flag buffers), cached by

@@ -109,7 +109,8 @@ struct Workspace {
   Level lv[kMaxLevels];
   void* base = nullptr;
   size_t bytes = 0;
-  double* partials = nullptr;   // [C][max tiles], kept at -1 between passes
+  size_t maxtiles = 0;          // most pass workgroups over any level
+  double* partials = nullptr;   // [C][maxtiles], kept unset between passes
   unsigned* counters = nullptr; // [C], kept at 0 between passes
   double* snorm = nullptr;  // [L][C]
   double* den = nullptr;    // [C]
@@ -159,6 +160,14 @@ struct Lease {
 std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc = true);
 // Device bytes of create_workspace(k).
 size_t workspace_bytes(const Key& k);
+// A workspace for key k whose buffers live in caller-owned device memory at
+// base (capacity bytes; nothing is allocated, the workspace never frees it):
+// Fail (E_INVALID) when it needs more than capacity; its counters and norm
+// partials are cleared on stream s.
+std::unique_ptr<Workspace> bind_workspace(const Key& k, void* base, size_t capacity, hipStream_t s);
+// Restore the state the kernels expect between passes (counters 0, norm
+// partials unset, convergence-test counts 0), on stream s.
+void clear_workspace_state(Workspace* ws, hipStream_t s);
 
 // Lease a free workspace for (device, sizes, channels, block, overlap,
 // coarsest side, precision), creating it on first use.  Idle workspaces stay

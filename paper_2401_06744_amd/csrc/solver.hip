@@ -90,25 +90,24 @@ std::vector<std::pair<int, int>> level_sizes(int W, int H, int coarsest) {
   return s;
 }
 
-std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
-  check_geometry(k.W, k.H, k.B, k.o);
-  auto ws = std::make_unique<Workspace>();
-  ws->key = k;
+// Lay out the workspace of key k: the byte size of every buffer from offset 0
+// (ws->bytes) and, when base is not null, the buffers' addresses in base.
+static void lay_out(Workspace* ws, const Key& k, char* base) {
   const auto sizes = level_sizes(k.W, k.H, k.coarsest);
   if ((int)sizes.size() > kMaxLevels) fail(INPAINT_E_INVALID, "image too large for the level table");
+  ws->key = k;
   ws->L = (int)sizes.size();
   const int C = k.C;
   size_t off = 0;
   auto take = [&](size_t n) {
     const size_t at = off;
     off = round_up(off + n, 256);
-    return at;
+    return base ? base + at : nullptr;
   };
-  struct Offs { size_t c, b, u0, u1, r, contrib, it, e0, e1, d, rh, dp; };
-  std::vector<Offs> lo(ws->L);
   size_t maxtiles = 1;
   for (int l = 0; l < ws->L; ++l) {
-    LevelView& v = ws->lv[l].v;
+    Level& L = ws->lv[l];
+    LevelView& v = L.v;
     v.W = sizes[l].first;
     v.H = sizes[l].second;
     v.P = (int)round_up((size_t)v.W, 64);
@@ -121,79 +120,83 @@ std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
     // corrections and all coarser fields use the correction precision
     const size_t es = prec_bytes(k.prec);
     const size_t f = (size_t)C * v.plane * (l == 0 ? sizeof(float) : es);
-    lo[l].c = take(v.plane);
-    lo[l].b = take(f);
-    lo[l].u0 = take(f);
-    lo[l].u1 = take(f);
+    L.c = (uint8_t*)take(v.plane);
+    L.b = (float*)take(f);
+    L.u[0] = (float*)take(f);
+    L.u[1] = (float*)take(f);
     // the precision form's finest grid keeps its residual in 16 bits (d, rh)
     // beside the correction e; the float32 residual is not needed there
     const bool corr = l == 0 && k.prec == PREC_F16 && ws->L > 1;
-    lo[l].r = corr ? 0 : take(f);
+    L.r = corr ? nullptr : (float*)take(f);
     if (corr) {
       const size_t fe = (size_t)C * v.plane * es;
-      lo[l].e0 = take(fe);
-      lo[l].e1 = take(fe);
-      lo[l].d = take(fe);
-      lo[l].rh = take(fe);
+      L.e[0] = take(fe);
+      L.e[1] = take(fe);
+      L.d = take(fe);
+      L.rh = take(fe);
     }
-    lo[l].contrib = take((size_t)C * v.nbx * v.nby * k.B * k.B * es);
-    lo[l].it = take((size_t)2 * C * v.nbx * v.nby * sizeof(int));
+    L.contrib = (float*)take((size_t)C * v.nbx * v.nby * k.B * k.B * es);
+    L.itot = (int*)take((size_t)2 * C * v.nbx * v.nby * sizeof(int));
+    L.imax = L.itot ? L.itot + (size_t)C * v.nbx * v.nby : nullptr;
     // deferred norm partials: written by passes over this level or, for the
     // fused restriction, over the next finer one
     const size_t wt = std::max(pass_tiles(v), l > 0 ? pass_tiles(ws->lv[l - 1].v) : (size_t)0);
-    ws->lv[l].dstride = wt <= Run::kDeferMax ? (int)wt : 0;
-    lo[l].dp = ws->lv[l].dstride ? take((size_t)C * wt * sizeof(double)) : 0;
+    L.dstride = wt <= Run::kDeferMax ? (int)wt : 0;
+    L.dpart = L.dstride ? (double*)take((size_t)C * wt * sizeof(double)) : nullptr;
     maxtiles = std::max(maxtiles, pass_tiles(v));
   }
-  const size_t o_part = take((size_t)C * maxtiles * sizeof(double));
-  const size_t o_cnt = take((size_t)C * kCounterLines * 32 * sizeof(unsigned));
-  const size_t o_sn = take((size_t)ws->L * C * sizeof(double));
-  const size_t o_den = take((size_t)C * sizeof(double));
-  const size_t o_rho = take((size_t)C * sizeof(float));
+  ws->maxtiles = maxtiles;
+  ws->partials = (double*)take((size_t)C * maxtiles * sizeof(double));
+  ws->counters = (unsigned*)take((size_t)C * kCounterLines * 32 * sizeof(unsigned));
+  ws->snorm = (double*)take((size_t)ws->L * C * sizeof(double));
+  ws->den = (double*)take((size_t)C * sizeof(double));
+  ws->rho = (float*)take((size_t)C * sizeof(float));
   // relres[4] doubles, active[4], status[4] and checks[4] ints: one block of
   // kFlagInts ints, so that a poll is a single copy
-  const size_t o_flags = take(kFlagInts * sizeof(int));
-  const size_t o_cg = take((size_t)kMaxLevels * C * 3 * sizeof(unsigned long long));
+  char* flags = take(kFlagInts * sizeof(int));
+  ws->relres = (double*)flags;
+  ws->active = flags ? (int*)(flags + 32) : nullptr;
+  ws->status = flags ? (int*)(flags + 48) : nullptr;
+  ws->checks = flags ? (int*)(flags + 64) : nullptr;
+  ws->cgstat = (unsigned long long*)take((size_t)kMaxLevels * C * 3 * sizeof(unsigned long long));
   ws->bytes = off;
+}
+
+void clear_workspace_state(Workspace* ws, hipStream_t s) {
+  const int C = ws->key.C;
+  // counters 0 (a whole number of doubles of zero bits), partials unset,
+  // convergence-test counts 0
+  static_assert((kCounterLines * 32 * sizeof(unsigned)) % sizeof(double) == 0, "counter block size");
+  HIPCHK(launch_fill((double*)ws->counters, (size_t)C * kCounterLines * 32 * sizeof(unsigned) / sizeof(double),
+                     0.0, s));
+  HIPCHK(launch_fill(ws->partials, (size_t)C * ws->maxtiles, unset_partial(), s));
+  HIPCHK(launch_fill((double*)ws->checks, 4 * sizeof(int) / sizeof(double), 0.0, s));
+}
+
+std::unique_ptr<Workspace> create_workspace(const Key& k, bool alloc) {
+  check_geometry(k.W, k.H, k.B, k.o);
+  auto ws = std::make_unique<Workspace>();
+  lay_out(ws.get(), k, nullptr);
   if (!alloc) return ws;
-  HIPCHK(hipMalloc(&ws->base, off));
-  char* base = (char*)ws->base;
-  for (int l = 0; l < ws->L; ++l) {
-    Level& L = ws->lv[l];
-    L.c = (uint8_t*)(base + lo[l].c);
-    L.b = (float*)(base + lo[l].b);
-    L.u[0] = (float*)(base + lo[l].u0);
-    L.u[1] = (float*)(base + lo[l].u1);
-    const bool corr = l == 0 && k.prec == PREC_F16 && ws->L > 1;
-    L.r = corr ? nullptr : (float*)(base + lo[l].r);
-    if (corr) {
-      L.e[0] = base + lo[l].e0;
-      L.e[1] = base + lo[l].e1;
-      L.d = base + lo[l].d;
-      L.rh = base + lo[l].rh;
-    }
-    L.contrib = (float*)(base + lo[l].contrib);
-    L.itot = (int*)(base + lo[l].it);
-    L.dpart = L.dstride ? (double*)(base + lo[l].dp) : nullptr;
-    L.imax = L.itot + (size_t)C * L.v.nbx * L.v.nby;
-  }
-  ws->partials = (double*)(base + o_part);
-  ws->counters = (unsigned*)(base + o_cnt);
-  HIPCHK(hipMemset(ws->counters, 0, (size_t)C * kCounterLines * 32 * sizeof(unsigned)));
-  HIPCHK(launch_fill(ws->partials, (size_t)C * maxtiles, unset_partial(), nullptr));
+  HIPCHK(hipMalloc(&ws->base, ws->bytes));
+  lay_out(ws.get(), k, (char*)ws->base);
+  clear_workspace_state(ws.get(), nullptr);
   HIPCHK(hipDeviceSynchronize());
-  ws->snorm = (double*)(base + o_sn);
-  ws->den = (double*)(base + o_den);
-  ws->rho = (float*)(base + o_rho);
-  ws->relres = (double*)(base + o_flags);
-  ws->active = (int*)(base + o_flags + 32);
-  ws->status = (int*)(base + o_flags + 48);
-  ws->checks = (int*)(base + o_flags + 64);
-  HIPCHK(hipMemset(ws->checks, 0, 4 * sizeof(int)));
-  ws->cgstat = (unsigned long long*)(base + o_cg);
   HIPCHK(hipHostMalloc(&ws->host, 4096, hipHostMallocDefault));
   HIPCHK(hipEventCreate(&ws->ev0));
   HIPCHK(hipEventCreate(&ws->ev1));
+  return ws;
+}
+
+std::unique_ptr<Workspace> bind_workspace(const Key& k, void* base, size_t capacity, hipStream_t s) {
+  check_geometry(k.W, k.H, k.B, k.o);
+  auto ws = std::make_unique<Workspace>();
+  lay_out(ws.get(), k, nullptr);
+  if (ws->bytes > capacity)
+    fail(INPAINT_E_INVALID, "the problem's grid hierarchy needs " + std::to_string(ws->bytes) +
+                                " device bytes, more than the " + std::to_string(capacity) + " available");
+  lay_out(ws.get(), k, (char*)base);
+  clear_workspace_state(ws.get(), s);
   return ws;
 }
 

@@ -110,3 +110,14 @@ def test_odd_overlaps_are_rejected_before_any_work():
     for o in (3, 5, 7):
         code, msg = _fake_solve(64, 64, overlap=o)
         assert code == binding.E_INVALID and "even" in msg, (o, code, msg)
+
+
+def test_noalloc_entry_point_checks_before_device_work():
+    """inpaint_solve_noalloc rejects bad options and the comparison CG
+    schedules before it looks at the pointers or the device."""
+    lib = binding.lib()
+    for opts in (binding.make_opts(overlap=5), binding.make_opts(schedule=binding.SCHED_CG)):
+        code = lib.inpaint_solve_noalloc(ctypes.c_void_p(1 << 44), ctypes.c_void_p(2 << 44), 64, 64, 1,
+                                         1e-6, ctypes.c_void_p(3 << 44), ctypes.byref(opts), None, None)
+        assert code == binding.E_INVALID, (code, binding.inpaint_last_error())
+    assert binding.NOALLOC_SCRATCH_BYTES == 256 << 20
