@@ -267,6 +267,9 @@ def main() -> int:
     ap.add_argument("--width", type=int, default=3840)
     ap.add_argument("--height", type=int, default=2160)
     ap.add_argument("--density", type=float, default=0.04)
+    ap.add_argument("--precision", choices=["fp32", "fp16", "bf16"], default="fp32",
+                    help="correction storage of the timed and profiled legs (profiling aid; "
+                         "the headline value is float32)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -278,8 +281,9 @@ def main() -> int:
     full = (args.width, args.height) == (3840, 2160)
     legs = [x for x in args.forms.split(",") if x]
     for x in legs:
-        if x not in FORM_LEGS:
-            print(f"bench.py: unknown form leg {x!r} (known: {', '.join(FORM_LEGS)})", file=sys.stderr)
+        if x not in FORM_LEGS + EXTRA_LEGS:
+            print(f"bench.py: unknown form leg {x!r} (known: {', '.join(FORM_LEGS + EXTRA_LEGS)})",
+                  file=sys.stderr)
             return 2
     forms = not args.no_forms and full and bool(legs)
     check = not args.no_oracle_check
@@ -294,6 +298,8 @@ def main() -> int:
             jobs += [("4k", args.density, ch) for ch in range(3)]
         if forms and "precision" in legs:
             jobs += [("prec", k, ch) for k in ("bernoulli", "bluenoise") for ch in range(3)]
+        elif forms and "tuning" in legs:
+            jobs += [("prec", "bernoulli", ch) for ch in range(3)]
         if forms and "serving" in legs:
             jobs += [("serve", (0, j), ch) for j in (0, 1) for ch in range(3)]
         if forms and "sweeps" in legs:
@@ -314,7 +320,8 @@ def main() -> int:
     md = torch.from_numpy(m).to(dev)
     od = torch.empty_like(fd)
     stream = torch.cuda.current_stream()
-    opts = binding.make_opts()
+    prec = {"fp32": binding.PREC_FP32, "fp16": binding.PREC_FP16, "bf16": binding.PREC_BF16}[args.precision]
+    opts = binding.make_opts(precision=prec)
 
     def step(o, out=od):
         return binding.inpaint_solve_ex(fd, md, args.tol, out=out, opts=o, stream=stream)
@@ -345,7 +352,7 @@ def main() -> int:
     out_last = od.clone()
 
     # ---- profiled leg: per-kernel HIP events on the solve's stream
-    popts = binding.make_opts(profile=1)
+    popts = binding.make_opts(profile=1, precision=prec)
     kms = np.zeros(len(binding.KERNELS))
     kcalls = np.zeros(len(binding.KERNELS))
     cg_fin = 0.0
@@ -461,6 +468,9 @@ def main() -> int:
         if "sweeps" in legs:
             form_res["sweeps"] = sweep_leg(binding, torch, synth, args, fd, pending)
             log("resolution and density sweeps done")
+        if "tuning" in legs:
+            form_res["tuning"] = tuning_leg(binding, torch, synth, args, fd, md, pending)
+            log("tuning sweep done")
         if "batched" in legs:
             form_res["batched"] = batched_leg(binding, torch, synth, args)
             log("batched form done")
@@ -548,12 +558,13 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "fp16": "f32+f16", "bf16": "f32+bf16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{W}x{H} RGB frame, shared Bernoulli {args.density:.0%} mask, "
                                f"FMG+ORAS to rel-res {args.tol:g}",
                    "W": W, "H": H, "channels": C, "density": args.density, "tol": args.tol,
-                   "block": 32, "overlap": 6, "schedule": "reduced FMG"},
+                   "block": 32, "overlap": 6, "schedule": "reduced FMG",
+                   "correction_storage": args.precision},
         "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 4),
                        "p99": round(float(np.percentile(lat_ms, 99)), 4)},
         "cycles": k_cyc,
@@ -661,9 +672,45 @@ def solvers_leg(binding, torch, args, fd, md, pending):
     return out
 
 
+def tuning_leg(binding, torch, synth, args, fd4, md4, pending):
+    """The block solve's work trade (Section 3.1 block and overlap, the local
+    stop): overlap {4, 6} x tau {0.002, 0.005, 0.01} x local cap {8, 16} on the
+    headline 4 % frame and the 1 % Bernoulli frame at rel-res 1e-6: frames/s,
+    V-cycles, finest-grid local CG pixel-iterations per frame, max error of
+    every channel against the oracle."""
+    out = {"workload": "3840x2160 RGB, 4 % and 1 % Bernoulli masks, rel-res 1e-6, float32, "
+                       "block 32, gamma 0.5; each setting timed over 8 solves"}
+    f1, m1 = synth.config_precision("bernoulli")
+    frames = [("bernoulli_4pct", fd4, md4, ("4k", args.density)),
+              ("bernoulli_1pct", torch.from_numpy(f1).cuda(), torch.from_numpy(m1).cuda(),
+               ("prec", "bernoulli"))]
+    for name, fd, md, job in frames:
+        od = torch.empty_like(fd)
+        row = {}
+        for o in (4, 6):
+            for tau in (0.002, 0.005, 0.01):
+                for cap in (8, 16):
+                    opts = binding.make_opts(overlap=o, tau=tau, max_local_iters=cap)
+                    sec = _timed(torch, lambda: binding.inpaint_solve_ex(fd, md, args.tol, out=od,
+                                                                         opts=opts), 8)
+                    _, st, stats = binding.inpaint_solve_ex(
+                        fd, md, args.tol, out=od,
+                        opts=binding.make_opts(overlap=o, tau=tau, max_local_iters=cap, profile=1))
+                    key = f"o{o}_tau{tau:g}_cap{cap}"
+                    row[key] = {"fps": round(1.0 / sec, 2), "ms": round(1e3 * sec, 3), "status": st,
+                                "cycles": stats["cycles"],
+                                "finest_pixel_iters": stats["finest_cg_pixel_iters"]}
+                    host = od.cpu().numpy()
+                    for ch in range(host.shape[0]):
+                        pending[f"tuning/{name}/{key}/ch{ch}"] = ((*job, ch), host[ch])
+        out[name] = row
+    return out
+
+
 QUALITY_DENSITIES = (0.005, 0.01, 0.02, 0.05, 0.10)
 LEAK_DENSITY = 0.02
 FORM_LEGS = ("precision", "solvers", "sweeps", "batched", "serving")
+EXTRA_LEGS = ("tuning",)   # run only when --forms names them
 
 
 def sweep_leg(binding, torch, synth, args, fd4, pending):

@@ -91,7 +91,9 @@ typedef enum inpaint_rhs_restriction {
  */
 typedef struct inpaint_opts {
   int struct_size;     /* sizeof(inpaint_opts) */
-  int block;           /* ORAS block side B: 16 or 32 (default 32, Section 3.1) */
+  int block;           /* ORAS block side B: 16, 32 or 64 (default 32, Section 3.1); with 64
+                          a block is solved by four wavefronts and the coarsest grid is at
+                          most 32 x 32 (one level more than the rule "at most B") */
   int overlap;         /* overlap o in pixels between neighbouring blocks: even (twice the
                           per-side halo), 2 <= o <= B/2 (default 6) */
   float gamma;         /* Robin term added per cut block edge, 0 < gamma <= 1 (gamma = 1 is
@@ -281,7 +283,7 @@ int inpaint_solve_batched(const inpaint_problem* problems, int n, double tol,
                           const inpaint_opts* opts, void* stream, inpaint_stats* stats);
 
 /*
- * Autotuner of the batched solve: picks the ORAS block side (16, 32), overlap
+ * Autotuner of the batched solve: picks the ORAS block side (16, 32, 64), overlap
  * (2, 4, 6, 8, at most half the block), Robin weight gamma (0.3, 0.5, 0.7),
  * local CG tolerance tau (0.002, 0.005, 0.01) and cycle schedule (RFMG, FMG)
  * for these problems by timing batched solves of them: one coordinate-descent

@@ -188,7 +188,7 @@ int autotune_impl(const inpaint_problem* probs, int n, double tol, const inpaint
     }
   };
   const int schedules[] = {INPAINT_SCHED_RFMG, INPAINT_SCHED_FMG};
-  const int blocks[] = {16, 32};
+  const int blocks[] = {16, 32, 64};
   const int overlaps[] = {2, 4, 6, 8};
   const float gammas[] = {0.3f, 0.5f, 0.7f};
   const float taus[] = {0.002f, 0.005f, 0.01f};

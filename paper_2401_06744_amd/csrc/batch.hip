@@ -41,6 +41,7 @@ __global__ void __launch_bounds__(64) k_reset_b(const ResetArgs* __restrict__ ar
   const int t = threadIdx.x;
   if (t < a.C) a.active[t] = 1;
   if (t < 4) a.status[t] = 0;
+  if (t < kKnownWords) a.status[kKnownAt + t] = 0;
   if (t < 4) a.checks[t] = 0;
   for (int i = t; i < 3 * a.C * kMaxLevels; i += blockDim.x) a.cgstat[i] = 0;
 }
@@ -747,7 +748,7 @@ void fill_stats(const Member* m, inpaint_stats& st) {
 
 // Reads the flag block written by the prepare plan: input checks of f and the mask.
 void check_prepared(const int* flags_host, Member* m) {
-  const int st = flags_host[kFlagInts * m->slot + 12];
+  const int st = input_checks(flags_host + kFlagInts * m->slot + 12);
   if (st & 1) {
     m->status = INPAINT_E_INVALID;
     m->msg = "f is not finite at a known pixel";
@@ -892,7 +893,7 @@ int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const in
     own.emplace_back(new Member());
     Member& m = *own.back();
     m.idx = m.slot = i;
-    acquire(m.lease, probs[i].W, probs[i].H, probs[i].channels, o.B, o.o, o.B, o.prec);
+    acquire(m.lease, probs[i].W, probs[i].H, probs[i].channels, o.B, o.o, coarsest_side(o.B), o.prec);
     init_member(m, probs[i], m.lease.ws, o, tol, s);
     all.push_back(own.back().get());
   }

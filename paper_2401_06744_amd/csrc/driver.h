@@ -34,6 +34,11 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 inline int num_blocks_axis(int n, int B, int o) { return n <= B ? 1 : (n - o + (B - o) - 1) / (B - o); }
 
+// Side of the coarsest grid of a hierarchy with ORAS block side B: the level
+// rule halves until both sides are at most B (Section 4.4), except that a
+// coarsest grid is at most 32 x 32, which one wavefront solves.
+inline int coarsest_side(int B) { return B < 32 ? B : 32; }
+
 // ---------------------------------------------------------------------------
 // options
 // ---------------------------------------------------------------------------

@@ -22,8 +22,20 @@ constexpr unsigned long long kUnsetPartialBits = 0xFFF7C0FFEE5E7A11ull;
 inline double unset_partial() { return __builtin_bit_cast(double, kUnsetPartialBits); }
 
 // Ints per flag block of a problem: relres[4] doubles, active[4], status[4],
-// checks[4] ints, spare.  One block is copied to the host per poll.
+// checks[4] ints, then kKnownWords "a known pixel was seen" words (status[8]
+// .. status[8 + kKnownWords - 1]; the staging writes 2 into the word of its XCD
+// with a plain store, so that no word is shared by all of a launch's
+// workgroups), spare.  One block is copied to the host per poll.
 constexpr int kFlagInts = 32;
+constexpr int kKnownWords = 8;
+constexpr int kKnownAt = 8;  // offset of the known words from status[0]
+// Input checks of a flag block (its status[0] .. status[kKnownAt + kKnownWords - 1]):
+// bit 1 a known pixel with non-finite f, bit 2 some known pixel exists.
+inline int input_checks(const int* status) {
+  int st = status[0] & 1;
+  for (int i = 0; i < kKnownWords; ++i) st |= status[kKnownAt + i] & 2;
+  return st | (status[0] & 2);
+}
 // Most norm partials a block solve adds up itself (deferred norms).
 constexpr int kDeferParts = 256;
 

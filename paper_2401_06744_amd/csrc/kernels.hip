@@ -557,14 +557,16 @@ __device__ __forceinline__ void stage_body(const StageArgs& a, unsigned lin) {
     t[ty][side == 0 ? 0 : TW - 1] = k ? hf : 0.0f;
     kn[ty][side == 0 ? 0 : TW - 1] = k;
   }
-  // Report through one word shared by the whole grid: skip the atomic when the
-  // bit is already set, so that it is issued a handful of times, not per wave.
+  // Report: a non-finite known value (rare) by an atomic OR into status[0];
+  // "a known pixel exists" (nearly every tile) by a plain store of 2 into the
+  // known word of this workgroup's XCD, which only that XCD's workgroups write
+  // (the same value: no read-modify-write, nothing to wait for, and no
+  // address that every workgroup of the launch contends for).
   const unsigned long long anybad = __ballot(bad);
   const unsigned long long anyknown = __ballot(any);
-  if ((threadIdx.x & 63) == 0 && (anybad || anyknown)) {
-    const int want = (anybad ? 1 : 0) | (anyknown ? 2 : 0);
-    const int have = __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((have & want) != want) atomicOr(status, want);
+  if ((threadIdx.x & 63) == 0) {
+    if (anybad) atomicOr(status, 1);
+    if (anyknown) status[kKnownAt + (blockIdx.x & (kKnownWords - 1))] = 2;
   }
   __syncthreads();
   const int tx = cc, tyg = g;  // phase 2: 8 rows of column gx per thread
@@ -1281,7 +1283,7 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs& a, unsigned li
 // local CG on one block held in the registers of one wavefront
 // ---------------------------------------------------------------------------
 //
-// Lane layout for block side B (B in {16, 32}): lane = lx + B * g, where lx is
+// Lane layout for block side B (B in {16, 32}; 64 is BlockCG64): lane = lx + B * g, where lx is
 // the column inside the block and g one of G = 64 / B row groups; each lane
 // holds the R = B / G rows g*R .. g*R + R - 1 of its column.  Horizontal
 // neighbours come from lanes +-1 through DPP wave shifts; vertical neighbours
@@ -1631,6 +1633,116 @@ struct BlockCGh2 {
   }
 };
 
+// The local CG for B = 64: four wavefronts per block.  Wave w holds rows
+// 16w .. 16w + 15, lane = column, so horizontal neighbours are wave-wide DPP
+// shifts (0 past the block's left and right edges) and vertical ones are the
+// lane's own registers except across waves: each iteration every wave puts
+// the first and last rows of the search direction in LDS for its neighbours.
+// Dot products are wave sums added over the four waves in LDS (fixed order).
+// Arithmetic per pixel is that of BlockCG; three workgroup barriers per
+// iteration.
+struct BlockCG64 {
+  static constexpr int B = 64, NW = 4, R = B / NW;
+  struct Shared {
+    float edge[2][NW][2][B];  // [buffer][wave][first, last row][column]
+    float dot[2][NW];         // [p.q, r.r][wave]
+  };
+  Shared* sh;
+  int lane, w;
+  float hasL, hasR;
+  float dg[R];
+  bool nm[R];
+
+  __device__ void apply(const float (&x)[R], float (&q)[R], int buf) const {
+    sh->edge[buf][w][0][lane] = x[0];
+    sh->edge[buf][w][1][lane] = x[R - 1];
+    __syncthreads();
+    const float fa = w > 0 ? sh->edge[buf][w - 1][1][lane] : 0.0f;
+    const float fb = w < NW - 1 ? sh->edge[buf][w + 1][0][lane] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const float l = lane_from_left(x[k]) * hasL;
+      const float r = lane_from_right(x[k]) * hasR;
+      const float up = k > 0 ? x[k - 1] : fa;
+      const float dn = k < R - 1 ? x[k + 1] : fb;
+      q[k] = nm[k] ? dg[k] * x[k] - ((l + r) + (up + dn)) : 0.0f;
+    }
+  }
+
+  // the block-wide sum of a per-lane value (uniform result, same order everywhere)
+  __device__ float block_sum(float v, int slot) const {
+    v = wave_sum(v);
+    if (lane == 0) sh->dot[slot][w] = v;
+    __syncthreads();
+    const float t = (sh->dot[slot][0] + sh->dot[slot][1]) + (sh->dot[slot][2] + sh->dot[slot][3]);
+    return t;
+  }
+
+  __device__ void setup(Shared* s, int x0, int y0, int bw, int bh, int W, int H, float gamma,
+                        const uint8_t* __restrict__ c, int P) {
+    sh = s;
+    lane = threadIdx.x & 63;
+    w = threadIdx.x >> 6;
+    hasL = lane > 0 ? 1.0f : 0.0f;
+    hasR = lane < B - 1 ? 1.0f : 0.0f;
+    const bool colok = lane < bw;
+    const float dl = lane > 0 ? 1.0f : (x0 > 0 ? gamma : 0.0f);
+    const float dr = lane < bw - 1 ? 1.0f : (x0 + bw < W ? gamma : 0.0f);
+    const int cx = x0 + min(lane, bw - 1);
+    uint8_t cm[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) cm[k] = glb(c)[(size_t)(y0 + min(w * R + k, bh - 1)) * P + cx];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      const int ly = w * R + k;
+      const bool unknown = (colok & (ly < bh)) & (cm[k] == 0);
+      const float du = ly > 0 ? 1.0f : (y0 > 0 ? gamma : 0.0f);
+      const float dd = ly < bh - 1 ? 1.0f : (y0 + bh < H ? gamma : 0.0f);
+      nm[k] = unknown;
+      dg[k] = unknown ? (dl + dr) + (du + dd) : 0.0f;
+    }
+  }
+
+  // Plain CG from v = 0 on A_i v = rho; stops when ||rho||^2 <= thr or after
+  // maxit iterations (every wave takes the same decisions: the sums are uniform).
+  __device__ int solve(float (&rho)[R], float (&v)[R], float thr, int maxit) const {
+    float p[R], q[R];
+    float rr = 0.0f;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      rho[k] = nm[k] ? rho[k] : 0.0f;
+      v[k] = 0.0f;
+      p[k] = rho[k];
+      rr += rho[k] * rho[k];
+    }
+    rr = block_sum(rr, 1);
+    int it = 0;
+    while (it < maxit && rr > thr && rr >= kTiny) {
+      apply(p, q, it & 1);
+      float pq = 0.0f;
+#pragma unroll
+      for (int k = 0; k < R; ++k) pq += p[k] * q[k];
+      pq = block_sum(pq, 0);
+      if (!(pq >= kTiny)) break;
+      const float alpha = rr * __builtin_amdgcn_rcpf(pq);
+      float rn = 0.0f;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        v[k] += alpha * p[k];
+        rho[k] -= alpha * q[k];
+        rn += rho[k] * rho[k];
+      }
+      rn = block_sum(rn, 1);
+      const float beta = rn * __builtin_amdgcn_rcpf(rr);
+      rr = rn;
+#pragma unroll
+      for (int k = 0; k < R; ++k) p[k] = rho[k] + beta * p[k];
+      ++it;
+    }
+    return it;
+  }
+};
+
 __device__ __forceinline__ float pou_weight(int l, int nb, int k, int B, int o, float inv_o1) {
   // 1-D partition of unity (Section 3.1): 0 at the outermost overlap pixel,
   // 1 at the innermost, linear in between; 1 away from overlaps.
@@ -1796,12 +1908,55 @@ __device__ __forceinline__ void block_body_h(const BlockArgs& a, int ch, unsigne
   count_iterations(a, (size_t)ch * nblk + bi, it);
 }
 
+// Local problems of side 64: BlockCG64, four wavefronts per block (any
+// residual and correction type, arithmetic in float32).
+template <class TR, class TC>
+__device__ __forceinline__ void block_body_64(const BlockArgs& a, int ch, unsigned bi, unsigned nblk,
+                                              bool act) {
+  constexpr int B = 64, R = BlockCG64::R;
+  __shared__ BlockCG64::Shared sh;
+  const LevelView& lv = a.lv;
+  const int S = B - lv.o;
+  const int bx = bi % lv.nbx, by = bi / lv.nbx;
+  const int x0 = bx * S, y0 = by * S;
+  const int bw = min(B, lv.W - x0), bh = min(B, lv.H - y0);
+  BlockCG64 cg;
+  cg.setup(&sh, x0, y0, bw, bh, lv.W, lv.H, a.gamma, a.c, lv.P);
+  float rho[R], v[R];
+  const Fld<TR> r(a.r, (size_t)ch * lv.plane, a.s_r, a.rho, ch);
+  const bool colok = cg.lane < bw;
+  {
+    const int cx = x0 + min(cg.lane, bw - 1);
+#pragma unroll
+    for (int k = 0; k < R; ++k) rho[k] = r.ld((y0 + min(cg.w * R + k, bh - 1)) * lv.P + cx);
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+      if (!(colok && cg.w * R + k < bh)) rho[k] = 0.0f;
+  }
+  const float thr = block_threshold(a, ch, bw, bh);
+  const int it = cg.solve(rho, v, thr, act ? a.maxit : 0);
+  if (!act) return;
+  const Fld<TC> out(a.contrib, (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B,
+                    a.s_contrib, a.rho, ch);
+  const float wx = pou_weight(cg.lane, lv.nbx, bx, B, lv.o, a.inv_o1);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int ly = cg.w * R + k;
+    if (colok && ly < bh) out.st(ly * B + cg.lane, wx * pou_weight(ly, lv.nby, by, B, lv.o, a.inv_o1) * v[k]);
+  }
+  if (cg.w == 0) count_iterations(a, (size_t)ch * nblk + bi, it);
+}
+
 template <int B, class TR, class TC>
 __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
   const unsigned nblk = (unsigned)a.lv.nbx * (unsigned)a.lv.nby;
   const int ch = lin / nblk;
   const unsigned bi = lin - (unsigned)ch * nblk;
   const bool act = channel_active(a.active, ch);  // tested after the loads
+  if constexpr (B == 64) {
+    block_body_64<TR, TC>(a, ch, bi, nblk, act);
+    return;
+  }
   if constexpr (B == 32) {
     // a correction stored in 16 bits is solved for in packed float16 (with
     // float32 accumulation), whatever the residual's type
@@ -1987,6 +2142,17 @@ __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(bloc
 k_block_solve(BlockArgs a) {
   block_body<B, TR, TC>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
+// side 64: one block per workgroup of four wavefronts
+template <class TR, class TC>
+__global__ void __launch_bounds__(4 * kWave) k_block_solve64(BlockArgs a) {
+  block_body<64, TR, TC>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+template <class TR, class TC>
+__global__ void __launch_bounds__(4 * kWave) k_block_b64(const BlockArgs* __restrict__ args,
+                                                        const unsigned* __restrict__ start, int n) {
+  INPAINT_BATCH_LOOKUP(BlockArgs)
+  block_body<64, TR, TC>(a, lin);
+}
 template <int B, class TR, class TC>
 __global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(block_waves<TR>(), 8)))
 k_block_b(const BlockArgs* __restrict__ args,
@@ -2122,6 +2288,8 @@ hipError_t launch_block_solve(const BlockArgs& a, int C, hipStream_t s) {
     using TC = typename decltype(tc)::type;
     if (a.lv.B == 32)
       hipLaunchKernelGGL((k_block_solve<32, TR, TC>), grid, dim3(kWave), 0, s, a);
+    else if (a.lv.B == 64)
+      hipLaunchKernelGGL((k_block_solve64<TR, TC>), grid, dim3(4 * kWave), 0, s, a);
     else if (a.lv.B == 16)
       hipLaunchKernelGGL((k_block_solve<16, TR, TC>), grid, dim3(kWave), 0, s, a);
     else
@@ -2131,12 +2299,14 @@ hipError_t launch_block_solve(const BlockArgs& a, int C, hipStream_t s) {
 }
 
 hipError_t launch_coarse_solve(const CoarseArgs& a, int C, hipStream_t s) {
-  if (a.lv.W > a.lv.B || a.lv.H > a.lv.B) return hipErrorInvalidValue;
+  // the coarsest grid of a side-64 hierarchy is at most 32 x 32 (one wavefront)
+  const int cb = a.lv.B == 64 ? 32 : a.lv.B;
+  if (a.lv.W > cb || a.lv.H > cb) return hipErrorInvalidValue;
   return with_types(a.prec, a.level0, [&](auto tu, auto) {
     using T = typename decltype(tu)::type;
-    if (a.lv.B == 32)
+    if (cb == 32)
       hipLaunchKernelGGL((k_coarse_solve<32, T>), dim3(C), dim3(kWave), 0, s, a);
-    else if (a.lv.B == 16)
+    else if (cb == 16)
       hipLaunchKernelGGL((k_coarse_solve<16, T>), dim3(C), dim3(kWave), 0, s, a);
     else
       return hipErrorInvalidValue;
@@ -2226,6 +2396,8 @@ hipError_t launch_block_b(const BlockArgs* args, const unsigned* start, int n, u
     using TC = typename decltype(tc)::type;
     if (B == 32)
       hipLaunchKernelGGL((k_block_b<32, TR, TC>), dim3(total), dim3(kWave), 0, s, args, start, n);
+    else if (B == 64)
+      hipLaunchKernelGGL((k_block_b64<TR, TC>), dim3(total), dim3(4 * kWave), 0, s, args, start, n);
     else if (B == 16)
       hipLaunchKernelGGL((k_block_b<16, TR, TC>), dim3(total), dim3(kWave), 0, s, args, start, n);
     else
@@ -2237,6 +2409,7 @@ hipError_t launch_block_b(const BlockArgs* args, const unsigned* start, int n, u
 hipError_t launch_coarse_b(const CoarseArgs* args, const unsigned* start, int n, unsigned total,
                            int prec, int level0, int B, hipStream_t s) {
   if (total == 0) return hipSuccess;
+  if (B == 64) B = 32;  // the coarsest grid of a side-64 hierarchy is at most 32 x 32
   return with_types(prec, level0, [&](auto tu, auto) {
     using T = typename decltype(tu)::type;
     if (B == 32)

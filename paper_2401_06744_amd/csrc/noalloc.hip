@@ -94,7 +94,7 @@ int solve_noalloc_impl(const float* f, const uint8_t* mask, int W, int H, int C,
   std::lock_guard<std::mutex> lock(ds.mu);
 
   // the hierarchy at the start of the array (rejected here if it is too large)
-  const Key k{dev, W, H, C, o.B, o.o, o.B, o.prec};
+  const Key k{dev, W, H, C, o.B, o.o, coarsest_side(o.B), o.prec};
   std::unique_ptr<Workspace> ws = bind_workspace(k, ds.ptr, kScratchBytes - kOutputReserve, s);
   Member m;
   m.W = W;

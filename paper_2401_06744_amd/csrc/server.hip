@@ -176,7 +176,7 @@ class GpuExecutor : public Executor {
 
  private:
   Key key(const inpaint_problem& p) const {
-    return Key{dev_, p.W, p.H, p.channels, o_.B, o_.o, o_.B, o_.prec};
+    return Key{dev_, p.W, p.H, p.channels, o_.B, o_.o, coarsest_side(o_.B), o_.prec};
   }
 
   void read_flags() {

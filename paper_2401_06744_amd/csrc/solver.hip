@@ -34,7 +34,7 @@ Opts resolve(const inpaint_opts* p) {
   }
   if (o.prec != PREC_F32 && o.prec != PREC_F16 && o.prec != PREC_BF16)
     fail(INPAINT_E_INVALID, "unknown precision");
-  if (o.B != 16 && o.B != 32) fail(INPAINT_E_INVALID, "block must be 16 or 32");
+  if (o.B != 16 && o.B != 32 && o.B != 64) fail(INPAINT_E_INVALID, "block must be 16, 32 or 64");
   if (o.o < 2 || 2 * o.o > o.B) fail(INPAINT_E_INVALID, "overlap must satisfy 2 <= overlap <= block/2");
   // the overlap is twice the per-side halo of a block; with an even overlap
   // (and block) every block starts at an even column, which the grid passes'
@@ -345,6 +345,7 @@ __global__ void k_reset(int* active, int* status, unsigned long long* cgstat, in
   const int t = threadIdx.x;
   if (t < C) active[t] = 1;
   if (t < 4) status[t] = 0;
+  if (t < kKnownWords) status[kKnownAt + t] = 0;
   for (int i = t; i < 3 * C * kMaxLevels; i += blockDim.x) cgstat[i] = 0;
 }
 
@@ -388,10 +389,11 @@ void prepare(Run& R, const float* f_d, const uint8_t* m_d, bool hierarchy, bool 
     }
   }
   int* h = (int*)ws->host;
-  HIPCHK(hipMemcpyAsync(h, ws->status, sizeof(int), hipMemcpyDeviceToHost, R.s));
+  HIPCHK(hipMemcpyAsync(h, ws->status, (kKnownAt + kKnownWords) * sizeof(int), hipMemcpyDeviceToHost, R.s));
   HIPCHK(hipStreamSynchronize(R.s));
-  if (h[0] & 1) fail(INPAINT_E_INVALID, "f is not finite at a known pixel");
-  if (!(h[0] & 2)) fail(INPAINT_E_EMPTY_MASK, "mask has no known pixel: the system is singular");
+  const int st = input_checks(h);
+  if (st & 1) fail(INPAINT_E_INVALID, "f is not finite at a known pixel");
+  if (!(st & 2)) fail(INPAINT_E_EMPTY_MASK, "mask has no known pixel: the system is singular");
 }
 
 void check_dims(const void* a, const void* b, int W, int H, int C) {
@@ -432,7 +434,7 @@ int solve_impl(const float* f, const uint8_t* mask, int W, int H, int C, double 
   if (overlap(out, nf, mask, (size_t)W * H)) fail(INPAINT_E_INVALID, "out overlaps mask");
   hipStream_t s = (hipStream_t)stream;
   Member m;
-  acquire(m.lease, W, H, C, o.B, o.o, o.B, o.prec);
+  acquire(m.lease, W, H, C, o.B, o.o, coarsest_side(o.B), o.prec);
   const inpaint_problem p{f, mask, W, H, C, out};
   init_member(m, p, m.lease.ws, o, tol, s);
   Workspace* ws = m.ws;

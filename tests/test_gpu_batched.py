@@ -41,7 +41,7 @@ def _solo(probs, **kw):
 @pytest.mark.parametrize("kw", [
     {}, {"schedule": binding.SCHED_FMG}, {"schedule": binding.SCHED_MULTILEVEL},
     {"schedule": binding.SCHED_SINGLE}, {"pre_smooth": 2, "post_smooth": -1},
-    {"pre_smooth": -1, "post_smooth": 2}, {"block": 16, "overlap": 4},
+    {"pre_smooth": -1, "post_smooth": 2}, {"block": 16, "overlap": 4}, {"block": 64, "overlap": 8},
     {"precision": binding.PREC_FP16}, {"precision": binding.PREC_BF16}, {"schedule": binding.SCHED_CG},
     {"schedule": binding.SCHED_CG_MULTILEVEL}, {"schedule": binding.SCHED_CG_MULTIGRID},
 ])
@@ -194,7 +194,7 @@ def test_autotune_picks_a_converging_configuration_and_caches_it(tmp_path, monke
     t0 = time.perf_counter()
     best, ms = binding.inpaint_autotune(probs, TOL)
     first = time.perf_counter() - t0
-    assert best.block in (16, 32) and 2 <= best.overlap <= best.block // 2
+    assert best.block in (16, 32, 64) and 2 <= best.overlap <= best.block // 2
     assert best.schedule in (binding.SCHED_RFMG, binding.SCHED_FMG)
     assert ms > 0
     t0 = time.perf_counter()

@@ -213,7 +213,7 @@ def test_errors():
     with pytest.raises(binding.InpaintError) as e:
         _solve(g, m)
     assert e.value.code == binding.E_INVALID
-    for bad in ({"block": 24}, {"overlap": 1}, {"overlap": 3}, {"overlap": 17}, {"gamma": 1.5}, {"schedule": 9}):
+    for bad in ({"block": 24}, {"block": 128}, {"overlap": 1}, {"overlap": 3}, {"overlap": 17}, {"gamma": 1.5}, {"schedule": 9}):
         with pytest.raises(binding.InpaintError) as e:
             _solve(f, m, **bad)
         assert e.value.code == binding.E_INVALID
@@ -305,6 +305,8 @@ def test_repeatable_and_device_pointers_and_alias():
 @pytest.mark.parametrize("kw", [
     {"schedule": binding.SCHED_FMG}, {"schedule": binding.SCHED_MULTILEVEL},
     {"block": 16, "overlap": 4}, {"overlap": 2}, {"overlap": 16, "block": 32},
+    {"block": 64, "overlap": 8}, {"block": 64, "overlap": 32}, {"block": 64, "overlap": 6,
+                                                                 "precision": binding.PREC_FP16},
     {"gamma": 1.0}, {"rhs_restriction": binding.RHS_NAIVE}, {"pre_smooth": 2, "post_smooth": 2},
     {"post_smooth": -1, "pre_smooth": 2}, {"pre_smooth": -1, "post_smooth": 2},
 ])

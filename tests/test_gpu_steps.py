@@ -66,7 +66,7 @@ def test_prolong_matches_oracle(Wf, Hf, seed):
 
 @pytest.mark.parametrize("W,H,B,o,gamma", [
     (100, 70, 32, 6, 0.5), (64, 64, 16, 4, 1.0), (45, 90, 32, 2, 0.3), (31, 29, 32, 6, 0.5),
-    (150, 33, 16, 8, 0.7),
+    (150, 33, 16, 8, 0.7), (150, 100, 64, 8, 0.5), (61, 130, 64, 6, 0.3),
 ])
 def test_oras_step_matches_oracle(W, H, B, o, gamma):
     """With the local CG run to convergence, one GPU ORAS iteration equals the
