@@ -230,23 +230,18 @@ __device__ __forceinline__ void output_body(const OutputArgs& a, unsigned lin) {
 // coarse problems (Section 4.3)
 // ---------------------------------------------------------------------------
 
-// Coarse mask of cell (X, Y): max pool over its existing children (a child
-// past the image edge repeats the existing one).
-__device__ __forceinline__ uint8_t pooled_mask(const gptr<const uint8_t> cf, const LevelView& fl, int X,
-                                               int Y) {
-  const int x0 = 2 * X, y0 = 2 * Y, x1 = min(x0 + 1, fl.W - 1), y1 = min(y0 + 1, fl.H - 1);
-  const uint8_t m = (cf[(size_t)y0 * fl.P + x0] | cf[(size_t)y0 * fl.P + x1]) |
-                    (cf[(size_t)y1 * fl.P + x0] | cf[(size_t)y1 * fl.P + x1]);
-  return m ? 1 : 0;
-}
-
-// One level of the coarse problems for cell (X, Y): its coarse mask (max pool,
-// Section 4.3) and its known value.  Modified form: a known child j is
-// weighted by its number of direct neighbours that are not known, judging a
-// neighbour in the same cell by the fine mask and one in an adjacent cell by
-// that cell's coarse mask (pooled here from the fine mask, so that both
-// pyramids take one launch per level); neighbours outside the image are not
-// counted.  If every weight is 0 the plain mean of the known children is used.
+// One level of the coarse problems (Section 4.3) for a tile of 64 x 4 coarse
+// cells: the coarse mask (max pool over the existing children; a child past
+// the image edge repeats the existing one) and the coarse known value.
+// Modified form: a known child j is weighted by its number of direct
+// neighbours that are not known, judging a neighbour in the same cell by the
+// fine mask and one in an adjacent cell by that cell's coarse mask (pooled
+// here from the fine mask, so that both pyramids take one launch per level);
+// neighbours outside the image are not counted.  If every weight is 0 the
+// plain mean of the known children is used.  The fine mask of the tile's
+// cells and their neighbours is staged in LDS, then the coarse masks of the
+// tile's cells plus a one-cell ring; every cell is then worked out from LDS.
+constexpr int kRhsCW = 64, kRhsCH = 4;  // coarse cells per workgroup (x, y)
 template <class TF, class TC>
 __device__ __forceinline__ void rhs_body(const RhsArgs& a, unsigned lin) {
   const LevelView& fl = a.fl;
@@ -256,12 +251,36 @@ __device__ __forceinline__ void rhs_body(const RhsArgs& a, unsigned lin) {
   const TF* __restrict__ bf = (const TF*)a.bf;
   TC* __restrict__ bc = (TC*)a.bc;
   const int C = a.C, naive = a.naive;
-  const unsigned gxn = (unsigned)((cl.W + 63) / 64);
-  const int X = (int)(lin % gxn) * 64 + (threadIdx.x & 63);
-  const int Y = (int)(lin / gxn) * 4 + (threadIdx.x >> 6);
+  const unsigned gxn = (unsigned)((cl.W + kRhsCW - 1) / kRhsCW);
+  const int X0 = (int)(lin % gxn) * kRhsCW, Y0 = (int)(lin / gxn) * kRhsCH;
+  // fine mask over columns 2 X0 - 2 .. 2 X0 + 2 kRhsCW + 1 and rows
+  // 2 Y0 - 2 .. 2 Y0 + 2 kRhsCH + 1 (0 outside the image), and the coarse
+  // masks of cells X0 - 1 .. X0 + kRhsCW, Y0 - 1 .. Y0 + kRhsCH
+  constexpr int FW = 2 * kRhsCW + 4, FH = 2 * kRhsCH + 4, MW = kRhsCW + 2, MH = kRhsCH + 2;
+  __shared__ uint8_t fm[FH][FW];
+  __shared__ uint8_t pm[MH][MW];
+  const int fx0 = 2 * X0 - 2, fy0 = 2 * Y0 - 2;
+  for (int i = threadIdx.x; i < FH * FW; i += blockDim.x) {
+    const int y = fy0 + i / FW, x = fx0 + i % FW;
+    const bool in = y >= 0 && y < fl.H && x >= 0 && x < fl.W;
+    fm[i / FW][i % FW] = in && cf[(size_t)(in ? y : 0) * fl.P + (in ? x : 0)] != 0;
+  }
+  __syncthreads();
+  const auto fmask = [&](int y, int x) -> uint8_t { return fm[y - fy0][x - fx0]; };
+  for (int i = threadIdx.x; i < MH * MW; i += blockDim.x) {
+    const int cy = Y0 - 1 + i / MW, cx = X0 - 1 + i % MW;
+    uint8_t m = 0;
+    if (cx >= 0 && cy >= 0 && cx < cl.W && cy < cl.H) {
+      const int xa = 2 * cx, ya = 2 * cy, xb = min(xa + 1, fl.W - 1), yb = min(ya + 1, fl.H - 1);
+      m = ((fmask(ya, xa) | fmask(ya, xb)) | (fmask(yb, xa) | fmask(yb, xb))) ? 1 : 0;
+    }
+    pm[i / MW][i % MW] = m;
+  }
+  __syncthreads();
+  const int X = X0 + (int)(threadIdx.x % kRhsCW), Y = Y0 + (int)(threadIdx.x / kRhsCW);
   if (X >= cl.W || Y >= cl.H) return;
   const size_t oc = (size_t)Y * cl.P + X;
-  const uint8_t m = pooled_mask(cf, fl, X, Y);
+  const uint8_t m = pm[Y - Y0 + 1][X - X0 + 1];
   cc[oc] = m;
   if (!m) {
     for (int ch = 0; ch < C; ++ch) bc[(size_t)ch * cl.plane + oc] = (TC)0.0f;
@@ -274,8 +293,7 @@ __device__ __forceinline__ void rhs_body(const RhsArgs& a, unsigned lin) {
     for (int dx = 0; dx < 2; ++dx) {
       const int y = 2 * Y + dy, x = 2 * X + dx;
       if (y >= fl.H || x >= fl.W) continue;
-      const size_t of = (size_t)y * fl.P + x;
-      if (!cf[of]) continue;
+      if (!fmask(y, x)) continue;
       int w = 0;
       const int ny[4] = {y, y, y - 1, y + 1};
       const int nx[4] = {x - 1, x + 1, x, x};
@@ -284,11 +302,11 @@ __device__ __forceinline__ void rhs_body(const RhsArgs& a, unsigned lin) {
         const int yy = ny[d], xx = nx[d];
         if (yy < 0 || yy >= fl.H || xx < 0 || xx >= fl.W) continue;
         const bool same = (yy >> 1) == Y && (xx >> 1) == X;
-        const uint8_t k = same ? cf[(size_t)yy * fl.P + xx] : pooled_mask(cf, fl, xx >> 1, yy >> 1);
+        const uint8_t k = same ? fmask(yy, xx) : pm[(yy >> 1) - Y0 + 1][(xx >> 1) - X0 + 1];
         w += k ? 0 : 1;
       }
       wts[nk] = w;
-      offs[nk] = of;
+      offs[nk] = (size_t)y * fl.P + x;
       ++nk;
     }
   int wsum = 0;
@@ -973,8 +991,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
     } else {
 #pragma unroll
       for (int j = 0; j < RJ; ++j) {
-        // rows past the halo repeat a valid row (their value is not stored)
-        const int ty = min(g + NG * j, TH - 1);
+        // the last row slot holds only the two bottom halo rows: the
+        // wavefronts of the other row groups skip it
+        if (j == RJ - 1 && g + NG * j >= TH) continue;
+        const int ty = g + NG * j;
         v[j] = F.value2(col, min(max(y0 - 1 + ty, 0), H - 1));
       }
       if (!act) return;  // the whole workgroup: one channel
