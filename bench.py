@@ -818,6 +818,20 @@ def batched_leg(binding, torch, synth, args):
     rr = max(float(binding.inpaint_rel_res(o, f, m).max()) for f, m, o in items)
     known = all(bool(torch.equal(o[:, m != 0], f[:, m != 0])) for f, m, o in items)
     n = len(items)
+    sizes = [f.numel() for f, _, _ in items]
+    # V-cycles per pixel-channel: the 1-10 % masks of the mix need more
+    # cycles than the headline frame's 4 % mask (a third for the sparser ones)
+    px_cycles = sum(z * s["cycles"] for z, s in zip(sizes, stats)) / px
+    # the same 64 shapes, channels and images with every mask at the headline
+    # frame's density: the batch's pixel rate at the headline's cycle count
+    same = synth.batched_problems(density=args.density)
+    dev_s = [(torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()) for f, m in same]
+    items_s = [(f, m, o) for (f, m), o in zip(dev_s, outs)]
+    t_same = _timed(torch, lambda: binding.inpaint_solve_batched(items_s, args.tol, opts=default), reps)
+    _, st_s, stats_s = binding.inpaint_solve_batched(items_s, args.tol, opts=default)
+    torch.cuda.synchronize()
+    rr_s = max(float(binding.inpaint_rel_res(o, f, m).max()) for f, m, o in items_s)
+    del dev_s, items_s
     return {
         "workload": f"{n} problems (seed 40): W uniform 128..1920, H 128..1080, 1 or 3 channels, "
                     f"Bernoulli 1-10 %, rel-res {args.tol:g}, float32",
@@ -837,6 +851,12 @@ def batched_leg(binding, torch, synth, args):
                              "batched_autotuned": round(px / (3840 * 2160 * 3) / t_tuned, 1)},
         "status": st, "rel_res_max": rr, "known_exact": known,
         "cycles": sorted({s["cycles"] for s in stats}),
+        "cycles_per_pixel": round(px_cycles, 3),
+        f"same_shapes_{args.density:.0%}_masks": {
+            "ms": round(1e3 * t_same, 3), "opts": "default",
+            "equiv_4k_rgb_fps": round(px / (3840 * 2160 * 3) / t_same, 1),
+            "cycles_per_pixel": round(sum(z * s["cycles"] for z, s in zip(sizes, stats_s)) / px, 3),
+            "status": st_s, "rel_res_max": rr_s},
         "batched_equals_solo": "bitwise (tests/test_gpu_batched.py)",
     }
 

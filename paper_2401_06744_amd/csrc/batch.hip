@@ -867,6 +867,37 @@ void build_output(Plan& P, const std::vector<Member*>& ms) {
   P.end();
 }
 
+// The output issued right after the V-cycles the last solve in context c
+// needed, before their convergence tests are read back: each channel's final
+// buffer is chosen on the device from its test count (nplan plans issued: the
+// cascade and the cycles), and a channel that has not stopped is left to the
+// host-selected output that follows more cycles.
+static void build_output_selected(Plan& P, const std::vector<Member*>& ms, const BatchCtx& c,
+                                  int nplan) {
+  P.begin(S_OUTPUT, 0, 0);
+  for (size_t i = 0; i < ms.size(); ++i) {
+    const Member* m = ms[i];
+    const Level& L0 = m->ws->lv[0];
+    OutputArgs a{};
+    a.lv = L0.v;
+    a.c = L0.c;
+    a.b = L0.b;
+    a.u[0] = L0.u[0];
+    a.u[1] = L0.u[1];
+    a.out = m->o_d;
+    a.Pout = m->W;
+    a.C = m->C;
+    a.flags = (const int*)m->ws->relres;
+    a.nplan = nplan;
+    a.ncycle = c.ncycle;
+    a.cur[0] = c.cascade.cur0[i];
+    a.cur[1] = c.cycle[0].cur0[i];
+    a.cur[2] = c.cycle[c.ncycle > 1 ? 1 : 0].cur0[i];
+    P.add(a, work_output(a));
+  }
+  P.end();
+}
+
 int solve_batched_impl(const inpaint_problem* probs, int n, double tol, const inpaint_opts* opts,
                        void* stream, inpaint_stats* stats) {
   if (!probs) fail(INPAINT_E_INVALID, "NULL problem array");
@@ -932,16 +963,26 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
   int* const gather_to = n == 1 ? nullptr : c.flags_dev;
   const void* const flags_src = n == 1 ? (const void*)all[0]->ws->relres : (const void*)c.flags_dev;
   build(prep, all, [&] { build_prepare(prep, all, o, gather_to); });
-  upload({&prep}, &c.call_dev, &c.call_cap, s);
-  HIPCHK(issue(prep, prec, B, s, prof));
   // With plans cached for every member and the cycle count of the last solve
   // in this context, the solve runs ahead: the input checks and the first
   // convergence tests are read back once, after that many V-cycles (a channel
-  // that converges earlier skips the remaining launches).
+  // that converges earlier skips the remaining launches) and the output
+  // (device-selected: when every channel has stopped by then, the results
+  // are in place when the tests are read).
   const std::string all_live(n, 1);
   const bool ahead = !prof && c.expect > 0 && c.live_key == all_live;
+  const int nahead = ahead ? std::min(c.expect, o.max_cycles) : 0;
+  Plan spec;
+  if (ahead) {
+    build_output_selected(spec, all, c, 1 + nahead);
+    upload({&prep, &spec}, &c.call_dev, &c.call_cap, s);
+  } else {
+    upload({&prep}, &c.call_dev, &c.call_cap, s);
+  }
+  HIPCHK(issue(prep, prec, B, s, prof));
   std::vector<Member*> live;
   std::string live_key;
+  bool written = false;
   if (ahead) {
     live = all;
     live_key = all_live;
@@ -986,10 +1027,14 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
     HIPCHK(issue(c.cascade, prec, B, s, prof));
     std::vector<const Plan*> seq{&c.cascade};
     int cycles = 0;
-    for (const int k = ahead ? std::min(c.expect, o.max_cycles) : 0; cycles < k; ++cycles) {
+    for (; cycles < nahead; ++cycles) {
       const Plan& P = c.cycle[cycles % c.ncycle];
       run_plan(P, prec, B, s);
       seq.push_back(&P);
+    }
+    if (ahead) {
+      HIPCHK(issue(spec, prec, B, s, prof));
+      HIPCHK(hipEventRecord(c.ev1, s));
     }
     HIPCHK(hipMemcpyAsync(c.flags_host, flags_src, (size_t)n * kFlagInts * sizeof(int),
                           hipMemcpyDeviceToHost, s));
@@ -1008,6 +1053,9 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
       }
     }
     bool done = apply_counted(c.flags_host, live, seq);
+    // every channel stopped within the cycles run ahead: the device-selected
+    // output has written every result
+    written = ahead && done;
     // Float32 CG can stall above tol (its updates round away against |u|): the
     // CG schedules give up, not converged, once the largest relative residual
     // still iterating has not improved by 1 % in kCgStallTests tests.
@@ -1043,12 +1091,14 @@ float run_batch(const std::vector<Member*>& all, const Opts& o, double tol, hipS
     for (Member* m : live) need = std::max(need, m->cycles);
     c.expect = done ? need : 0;
     for (size_t i = 0; i < live.size(); ++i) finish_member(live[i], seq.back()->cur0[i]);
-    Plan out;
-    build_output(out, live);
-    upload({&out}, &c.call_dev, &c.call_cap, s);
-    HIPCHK(issue(out, prec, B, s, prof));
+    if (!written) {
+      Plan out;
+      build_output(out, live);
+      upload({&out}, &c.call_dev, &c.call_cap, s);
+      HIPCHK(issue(out, prec, B, s, prof));
+    }
   }
-  HIPCHK(hipEventRecord(c.ev1, s));
+  if (!written) HIPCHK(hipEventRecord(c.ev1, s));
   for (Member* m : live)
     if (m->out_host)
       HIPCHK(hipMemcpyAsync(m->out, m->o_d, (size_t)m->W * m->H * m->C * sizeof(float),

@@ -241,6 +241,14 @@ struct CgArgs {
   NormOut norm;           // p.q (direction pass) or r.r (step pass)
 };
 
+// Output of one problem.  flags null: u[ch] is channel ch's final iterate.
+// flags set (the output issued before the host has read the convergence
+// tests): u[0], u[1] are the two level-0 iterate buffers and each channel's is
+// chosen on the device from the problem's flag block: a channel that stopped
+// after its k-th test (k = 1 the cascade, k > 1 cycle plan (k - 2) % ncycle)
+// ends in buffer cur[0] resp. cur[1 + (k - 2) % ncycle]; a channel still
+// iterating, a k outside 1..nplan, or a problem whose input checks failed is
+// not written.
 struct OutputArgs {
   LevelView lv;
   const uint8_t* c;
@@ -248,6 +256,9 @@ struct OutputArgs {
   const float* u[kMaxChannels];
   float* out;
   int Pout, C;
+  const int* flags;
+  int nplan, ncycle;
+  int cur[3];
 };
 
 // Work items (workgroups) of one problem in each kernel; a batched launch

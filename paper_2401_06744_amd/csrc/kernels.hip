@@ -54,9 +54,11 @@ __device__ __forceinline__ gptr<T> glb(T* p) {
   return (gptr<T>)p;
 }
 
-// Whether channel ch still iterates (no flags: always).  Read as early as
-// possible and tested late, so that the flag's round trip overlaps the
-// kernel's first loads instead of preceding them.
+// Whether channel ch still iterates (no flags: always).  Tested before the
+// kernel's first loads: a converged channel's workgroups then cost a flag read
+// and no field traffic (testing it late, to overlap the flag's round trip with
+// those loads, was not faster on a live channel and made a stopped one cost
+// about half a full pass).
 __device__ __forceinline__ bool channel_active(const int* active, int ch) {
   return !active || glb(active)[ch] != 0;
 }
@@ -209,7 +211,24 @@ __device__ __forceinline__ void output_body(const OutputArgs& a, unsigned lin) {
   if (x >= lv.W) return;
   // select without indexing the argument array dynamically (that would place
   // the arguments in scratch memory)
-  const gptr<const float> u = glb(ch == 0 ? a.u[0] : ch == 1 ? a.u[1] : ch == 2 ? a.u[2] : a.u[3]);
+  const float* up = ch == 0 ? a.u[0] : ch == 1 ? a.u[1] : ch == 2 ? a.u[2] : a.u[3];
+  if (a.flags) {
+    const gptr<const int> blk = glb(a.flags);
+    const int s0 = blk[12];
+    int known = 0;
+#pragma unroll
+    for (int i = 0; i < kKnownWords; ++i) known |= blk[12 + kKnownAt + i];
+    // a non-finite known value, no known pixel, or a lost norm partial: the
+    // host reports the problem and nothing is written
+    if ((s0 & 5) || !((s0 | known) & 2)) return;
+    const double rr = ((const gptr<const double>)blk)[ch];
+    if (blk[8 + ch] != 0 && isfinite(rr)) return;  // still iterating
+    const int k = blk[16 + ch];
+    if (k < 1 || k > a.nplan) return;
+    const int cb = k == 1 ? a.cur[0] : (k - 2) % a.ncycle == 0 ? a.cur[1] : a.cur[2];
+    up = cb == 0 ? a.u[0] : a.u[1];
+  }
+  const gptr<const float> u = glb(up);
   uint8_t k[kOutRows];
   float bv[kOutRows], uv[kOutRows];
 #pragma unroll
@@ -929,7 +948,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   const unsigned ntiles = tiles_x * (unsigned)((a.lv.H + kTileH - 1) / kTileH);
   const int ch = lin / ntiles;
   const unsigned tile = lin - (unsigned)ch * ntiles;
-  const bool act = channel_active(a.active, ch);  // tested after the first loads
+  if (!channel_active(a.active, ch)) return;  // the whole workgroup: one channel
   const LevelView& lv = a.lv;
   const int W = lv.W, H = lv.H;
   const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
@@ -971,7 +990,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
         const int ty = min(g + NG * j, TH - 1);
         pr[j] = F.pre2(col, min(max(y0 - 1 + ty, 0), H - 1));
       }
-      if (!act) return;  // the whole workgroup: one channel
       // coarse cells (x0/2 - 1 .. x0/2 + 32) x (y0/2 - 1 .. y0/2 + 16), clamped
       const int cx0 = max((x0 >> 1) - 1, 0), cy0 = max((y0 >> 1) - 1, 0);
       for (int i = threadIdx.x; i < kCoarseW * kCoarseH; i += kPassThreads) {
@@ -997,7 +1015,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
         const int ty = g + NG * j;
         v[j] = F.value2(col, min(max(y0 - 1 + ty, 0), H - 1));
       }
-      if (!act) return;  // the whole workgroup: one channel
     }
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
@@ -1153,7 +1170,7 @@ __device__ __forceinline__ void cg_dir_body(const CgArgs& a, unsigned lin) {
   const unsigned ntiles = tiles_x * (unsigned)((lv.H + kTileH - 1) / kTileH);
   const int ch = lin / ntiles;
   const unsigned tile = lin - (unsigned)ch * ntiles;
-  const bool act = channel_active(a.active, ch);
+  if (!channel_active(a.active, ch)) return;  // the whole workgroup: one channel
   const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
   __shared__ float t[TH][TW];
   const size_t po = (size_t)ch * lv.plane;
@@ -1184,7 +1201,6 @@ __device__ __forceinline__ void cg_dir_body(const CgArgs& a, unsigned lin) {
     hr = r[off];
     hp = pin[off];
   }
-  if (!act) return;  // the whole workgroup: one channel
 #pragma unroll
   for (int j = 0; j < RJ; ++j) {
     const int ty = g + NG * j;
@@ -1219,7 +1235,7 @@ __device__ __forceinline__ void cg_step_body(const CgArgs& a, unsigned lin) {
   const unsigned ntiles = tiles_x * (unsigned)((lv.H + kTileH - 1) / kTileH);
   const int ch = lin / ntiles;
   const unsigned tile = lin - (unsigned)ch * ntiles;
-  const bool act = channel_active(a.active, ch);
+  if (!channel_active(a.active, ch)) return;  // the whole workgroup: one channel
   const int x0 = (int)(tile % tiles_x) * kTileW, y0 = (int)(tile / tiles_x) * kTileH;
   const int c = threadIdx.x & (kTileW - 1), g = threadIdx.x / kTileW;
   const int gx = x0 + c, gxc = min(gx, lv.W - 1);
@@ -1237,7 +1253,6 @@ __device__ __forceinline__ void cg_step_body(const CgArgs& a, unsigned lin) {
     pv[k] = p[off];
     qv[k] = q[off];
   }
-  if (!act) return;
   double acc = 0.0;
 #pragma unroll
   for (int k = 0; k < RK; ++k) {
@@ -1803,8 +1818,7 @@ __device__ __forceinline__ void count_iterations(const BlockArgs& a, size_t ib, 
 
 // float32 local problems of side 32: BlockCG2 lane layout
 template <class TC>
-__device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsigned bi, unsigned nblk,
-                                               bool act) {
+__device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsigned bi, unsigned nblk) {
   constexpr int B = 32, R = BlockCG2::R;
   const LevelView& lv = a.lv;
   const int S = B - lv.o;
@@ -1826,8 +1840,7 @@ __device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsig
     }
   }
   const float thr = block_threshold(a, ch, bw, bh);
-  const int it = cg.solve(rho, v, thr, act ? a.maxit : 0);  // zeroes rho outside the block
-  if (!act) return;
+  const int it = cg.solve(rho, v, thr, a.maxit);  // zeroes rho outside the block
   const Fld<TC> out(a.contrib, (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B,
                     a.s_contrib, a.rho, ch);
   float wx[2];
@@ -1849,8 +1862,7 @@ __device__ __forceinline__ void block_body_f32(const BlockArgs& a, int ch, unsig
 
 // Local problems of side 32 with 16-bit corrections: BlockCGh2 in packed float16
 template <class TR, class TC>
-__device__ __forceinline__ void block_body_h(const BlockArgs& a, int ch, unsigned bi, unsigned nblk,
-                                             bool act) {
+__device__ __forceinline__ void block_body_h(const BlockArgs& a, int ch, unsigned bi, unsigned nblk) {
   constexpr int B = 32, R = BlockCGh2::R;
   const LevelView& lv = a.lv;
   const int S = B - lv.o;
@@ -1889,7 +1901,6 @@ __device__ __forceinline__ void block_body_h(const BlockArgs& a, int ch, unsigne
   float v[2][R];
   int it = 0;
   float un = 0.0f;  // ||r||; stays 0 (and v = 0) when the block needs no solve
-  if (!act) return;
   if (ss * rs2 > thr && a.maxit > 0) {
     const float sc = __builtin_amdgcn_rsqf(ss);  // unit-norm right-hand side
     half2_t rh[R];
@@ -1931,8 +1942,7 @@ __device__ __forceinline__ void block_body_h(const BlockArgs& a, int ch, unsigne
 // Local problems of side 64: BlockCG64, four wavefronts per block (any
 // residual and correction type, arithmetic in float32).
 template <class TR, class TC>
-__device__ __forceinline__ void block_body_64(const BlockArgs& a, int ch, unsigned bi, unsigned nblk,
-                                              bool act) {
+__device__ __forceinline__ void block_body_64(const BlockArgs& a, int ch, unsigned bi, unsigned nblk) {
   constexpr int B = 64, R = BlockCG64::R;
   __shared__ BlockCG64::Shared sh;
   const LevelView& lv = a.lv;
@@ -1954,8 +1964,7 @@ __device__ __forceinline__ void block_body_64(const BlockArgs& a, int ch, unsign
       if (!(colok && cg.w * R + k < bh)) rho[k] = 0.0f;
   }
   const float thr = block_threshold(a, ch, bw, bh);
-  const int it = cg.solve(rho, v, thr, act ? a.maxit : 0);
-  if (!act) return;
+  const int it = cg.solve(rho, v, thr, a.maxit);
   const Fld<TC> out(a.contrib, (size_t)ch * ((size_t)nblk * B * B) + (size_t)bi * B * B,
                     a.s_contrib, a.rho, ch);
   const float wx = pou_weight(cg.lane, lv.nbx, bx, B, lv.o, a.inv_o1);
@@ -1972,21 +1981,20 @@ __device__ __forceinline__ void block_body(const BlockArgs& a, unsigned lin) {
   const unsigned nblk = (unsigned)a.lv.nbx * (unsigned)a.lv.nby;
   const int ch = lin / nblk;
   const unsigned bi = lin - (unsigned)ch * nblk;
-  const bool act = channel_active(a.active, ch);  // tested after the loads
+  if (!channel_active(a.active, ch)) return;  // the whole workgroup: one channel
   if constexpr (B == 64) {
-    block_body_64<TR, TC>(a, ch, bi, nblk, act);
+    block_body_64<TR, TC>(a, ch, bi, nblk);
     return;
   }
   if constexpr (B == 32) {
     // a correction stored in 16 bits is solved for in packed float16 (with
     // float32 accumulation), whatever the residual's type
     if constexpr (is_f32<TR>() && is_f32<TC>())
-      block_body_f32<TC>(a, ch, bi, nblk, act);
+      block_body_f32<TC>(a, ch, bi, nblk);
     else
-      block_body_h<TR, TC>(a, ch, bi, nblk, act);
+      block_body_h<TR, TC>(a, ch, bi, nblk);
     return;
   }
-  if (!act) return;
   const LevelView& lv = a.lv;
   const int S = B - lv.o;
   const int bx = bi % lv.nbx, by = bi / lv.nbx;

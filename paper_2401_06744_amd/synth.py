@@ -226,8 +226,12 @@ def config_precision(kind: str = "bernoulli", W: int = 3840, H: int = 2160):
     return img, m
 
 
-def batched_specs(n: int = 64, seed: int = 40, wmax: int = 1920, hmax: int = 1080):
-    """Shapes of ``batched_problems``: ``(W, H, C, density, image_seed)`` per problem."""
+def batched_specs(n: int = 64, seed: int = 40, wmax: int = 1920, hmax: int = 1080,
+                  density: float | None = None):
+    """Shapes of ``batched_problems``: ``(W, H, C, density, image_seed)`` per problem.
+
+    ``density`` set: every problem gets that mask density, with the same sizes,
+    channels and seeds as the default draw."""
     rng = np.random.default_rng(seed)
     specs = []
     for _ in range(n):
@@ -236,7 +240,7 @@ def batched_specs(n: int = 64, seed: int = 40, wmax: int = 1920, hmax: int = 108
         C = 1 if rng.random() < 0.5 else 3
         dens = float(rng.uniform(0.01, 0.10))
         s = int(rng.integers(1 << 30))
-        specs.append((W, H, C, dens, s))
+        specs.append((W, H, C, dens if density is None else density, s))
     return specs
 
 
@@ -246,10 +250,12 @@ def batched_problem(i: int, n: int = 64, seed: int = 40, wmax: int = 1920, hmax:
     return frame_image(W, H, C, seed=s), bernoulli_mask(W, H, dens, seed=s + 1)
 
 
-def batched_problems(n: int = 64, seed: int = 40, wmax: int = 1920, hmax: int = 1080):
-    """``n`` problems of uneven size: W in [128, wmax], H in [128, hmax], C in {1, 3}, 1-10 % masks."""
+def batched_problems(n: int = 64, seed: int = 40, wmax: int = 1920, hmax: int = 1080,
+                     density: float | None = None):
+    """``n`` problems of uneven size: W in [128, wmax], H in [128, hmax], C in {1, 3}, 1-10 % masks
+    (or all at ``density``)."""
     return [(frame_image(W, H, C, seed=s), bernoulli_mask(W, H, dens, seed=s + 1))
-            for W, H, C, dens, s in batched_specs(n, seed, wmax, hmax)]
+            for W, H, C, dens, s in batched_specs(n, seed, wmax, hmax, density)]
 
 
 def poisson_trace(qps: float, n: int, seed: int = 50):

@@ -157,6 +157,60 @@ def test_batched_running_ahead_too_far_changes_nothing():
         assert np.array_equal(o, s)
 
 
+def test_batched_running_ahead_too_short_finishes_on_the_host():
+    """Same shapes, harder masks after easier ones: the cycles issued ahead
+    do not reach convergence, so the output issued with them writes only the
+    channels that stopped and the host finishes the rest: results as solo."""
+    shapes = [(301, 203), (160, 96)]
+    easy = [(synth.frame_image(W, H, 3, seed=830 + k), synth.bernoulli_mask(W, H, 0.4, seed=840 + k))
+            for k, (W, H) in enumerate(shapes)]
+    hard = [(f, synth.bernoulli_mask(f.shape[2], f.shape[1], 0.01, seed=850 + k))
+            for k, (f, _) in enumerate(easy)]
+    _, st, se = binding.inpaint_solve_batched(easy, TOL)
+    assert st == binding.OK
+    outs, st, sh = binding.inpaint_solve_batched(hard, TOL)
+    assert st == binding.OK
+    assert max(s["cycles"] for s in sh) > max(s["cycles"] for s in se)
+    for o, s in zip(outs, _solo(hard)):
+        assert np.array_equal(o, s)
+    # one problem alone, the same way round (a batch of one reads its own flags)
+    f, m = hard[0]
+    binding.inpaint_solve_ex(easy[0][0], easy[0][1], TOL)
+    u, st, s1 = binding.inpaint_solve_ex(f, m, TOL)
+    assert st == binding.OK
+    again, _, s2 = binding.inpaint_solve_ex(f, m, TOL)  # now ahead by the right count
+    assert np.array_equal(u, again) and s1["cycles"] == s2["cycles"]
+    assert np.array_equal(u, outs[0])
+    assert np.all(oracle.rel_res(u.astype(np.float64), f.astype(np.float64), m) <= TOL)
+
+
+def test_batched_in_place_run_ahead_with_a_rejected_problem():
+    """Outputs aliasing the inputs in a call that runs ahead and then finds an
+    input rejected: the valid problems, written once by the output issued
+    ahead and solved again from those buffers, still end as solo (the solve
+    reads f at known pixels only, which the output leaves as they were); the
+    rejected problem's buffer is untouched."""
+    import torch
+    probs = _mix(seed=900)[:3]
+    ref = _solo(probs)
+    dev = [(torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()) for f, m in probs]
+    _, st, _ = binding.inpaint_solve_batched(dev, TOL)  # this context now runs ahead
+    assert st == binding.OK
+    bad = dev[1][0].clone()
+    k = torch.nonzero(dev[1][1])[0]
+    bad[0, k[0], k[1]] = float("nan")
+    bad_before = bad.clone()
+    items = [(dev[0][0].clone(), dev[0][1]), (bad, dev[1][1]), (dev[2][0].clone(), dev[2][1])]
+    items = [(f, m, f) for f, m in items]
+    _, st, stats = binding.inpaint_solve_batched(items, TOL, raise_on_error=False)
+    torch.cuda.synchronize()
+    assert st == binding.E_INVALID
+    assert [s["status"] for s in stats] == [binding.OK, binding.E_INVALID, binding.OK]
+    assert np.array_equal(items[0][0].cpu().numpy(), ref[0])
+    assert np.array_equal(items[2][0].cpu().numpy(), ref[2])
+    assert torch.equal(torch.nan_to_num(bad, nan=7.0), torch.nan_to_num(bad_before, nan=7.0))
+
+
 def test_batched_argument_errors():
     probs = _mix()[:2]
     with pytest.raises(binding.InpaintError) as e:
