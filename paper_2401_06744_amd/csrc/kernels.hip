@@ -801,14 +801,20 @@ struct Former {
     } else if constexpr (mode_upd(MODE)) {
       float d = 0.0f;
       if constexpr (mode_contrib(MODE)) {
-        // all four slots are read, absent ones at a valid stand-in address and
-        // then dropped, so that the loads issue together rather than behind
-        // per-pixel branches
+        // the upper blocks' slots only in the rows they cover (a branch that
+        // is uniform over a wavefront but at the edges of those rows); the
+        // left block's slot is read in every column, an absent one at a valid
+        // stand-in address and then dropped (a branch per column, taken by
+        // some lanes of every wavefront, saves nothing)
         int ry0, ry1;
         bool hy;
         rows(gy, ry0, ry1, hy);
         const int cx0 = c.h0 ? c.cx0 : c.cx1;
-        const float d00 = cb.ld(ry0 + cx0), d01 = cb.ld(ry0 + c.cx1);
+        float d00 = 0.0f, d01 = 0.0f;
+        if (hy) {
+          d00 = cb.ld(ry0 + cx0);
+          d01 = cb.ld(ry0 + c.cx1);
+        }
         const float d10 = cb.ld(ry1 + cx0), d11 = cb.ld(ry1 + c.cx1);
         d = sum4(d00, d01, d10, d11, hy, c.h0);
       }
@@ -839,7 +845,11 @@ struct Former {
         bool hy;
         rows(gy, ry0, ry1, hy);
         const int cx0 = c.h0 ? c.cx0 : c.cx1;
-        const Px2 d00 = ld2(cb, ry0 + cx0), d01 = ld2(cb, ry0 + c.cx1);
+        Px2 d00{{0.0f, 0.0f}}, d01{{0.0f, 0.0f}};
+        if (hy) {  // as in value()
+          d00 = ld2(cb, ry0 + cx0);
+          d01 = ld2(cb, ry0 + c.cx1);
+        }
         const Px2 d10 = ld2(cb, ry1 + cx0), d11 = ld2(cb, ry1 + c.cx1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) d.v[h] = sum4(d00.v[h], d01.v[h], d10.v[h], d11.v[h], hy, c.h0);
@@ -915,7 +925,11 @@ __device__ __forceinline__ float coarse_updated(const PassArgs& a, const Fld<TC>
   const int cx0 = ax.h0 ? (ax.b1 - 1) * B * B + ax.l1 + S : cx1;
   const int ry1 = ay.b1 * cl.nbx * B * B + ay.l1 * B;
   const int ry0 = ay.h0 ? (ay.b1 - 1) * cl.nbx * B * B + (ay.l1 + S) * B : ry1;
-  const float d00 = cb.ld(ry0 + cx0), d01 = cb.ld(ry0 + cx1);
+  float d00 = 0.0f, d01 = 0.0f;
+  if (ay.h0) {  // the upper blocks' slots only in the rows they cover
+    d00 = cb.ld(ry0 + cx0);
+    d01 = cb.ld(ry0 + cx1);
+  }
   const float d10 = cb.ld(ry1 + cx0), d11 = cb.ld(ry1 + cx1);
   const float d = (((ay.h0 && ax.h0 ? d00 : 0.0f) + (ay.h0 ? d01 : 0.0f)) + (ax.h0 ? d10 : 0.0f)) + d11;
   const float un = uc.ld(Y * a.Pc + X) + d;
