@@ -958,6 +958,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   constexpr int TW = kTileW + 4;
   constexpr int RJ = (TH + NG - 1) / NG;     // phase-1 rows per thread
   constexpr int RK = kTileH / NG;            // phase-2 rows per thread
+  static_assert(RJ == RK + 1 && kTileH == NG * RK, "row slots: RK tile rows and one halo slot");
   const unsigned tiles_x = (unsigned)((a.lv.W + kTileW - 1) / kTileW);
   const unsigned ntiles = tiles_x * (unsigned)((a.lv.H + kTileH - 1) / kTileH);
   const int ch = lin / ntiles;
@@ -976,6 +977,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   // last in-image pair (its pixel W - 1 is the mirror of column W)
   const int gxe = min(gx, (W - 1) & ~1);
   const bool lastodd = ((W - 1) & 1) != 0;  // column W - 1 is the pair's second pixel
+  // Rows: slot k < RK of thread row group g holds tile row g + NG k (LDS row
+  // g + NG k + 1) in both phases, so that a prolongation's known flags of
+  // phase 1 serve phase 2; slot RK holds the top halo row (g = 0) or the
+  // bottom one (g = 1), and is idle for the other row groups.
+  const auto slot_ty = [&](int j) { return j < RK ? g + NG * j + 1 : (g == 0 ? 0 : TH - 1); };
+  const auto slot_on = [&](int j) { return j < RK || g < 2; };
   // Phase-2 inputs that do not depend on phase 1 (masks and right-hand sides
   // of this thread's rows) are loaded first, from clamped addresses, so that
   // their latency overlaps phase 1's.  (The final pass of the correction form
@@ -983,11 +990,13 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   unsigned short mk[RK];
   Px2 bvv[RK];
   if constexpr (!mode_fin(MODE)) {
+    if constexpr (!kProlong) {  // a prolongation takes them from phase 1
 #pragma unroll
-    for (int k = 0; k < RK; ++k) mk[k] = ld_mask2(a.c, min(y0 + g * RK + k, H - 1) * lv.P + gxe);
+      for (int k = 0; k < RK; ++k) mk[k] = ld_mask2(a.c, min(y0 + g + NG * k, H - 1) * lv.P + gxe);
+    }
     if (MODE == PASS_RES || !a.solution) {
 #pragma unroll
-      for (int k = 0; k < RK; ++k) bvv[k] = ld2(F.bb, min(y0 + g * RK + k, H - 1) * lv.P + gxe);
+      for (int k = 0; k < RK; ++k) bvv[k] = ld2(F.bb, min(y0 + g + NG * k, H - 1) * lv.P + gxe);
     } else {
 #pragma unroll
       for (int k = 0; k < RK; ++k) bvv[k] = Px2{{0.0f, 0.0f}};
@@ -1001,8 +1010,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
       typename Former<MODE, TU, TC>::Pre2 pr[RJ];
 #pragma unroll
       for (int j = 0; j < RJ; ++j) {
-        const int ty = min(g + NG * j, TH - 1);
-        pr[j] = F.pre2(col, min(max(y0 - 1 + ty, 0), H - 1));
+        if (!slot_on(j)) continue;
+        pr[j] = F.pre2(col, min(max(y0 - 1 + slot_ty(j), 0), H - 1));
+      }
+      if constexpr (!mode_fin(MODE)) {
+#pragma unroll
+        for (int k = 0; k < RK; ++k) mk[k] = pr[k].known;
       }
       // coarse cells (x0/2 - 1 .. x0/2 + 32) x (y0/2 - 1 .. y0/2 + 16), clamped
       const int cx0 = max((x0 >> 1) - 1, 0), cy0 = max((y0 >> 1) - 1, 0);
@@ -1017,23 +1030,20 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < RJ; ++j) {
-        const int ty = min(g + NG * j, TH - 1);
-        v[j] = F.fin2(col, min(max(y0 - 1 + ty, 0), H - 1), pr[j]);
+        if (!slot_on(j)) continue;
+        v[j] = F.fin2(col, min(max(y0 - 1 + slot_ty(j), 0), H - 1), pr[j]);
       }
     } else {
 #pragma unroll
       for (int j = 0; j < RJ; ++j) {
-        // the last row slot holds only the two bottom halo rows: the
-        // wavefronts of the other row groups skip it
-        if (j == RJ - 1 && g + NG * j >= TH) continue;
-        const int ty = g + NG * j;
-        v[j] = F.value2(col, min(max(y0 - 1 + ty, 0), H - 1));
+        if (!slot_on(j)) continue;  // the halo slot: wavefronts of row groups >= 2 skip it
+        v[j] = F.value2(col, min(max(y0 - 1 + slot_ty(j), 0), H - 1));
       }
     }
 #pragma unroll
     for (int j = 0; j < RJ; ++j) {
-      const int ty = g + NG * j;
-      if (ty < TH) {
+      const int ty = slot_ty(j);
+      if (slot_on(j)) {
         const float vl = lastodd ? v[j].v[1] : v[j].v[0];  // column W - 1
         const float v0 = gx <= W - 1 ? v[j].v[0] : vl;
         const float v1 = gx + 1 <= W - 1 ? v[j].v[1] : vl;
@@ -1059,10 +1069,10 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   double acc = 0.0;
   if constexpr (mode_fin(MODE)) {
 #pragma unroll
-    for (int k = 0; k < RK; ++k) mk[k] = ld_mask2(a.c, min(y0 + g * RK + k, H - 1) * lv.P + gxe);
+    for (int k = 0; k < RK; ++k) mk[k] = ld_mask2(a.c, min(y0 + g + NG * k, H - 1) * lv.P + gxe);
     if (!a.solution) {
 #pragma unroll
-      for (int k = 0; k < RK; ++k) bvv[k] = ld2(F.bb, min(y0 + g * RK + k, H - 1) * lv.P + gxe);
+      for (int k = 0; k < RK; ++k) bvv[k] = ld2(F.bb, min(y0 + g + NG * k, H - 1) * lv.P + gxe);
     } else {
 #pragma unroll
       for (int k = 0; k < RK; ++k) bvv[k] = Px2{{0.0f, 0.0f}};
@@ -1072,7 +1082,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, unsigned lin) {
   const bool r_small = mode_fin(MODE) || ((MODE == PASS_PSOL || MODE == PASS_RES) && a.r_tc);
 #pragma unroll
   for (int k = 0; k < RK; ++k) {
-    const int ty = g * RK + k;
+    const int ty = g + NG * k;
     const int gy = y0 + ty;
     if (!(in0 && gy < H)) continue;
     const int off = gy * lv.P + gx;
