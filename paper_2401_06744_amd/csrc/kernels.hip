@@ -167,12 +167,20 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// Workgroups are handed to the 8 XCDs round robin; remap so that each XCD
-// works on one contiguous range of tiles and shares halo reads in its L2.
+// Workgroups are handed to the 8 XCDs round robin.  Remap them so that each
+// XCD works on runs of kXcdRun consecutive work items (tiles or blocks, which
+// share halo and overlap reads in that XCD's L2), the runs dealt out to the
+// XCDs in turn: every XCD then holds an even share of every part of the grid,
+// and of every problem of a batch, whatever their costs.  (One contiguous
+// eighth of the grid per XCD left an XCD with the slow problems of a batch,
+// or with the last problems still iterating, and was slower on a single
+// frame too; the last partial round keeps the hardware order.)
+constexpr unsigned kXcdRun = 16;
 __device__ __forceinline__ unsigned xcd_remap(unsigned wg, unsigned n) {
-  const unsigned nper = n >> 3, rem = n & 7u;
-  const unsigned xcd = wg & 7u, idx = wg >> 3;
-  return xcd < rem ? xcd * (nper + 1) + idx : rem * (nper + 1) + (xcd - rem) * nper + idx;
+  const unsigned full = n - n % (8u * kXcdRun);
+  if (wg >= full) return wg;
+  const unsigned xcd = wg & 7u, idx = wg >> 3;  // the idx-th work item of this XCD
+  return ((idx / kXcdRun) * 8u + xcd) * kXcdRun + idx % kXcdRun;
 }
 
 // Problem owning global work item g of a batched launch: the largest p with
