@@ -9,6 +9,7 @@ call raises ``RuntimeError``: there is no fallback path.
 from __future__ import annotations
 
 import ctypes as ct
+from collections.abc import Mapping
 import os
 import threading
 
@@ -66,6 +67,29 @@ class InpaintStats(ct.Structure):
             v = getattr(self, k)
             d[k] = list(v) if k in ("kernel_ms", "kernel_calls") else v
         return d
+
+
+class StatsView(Mapping):
+    """Read-only mapping over one InpaintStats of a batch: fields are read from
+    the C struct when asked for (a batch's statistics are not copied into 64
+    dicts on every call)."""
+    __slots__ = ("_s",)
+    _names = tuple(k for k, _ in InpaintStats._fields_)
+
+    def __init__(self, s: InpaintStats):
+        self._s = s
+
+    def __getitem__(self, k):
+        if k not in self._names:
+            raise KeyError(k)
+        v = getattr(self._s, k)
+        return list(v) if k in ("kernel_ms", "kernel_calls") else v
+
+    def __iter__(self):
+        return iter(self._names)
+
+    def __len__(self):
+        return len(self._names)
 
 
 class InpaintProblem(ct.Structure):
@@ -255,7 +279,7 @@ def inpaint_solve_batched(problems, tol: float = 1e-6, opts: InpaintOpts | None 
                                      _stream_handle(stream), stats)
     if raise_on_error:
         _check(st)
-    return outs, st, [stats[k].as_dict() for k in range(len(problems))]
+    return outs, st, [StatsView(stats[k]) for k in range(len(problems))]
 
 
 def inpaint_autotune(problems, tol: float = 1e-6, base: InpaintOpts | None = None, stream=None):

@@ -4,6 +4,8 @@ import glob
 import os
 import re
 
+import pytest
+
 from paper_2401_06744_amd import binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -121,3 +123,17 @@ def test_noalloc_entry_point_checks_before_device_work():
                                          1e-6, ctypes.c_void_p(3 << 44), ctypes.byref(opts), None, None)
         assert code == binding.E_INVALID, (code, binding.inpaint_last_error())
     assert binding.NOALLOC_SCRATCH_BYTES == 256 << 20
+
+
+def test_batched_stats_view_reads_the_struct():
+    """The batched binding returns one read-only mapping per problem over the
+    C statistics struct: same keys and values as the dict of a single solve."""
+    s = binding.InpaintStats()
+    s.rel_res, s.cycles, s.status = 3.5e-7, 2, binding.NOT_CONVERGED
+    s.kernel_calls[2] = 4
+    v = binding.StatsView(s)
+    assert dict(v) == s.as_dict()
+    assert v["cycles"] == 2 and v["rel_res"] == 3.5e-7 and v["status"] == binding.NOT_CONVERGED
+    assert v["kernel_calls"][2] == 4 and len(v) == len(binding.InpaintStats._fields_)
+    with pytest.raises(KeyError):
+        v["no_such_field"]
