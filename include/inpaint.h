@@ -68,10 +68,20 @@ typedef enum inpaint_schedule {
   INPAINT_SCHED_CG_MULTILEVEL = 5, /* comparison (Section 5.1): the MULTILEVEL cascade with CG
                                    in place of ORAS (pre_smooth CG iterations per coarse level,
                                    default 8), then CG on the finest grid as in SCHED_CG */
-  INPAINT_SCHED_CG_MULTIGRID = 6   /* comparison (Section 5.1): the RFMG cascade and V-cycles
+  INPAINT_SCHED_CG_MULTIGRID = 6,  /* comparison (Section 5.1): the RFMG cascade and V-cycles
                                    with CG in place of ORAS as pre- and post-smoother
                                    (pre_smooth / post_smooth CG iterations, default 2 each,
                                    each smoothing restarting CG from the current residual) */
+  INPAINT_SCHED_WARM = 7          /* warm start: the RFMG V-cycles on the finest grid from an
+                                   initial guess instead of the cascade.  On entry `out`
+                                   holds the guess (its values at unknown pixels are used,
+                                   known pixels take f; it must be finite there); the first
+                                   convergence test is on the guess itself, so a guess that
+                                   already meets tol is returned after 0 cycles.  For
+                                   sequences of related problems, as the next frame of a
+                                   video or the next mask of an encoder's search (the
+                                   temporal coherence Section 1.2 leaves unused).  Solve and
+                                   batched entry points only (the server rejects it). */
   /* The three CG schedules run in float32 only (another precision is E_INVALID)
      and are not accepted by inpaint_server_create.  Float32 CG can stall with a
      relative residual between 1e-6 and 1e-5 on sparse (1-2 %) masks: a CG solve
@@ -103,7 +113,7 @@ typedef struct inpaint_opts {
   int schedule;        /* inpaint_schedule (default INPAINT_SCHED_RFMG) */
   int max_cycles;      /* cap on V-cycles (or finest ORAS iterations for MULTILEVEL and
                           SINGLE, or blocks of 8 CG iterations for CG and CG_MULTILEVEL);
-                          default 30 for RFMG/FMG/CG_MULTIGRID, 500 for CG and
+                          default 30 for RFMG/FMG/CG_MULTIGRID/WARM, 500 for CG and
                           CG_MULTILEVEL, 2000 otherwise */
   int pre_smooth;      /* ORAS iterations before the coarse correction, at most 16
                           (0 = default 1; a negative value = none); CG iterations for the

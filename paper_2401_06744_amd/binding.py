@@ -24,7 +24,7 @@ E_INVALID, E_EMPTY_MASK, E_NOMEM, E_DEVICE, E_DIVERGED = -1, -2, -3, -4, -5
 KERNELS = ["stage", "pyramid", "block_solve", "update", "prolong", "restrict", "coarse",
            "residual", "output"]
 SCHED_RFMG, SCHED_FMG, SCHED_MULTILEVEL, SCHED_SINGLE, SCHED_CG = 0, 1, 2, 3, 4
-SCHED_CG_MULTILEVEL, SCHED_CG_MULTIGRID = 5, 6
+SCHED_CG_MULTILEVEL, SCHED_CG_MULTIGRID, SCHED_WARM = 5, 6, 7
 RHS_MODIFIED, RHS_NAIVE = 0, 1
 PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
 

@@ -24,6 +24,7 @@ enum StepKind : int {
   S_GATHER,
   S_CG_DIR,
   S_CG_STEP,
+  S_WARM,
 };
 
 // One batched launch: n argument structs and n + 1 work offsets, stored at

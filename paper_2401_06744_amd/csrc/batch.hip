@@ -189,6 +189,7 @@ hipError_t issue_step(const Step& st, const unsigned char* dev, int prec, int B,
       case S_OUTPUT: e = launch_output_b((const OutputArgs*)a, start, st.n, st.total, s); break;
       case S_CG_DIR: e = launch_cg_dir_b((const CgArgs*)a, start, st.n, st.total, s); break;
       case S_CG_STEP: e = launch_cg_step_b((const CgArgs*)a, start, st.n, st.total, s); break;
+      case S_WARM: e = launch_warm_b((const WarmArgs*)a, start, st.n, st.total, s); break;
       default: e = hipErrorInvalidValue;
     }
     return e;
@@ -438,6 +439,11 @@ void build_vcycle_cg(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
 
 // The coarse-to-fine initial guess (Section 4.2) of every member.
 void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
+  if (o.schedule == INPAINT_SCHED_WARM) {
+    // no cascade: the residual of the guess and the first convergence test
+    step_residual(P, ms);
+    return;
+  }
   if (o.schedule == INPAINT_SCHED_CG) {
     step_cg_residual(P, ms);
     step_cg(P, ms, true);
@@ -487,7 +493,8 @@ void build_cascade(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
 }
 
 void build_cycle(Plan& P, const std::vector<Member*>& ms, const Opts& o) {
-  if (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG) {
+  if (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG ||
+      o.schedule == INPAINT_SCHED_WARM) {
     build_vcycle(P, ms, 0, o);
   } else if (o.schedule == INPAINT_SCHED_CG_MULTIGRID) {
     build_vcycle_cg(P, ms, o);
@@ -800,7 +807,12 @@ void init_member(Member& m, const inpaint_problem& p, Workspace* ws, const Opts&
     HIPCHK(hipMemcpyAsync(m.ws->m_dev, p.mask, (size_t)m.W * m.H, hipMemcpyHostToDevice, s));
     m.m_d = m.ws->m_dev;
   }
-  if (!od) m.o_d = m.ws->o_dev;
+  if (!od) {
+    m.o_d = m.ws->o_dev;
+    // a warm start reads its guess from out
+    if (o.schedule == INPAINT_SCHED_WARM)
+      HIPCHK(hipMemcpyAsync(m.o_d, p.out, nf, hipMemcpyHostToDevice, s));
+  }
   m.final_cur.assign(m.C, -1);
   m.rel.assign(m.C, 0.0);
 }
@@ -831,6 +843,16 @@ void build_prepare(Plan& P, const std::vector<Member*>& ms, const Opts& o, int* 
     P.add(a, work_stage(a));
   }
   P.end();
+  if (o.schedule == INPAINT_SCHED_WARM) {
+    // the caller's guess (in out) becomes the finest iterate, known pixels b
+    P.begin(S_WARM, 0, 0);
+    for (Member* m : ms) {
+      const Level& L0 = m->ws->lv[0];
+      const WarmArgs a{L0.v, L0.c, L0.b, L0.u[0], m->o_d, m->W, m->C};
+      P.add(a, work_warm(a));
+    }
+    P.end();
+  }
   if (!single) {
     int maxL = 0;
     for (Member* m : ms) maxL = std::max(maxL, m->ws->L);

@@ -261,6 +261,17 @@ struct OutputArgs {
   int cur[3];
 };
 
+// Initial guess of a warm-started solve on the finest grid: u = known ? b :
+// src, with src the caller's planar buffer [C][H][Psrc].
+struct WarmArgs {
+  LevelView lv;
+  const uint8_t* c;
+  const float* b;
+  float* u;
+  const float* src;
+  int Psrc, C;
+};
+
 // Work items (workgroups) of one problem in each kernel; a batched launch
 // gives problem p the global items [start[p], start[p + 1]).
 unsigned work_stage(const StageArgs& a);
@@ -270,6 +281,7 @@ unsigned work_restrict(const RestrictArgs& a, int C);
 unsigned work_block(const BlockArgs& a, int C);
 unsigned work_coarse(const CoarseArgs& a, int C);
 unsigned work_output(const OutputArgs& a);
+unsigned work_warm(const WarmArgs& a);
 
 // Batched launches: `args` (device) holds n argument structs, `start` (device)
 // n + 1 offsets, `total` = start[n].  Every problem shares the kernel variant:
@@ -289,6 +301,8 @@ hipError_t launch_coarse_b(const CoarseArgs* args, const unsigned* start, int n,
                            int prec, int level0, int B, hipStream_t s);
 hipError_t launch_output_b(const OutputArgs* args, const unsigned* start, int n, unsigned total,
                            hipStream_t s);
+hipError_t launch_warm_b(const WarmArgs* args, const unsigned* start, int n, unsigned total,
+                         hipStream_t s);
 unsigned work_cg(const CgArgs& a, int C);
 hipError_t launch_cg_dir_b(const CgArgs* args, const unsigned* start, int n, unsigned total,
                            hipStream_t s);

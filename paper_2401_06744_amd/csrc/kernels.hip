@@ -253,6 +253,35 @@ __device__ __forceinline__ void output_body(const OutputArgs& a, unsigned lin) {
   }
 }
 
+// The initial guess of a warm-started solve, laid out as the output (64
+// columns x kOutRows rows every 4 per workgroup): u = known ? b : src, the
+// caller's buffer read with its own pitch.
+__device__ __forceinline__ void warm_body(const WarmArgs& a, unsigned lin) {
+  const LevelView& lv = a.lv;
+  const unsigned gxn = (unsigned)((lv.W + 63) / 64);
+  const unsigned per = gxn * (unsigned)((lv.H + 4 * kOutRows - 1) / (4 * kOutRows));
+  const int ch = lin / per;
+  const unsigned q = lin - (unsigned)ch * per;
+  const int x = (int)(q % gxn) * 64 + (threadIdx.x & 63);
+  const int y0 = (int)(q / gxn) * 4 * kOutRows + (threadIdx.x >> 6);
+  if (x >= lv.W) return;
+  uint8_t k[kOutRows];
+  float bv[kOutRows], sv[kOutRows];
+#pragma unroll
+  for (int r = 0; r < kOutRows; ++r) {
+    const int y = min(y0 + 4 * r, lv.H - 1);
+    const size_t o = (size_t)y * lv.P + x;
+    k[r] = glb(a.c)[o];
+    bv[r] = glb(a.b)[(size_t)ch * lv.plane + o];
+    sv[r] = glb(a.src)[(size_t)ch * a.Psrc * lv.H + (size_t)y * a.Psrc + x];
+  }
+#pragma unroll
+  for (int r = 0; r < kOutRows; ++r) {
+    const int y = y0 + 4 * r;
+    if (y < lv.H) glb(a.u)[(size_t)ch * lv.plane + (size_t)y * lv.P + x] = k[r] ? bv[r] : sv[r];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // coarse problems (Section 4.3)
 // ---------------------------------------------------------------------------
@@ -2155,6 +2184,13 @@ __global__ void __launch_bounds__(256) k_output_b(const OutputArgs* __restrict__
 }
 
 
+__global__ void __launch_bounds__(256) k_warm_b(const WarmArgs* __restrict__ args,
+                                                const unsigned* __restrict__ start, int n) {
+  const unsigned g = xcd_remap(blockIdx.x, gridDim.x);
+  const int p = find_problem(start, n, g);
+  warm_body(args[p], g - start[p]);
+}
+
 template <class TF, class TC>
 __global__ void __launch_bounds__(256) k_rhs_down(RhsArgs a) {
   rhs_body<TF, TC>(a, xcd_remap(blockIdx.x, gridDim.x));
@@ -2492,6 +2528,18 @@ hipError_t launch_output_b(const OutputArgs* args, const unsigned* start, int n,
                            hipStream_t s) {
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_output_b, dim3(total), dim3(256), 0, s, args, start, n);
+  return hipGetLastError();
+}
+
+unsigned work_warm(const WarmArgs& a) {
+  return (unsigned)((a.lv.W + 63) / 64) * (unsigned)((a.lv.H + 4 * kOutRows - 1) / (4 * kOutRows)) *
+         (unsigned)a.C;
+}
+
+hipError_t launch_warm_b(const WarmArgs* args, const unsigned* start, int n, unsigned total,
+                         hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_warm_b, dim3(total), dim3(256), 0, s, args, start, n);
   return hipGetLastError();
 }
 

@@ -224,6 +224,8 @@ INPAINT_EXPORT int inpaint_server_create(const inpaint_server_cfg* cfg, inpaint_
     o.profile = 0;
     if (cg_schedule(o.schedule))
       fail(INPAINT_E_INVALID, "the server runs the multigrid schedules (CG is a comparison schedule)");
+    if (o.schedule == INPAINT_SCHED_WARM)
+      fail(INPAINT_E_INVALID, "the server solves from the cascade (its outputs hold no guess)");
     int max_batch = 64;
     if (cfg && cfg->max_batch) max_batch = cfg->max_batch;
     if (max_batch < 1 || max_batch > 1024) fail(INPAINT_E_INVALID, "max_batch must lie in [1, 1024]");

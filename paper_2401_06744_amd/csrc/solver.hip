@@ -43,7 +43,7 @@ Opts resolve(const inpaint_opts* p) {
   if (!(o.gamma > 0.0f && o.gamma <= 1.0f)) fail(INPAINT_E_INVALID, "gamma must lie in (0, 1]");
   if (!(o.tau >= 0.0f) || !std::isfinite(o.tau)) fail(INPAINT_E_INVALID, "tau must be finite and >= 0");
   if (o.maxit < 0 || o.coarse_maxit < 0) fail(INPAINT_E_INVALID, "iteration caps must be >= 0");
-  if (o.schedule < INPAINT_SCHED_RFMG || o.schedule > INPAINT_SCHED_CG_MULTIGRID)
+  if (o.schedule < INPAINT_SCHED_RFMG || o.schedule > INPAINT_SCHED_WARM)
     fail(INPAINT_E_INVALID, "unknown schedule");
   if (cg_schedule(o.schedule) && o.prec != PREC_F32)
     fail(INPAINT_E_INVALID, "the CG schedules run in float32 only");
@@ -59,7 +59,7 @@ Opts resolve(const inpaint_opts* p) {
   if (o.max_cycles < 0) fail(INPAINT_E_INVALID, "max_cycles must be >= 0");
   if (o.max_cycles == 0)
     o.max_cycles = (o.schedule == INPAINT_SCHED_RFMG || o.schedule == INPAINT_SCHED_FMG ||
-                    o.schedule == INPAINT_SCHED_CG_MULTIGRID)
+                    o.schedule == INPAINT_SCHED_CG_MULTIGRID || o.schedule == INPAINT_SCHED_WARM)
                        ? 30
                    : cg_schedule(o.schedule) ? 500
                                              : 2000;

@@ -137,3 +137,21 @@ def test_batched_stats_view_reads_the_struct():
     assert v["kernel_calls"][2] == 4 and len(v) == len(binding.InpaintStats._fields_)
     with pytest.raises(KeyError):
         v["no_such_field"]
+
+
+def test_schedules_are_validated_and_the_server_refuses_a_warm_start():
+    """Schedules 0..7 are accepted (7 = warm start from the guess in out), any
+    other value is invalid before any work; the request loop solves from the
+    cascade and rejects a warm start before it touches the device."""
+    code, msg = _fake_solve(64, 64, schedule=8)
+    assert code == binding.E_INVALID and "schedule" in msg, (code, msg)
+    assert binding.SCHED_WARM == 7
+    # an accepted schedule gets past option checks to the size checks
+    code, msg = _fake_solve(1 << 24, 2, schedule=binding.SCHED_WARM)
+    assert code == binding.E_INVALID and "2^24" in msg, (code, msg)
+    cfg = binding.InpaintServerCfg()
+    cfg.struct_size = ctypes.sizeof(binding.InpaintServerCfg)
+    cfg.opts = binding.make_opts(schedule=binding.SCHED_WARM)
+    h = ctypes.c_void_p()
+    code = binding.lib().inpaint_server_create(ctypes.byref(cfg), ctypes.byref(h))
+    assert code == binding.E_INVALID and "cascade" in binding.inpaint_last_error()
