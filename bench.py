@@ -5,7 +5,7 @@ seeded synthetic image) to a relative residual of 1e-6 through the C ABI,
 with f, mask and out resident in HBM.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                  [--no-forms | --forms precision,solvers,sweeps,batched,serving]
+                  [--no-forms | --forms precision,solvers,sweeps,batched,serving,warm]
                   [--serve-qps 60,120,240,480] [--serve-requests 2000]
 
 Legs:
@@ -26,6 +26,9 @@ Legs:
              serving    Poisson arrivals of 720p/1080p/4K RGB requests at fixed QPS
                         and a saturating burst: frames/s, p50/p99 latency, vs the
                         same requests solved one at a time
+             warm       8-step sequences at 4K (an encoder's mask search, a panning
+                        video): the warm start from the previous solution vs
+                        the cold reduced full multigrid
   cpu        the CPU oracle (float64 Jacobi-PCG, test infrastructure): its time
              on channel 0 of the 4K frame to rel-res 1e-6 on one core (the
              cpu_baseline), and its reference solutions to rel-res 1e-12 (worker
@@ -200,6 +203,11 @@ def _inputs(kind, arg):
         return synth.batched_problems()[arg]
     if kind == "serve":
         return serve_entry(*arg)[:2]
+    if kind == "warm_enc":
+        f, m = synth.config_4k(density=arg[0])
+        return f, synth.mask_search(m, arg[1], share=WARM_SHARE)[arg[1]]
+    if kind == "warm_vid":
+        return synth.pan_frame(3840, 2160, arg)
     raise ValueError(kind)
 
 
@@ -304,6 +312,9 @@ def main() -> int:
             jobs += [("serve", (0, j), ch) for j in (0, 1) for ch in range(3)]
         if forms and "sweeps" in legs:
             jobs += [("4kq", d, 0) for d in QUALITY_DENSITIES] + [("4ke", LEAK_DENSITY, 0)]
+        if forms and "warm" in legs:
+            jobs += [(k, a, ch) for k, a in (("warm_enc", (args.density, WARM_STEPS)), ("warm_vid", WARM_STEPS))
+                     for ch in range(3)]
     host_cores, cpu_model = host_cpu()
     nproc = min(max(len(jobs), 0 if args.no_cpu_baseline else 3), max(3, host_cores - 1))
     pool = mp.get_context("spawn").Pool(nproc, initializer=_init_worker) if nproc else None
@@ -477,6 +488,9 @@ def main() -> int:
         if "serving" in legs:
             form_res["serving"] = serving_leg(binding, torch, args, pending)
             log("serving form done")
+        if "warm" in legs:
+            form_res["warm"] = warm_leg(binding, torch, synth, args, pending)
+            log("warm start form done")
     if check and full:
         for ch in range(C):
             pending[f"headline/{ch}"] = (("4k", args.density, ch), out_host[ch])
@@ -709,7 +723,9 @@ def tuning_leg(binding, torch, synth, args, fd4, md4, pending):
 
 QUALITY_DENSITIES = (0.005, 0.01, 0.02, 0.05, 0.10)
 LEAK_DENSITY = 0.02
-FORM_LEGS = ("precision", "solvers", "sweeps", "batched", "serving")
+FORM_LEGS = ("precision", "solvers", "sweeps", "batched", "serving", "warm")
+WARM_STEPS = 8       # solves per warm-start sequence
+WARM_SHARE = 0.02    # share of the known pixels moved per mask-search step
 EXTRA_LEGS = ("tuning",)   # run only when --forms names them
 
 
@@ -859,6 +875,59 @@ def batched_leg(binding, torch, synth, args):
             "status": st_s, "rel_res_max": rr_s},
         "batched_equals_solo": "bitwise (tests/test_gpu_batched.py)",
     }
+
+
+def warm_leg(binding, torch, synth, args, pending):
+    """Warm start (schedule WARM: V-cycles from the previous solution) against
+    the cold reduced FMG, on two 4K RGB sequences at the benchmark tolerance:
+    an encoder's mask search (each step moves 2 % of the known pixels of the
+    4 % mask) and a panning video (one pixel per frame, a fresh 4 % mask per
+    frame).  Each sequence is timed as WARM_STEPS solves in a row, every warm
+    solve reading its guess from the buffer the previous one wrote."""
+    warm = binding.make_opts(schedule=binding.SCHED_WARM)
+    out = {"workload": f"3840x2160 RGB, rel-res {args.tol:g}, float32; mask search: the 4 % frame "
+                       f"(seeds 10, 20), {WARM_STEPS} steps each moving {WARM_SHARE:.0%} of the known "
+                       f"pixels (seeds 42...); video: the frame panned one pixel per frame, a fresh 4 % "
+                       f"mask per frame (seeds 60...); max error of the last solve against the oracle"}
+    f, m = synth.config_4k(density=args.density)
+    masks = synth.mask_search(m, WARM_STEPS, share=WARM_SHARE)
+    fd = torch.from_numpy(f).cuda()
+    seqs = {"mask_search": ([fd] * (WARM_STEPS + 1), [torch.from_numpy(x).cuda() for x in masks],
+                            ("warm_enc", (args.density, WARM_STEPS)))}
+    # synth.pan_frame(3840, 2160, t), with the roll done on the device
+    v0, _ = synth.pan_frame(3840, 2160, 0)
+    v0 = torch.from_numpy(v0).cuda()
+    seqs["video"] = ([torch.roll(v0, t, dims=2).contiguous() for t in range(WARM_STEPS + 1)],
+                     [torch.from_numpy(synth.pan_frame_mask(3840, 2160, t)).cuda() for t in range(WARM_STEPS + 1)],
+                     ("warm_vid", WARM_STEPS))
+    for name, (fs, ms, job) in seqs.items():
+        buf = torch.empty_like(fd)
+        cold_out = torch.empty_like(fd)
+        res = {}
+        for mode in ("cold", "warm"):
+            for rep in range(2):  # the first pass builds workspaces and plans
+                # the guess for step 1: the solution of step 0
+                binding.inpaint_solve_ex(fs[0], ms[0], args.tol, out=buf)
+                torch.cuda.synchronize()
+                cycles = []
+                t = time.perf_counter()
+                for k in range(1, WARM_STEPS + 1):
+                    if mode == "warm":
+                        _, _, st = binding.inpaint_solve_ex(fs[k], ms[k], args.tol, out=buf, opts=warm)
+                    else:
+                        _, _, st = binding.inpaint_solve_ex(fs[k], ms[k], args.tol, out=cold_out)
+                    cycles.append(st["cycles"])
+                torch.cuda.synchronize()
+                sec = (time.perf_counter() - t) / WARM_STEPS
+            last = (buf if mode == "warm" else cold_out).cpu().numpy()
+            res[mode] = {"ms": round(1e3 * sec, 3), "fps": round(1.0 / sec, 1), "cycles": cycles,
+                         "rel_res_max": float(binding.inpaint_rel_res(last, fs[-1].cpu().numpy(),
+                                                                      ms[-1].cpu().numpy()).max())}
+            for ch in range(last.shape[0]):
+                pending[f"warm/{name}/{mode}/ch{ch}"] = ((*job, ch), last[ch])
+        res["speedup"] = round(res["cold"]["ms"] / res["warm"]["ms"], 3)
+        out[name] = res
+    return out
 
 
 def serving_leg(binding, torch, args, pending):

@@ -207,6 +207,40 @@ def edge_mask(W: int, H: int, density: float, seed: int, region_seed: int,
 # Named workloads
 # --------------------------------------------------------------------------
 
+def perturbed_mask(mask: np.ndarray, share: float, seed: int) -> np.ndarray:
+    """``mask`` with ``share`` of its known pixels moved to unknown pixels
+    drawn at random (the same count known): one step of an encoder's mask
+    search."""
+    rng = np.random.default_rng(seed)
+    m = mask.ravel().copy()
+    known = np.flatnonzero(m)
+    unknown = np.flatnonzero(m == 0)
+    k = int(round(share * known.size))
+    m[rng.choice(known, size=k, replace=False)] = 0
+    m[rng.choice(unknown, size=k, replace=False)] = 1
+    return m.reshape(mask.shape)
+
+
+def mask_search(mask: np.ndarray, steps: int, share: float = 0.02, seed: int = 42) -> list:
+    """``mask`` and ``steps`` successive perturbations of it (seeds seed, seed + 1, ...)."""
+    seq = [mask]
+    for j in range(steps):
+        seq.append(perturbed_mask(seq[-1], share, seed + j))
+    return seq
+
+
+def pan_frame_mask(W: int, H: int, t: int, density: float = 0.04, mask_seed: int = 60) -> np.ndarray:
+    """The mask of frame t of the panning video: a fresh Bernoulli mask."""
+    return bernoulli_mask(W, H, density, seed=mask_seed + t)
+
+
+def pan_frame(W: int, H: int, t: int, seed: int = 10, density: float = 0.04, mask_seed: int = 60):
+    """Frame t of a panning video: the RGB frame of ``seed`` moved t pixels to
+    the right (wrapping), with a fresh Bernoulli mask (seed mask_seed + t)."""
+    f = np.ascontiguousarray(np.roll(frame_image(W, H, 3, seed=seed), t, axis=2))
+    return f, pan_frame_mask(W, H, t, density, mask_seed)
+
+
 def config_small(W: int = 256, H: int = 256, density: float = 0.05):
     """256x256 grey, smooth field (seed 1), Bernoulli mask (seed 2)."""
     return plain_image(W, H, seed=1), bernoulli_mask(W, H, density, seed=2)

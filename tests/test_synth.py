@@ -54,3 +54,18 @@ def test_edge_mask_concentrates_on_region_borders():
     share = (m.astype(bool) & e).sum() / m.sum()
     assert 0.7 < share < 0.9
     assert np.array_equal(m, synth.edge_mask(W, H, 0.02, seed=5, region_seed=10))
+
+
+def test_warm_start_sequences():
+    m = synth.bernoulli_mask(300, 200, 0.05, seed=3)
+    seq = synth.mask_search(m, 3, share=0.02, seed=42)
+    k = int(m.sum())
+    moved = int(round(0.02 * k))
+    for a, b in zip(seq, seq[1:]):
+        assert int(b.sum()) == k                      # the same number of known pixels
+        assert int((a & ~b).sum()) == moved           # moved away ...
+        assert int((b & ~a).sum()) == moved           # ... to pixels unknown before
+    assert np.array_equal(synth.mask_search(m, 3, share=0.02, seed=42)[3], seq[3])  # seeded
+    f0, m0 = synth.pan_frame(64, 32, 0)
+    f2, m2 = synth.pan_frame(64, 32, 2)
+    assert np.array_equal(f2[:, :, 2:], f0[:, :, :-2]) and not np.array_equal(m0, m2)
