@@ -14,6 +14,9 @@ Jobs:
   ("batched", i, ch)                        problem i of the 64-problem batch
   ("frame", W, H, C, img_seed, density, mask_seed, ch)
                                             synth.frame_image + synth.bernoulli_mask
+  ("pan", t, ch)                            frame t of the 4K panning video (synth.pan_frame)
+  ("msearch", k, ch)                        the 4K frame with step k of the mask search
+                                            (synth.mask_search of its 4 % mask)
 """
 from __future__ import annotations
 
@@ -28,6 +31,7 @@ TOL = 1e-12
 # the workloads of the full-size parity tests (tests/test_gpu_x_fullsize.py)
 BATCHED_SAMPLE_STRIDE = 8
 SERVED = {"4k": (3840, 2160, 3, 90, 0.03, 91), "1080p": (1920, 1080, 3, 92, 0.05, 93)}
+WARM_STEP = 2  # the warm-start sequences are checked at their second step
 
 
 def job_inputs(job):
@@ -43,6 +47,11 @@ def job_inputs(job):
     if kind == "frame":
         W, H, C, fs, d, ms = job[1:7]
         return synth.frame_image(W, H, C, seed=fs), synth.bernoulli_mask(W, H, d, seed=ms)
+    if kind == "pan":
+        return synth.pan_frame(3840, 2160, job[1])
+    if kind == "msearch":
+        f, m = synth.config_4k()
+        return f, synth.mask_search(m, job[1])[job[1]]
     raise ValueError(f"unknown job {job!r}")
 
 
@@ -78,6 +87,7 @@ def full_size_jobs():
     jobs = [("prec", k, ch) for k in ("bernoulli", "bluenoise") for ch in range(3)]
     jobs += [("4k", 0.04, ch) for ch in range(3)]
     jobs += [("frame", *SERVED["4k"], ch) for ch in range(SERVED["4k"][2])]
+    jobs += [(kind, WARM_STEP, ch) for kind in ("pan", "msearch") for ch in range(3)]
     specs = synth.batched_specs()
     bj = [("batched", i, ch) for i in batched_sample() for ch in range(specs[i][2])]
     bj.sort(key=lambda j: -specs[j[1]][0] * specs[j[1]][1])

@@ -143,3 +143,38 @@ def test_served_4k_and_1080p_requests(oracle_refs):
         solo, _, _ = binding.inpaint_solve_ex(dev[name][0], dev[name][1], TOL, opts=opts)
         torch.cuda.synchronize()
         assert np.array_equal(solo.cpu().numpy(), u), name
+
+
+@pytest.mark.timeout(1800)
+@pytest.mark.parametrize("kind", ["pan", "msearch"])
+def test_warm_start_4k_sequences(kind, oracle_refs):
+    """The warm start at full size: steps 1 and 2 of the panning video (a fresh
+    4 % mask each frame) or of the mask search (2 % of the known pixels moved
+    per step), each solved in place from the previous step's result (step 0
+    solved cold); step 2 against the oracle on every channel, and the warm
+    result against the cold solve of the same step (both within the gate)."""
+    import torch
+    n = refs_mod.WARM_STEP
+    if kind == "pan":
+        seq = [synth.pan_frame(3840, 2160, t) for t in range(n + 1)]
+    else:
+        f0, m0 = synth.config_4k()
+        seq = [(f0, m) for m in synth.mask_search(m0, n)]
+    warm = binding.make_opts(schedule=binding.SCHED_WARM)
+    fd, md = torch.from_numpy(seq[0][0]).cuda(), torch.from_numpy(seq[0][1]).cuda()
+    buf, st, _ = binding.inpaint_solve_ex(fd, md, TOL)
+    assert st == binding.OK
+    cycles = []
+    for t in range(1, n + 1):
+        fd, md = torch.from_numpy(seq[t][0]).cuda(), torch.from_numpy(seq[t][1]).cuda()
+        _, st, stats = binding.inpaint_solve_ex(fd, md, TOL, out=buf, opts=warm)
+        torch.cuda.synchronize()
+        assert st == binding.OK, (t, st)
+        cycles.append(stats["cycles"])
+    f, m = seq[n]
+    jobs = [(kind, n, ch) for ch in range(3)]
+    _check(f"warm {kind} step {n} (V-cycles {cycles})", buf.cpu().numpy(), f, m, oracle_refs, jobs)
+    cold, st, stats = binding.inpaint_solve_ex(fd, md, TOL)
+    torch.cuda.synchronize()
+    assert st == binding.OK
+    _check(f"cold {kind} step {n} ({stats['cycles']} cycles)", cold.cpu().numpy(), f, m, oracle_refs, jobs)
