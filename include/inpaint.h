@@ -75,9 +75,10 @@ typedef enum inpaint_schedule {
   INPAINT_SCHED_WARM = 7          /* warm start: the RFMG V-cycles on the finest grid from an
                                    initial guess instead of the cascade.  On entry `out`
                                    holds the guess (its values at unknown pixels are used,
-                                   known pixels take f; it must be finite there); the first
-                                   convergence test is on the guess itself, so a guess that
-                                   already meets tol is returned after 0 cycles.  For
+                                   known pixels take f; a channel whose guess is not finite
+                                   there stops as INPAINT_E_DIVERGED, the others are solved);
+                                   the first convergence test is on the guess itself, so a
+                                   guess that already meets tol is returned after 0 cycles.  For
                                    sequences of related problems, as the next frame of a
                                    video or the next mask of an encoder's search (the
                                    temporal coherence Section 1.2 leaves unused).  Solve and

@@ -139,3 +139,29 @@ def test_warm_start_in_the_precision_forms(prec):
     u, st, stats = _warm(f, m, u0, precision=prec)
     assert st == binding.OK
     _check(u, f, m, ref)
+
+
+def test_non_finite_guess_diverges_alone():
+    """A guess that is not finite at an unknown pixel of one channel: that
+    channel's first convergence test sees a non-finite residual and the solve
+    ends with E_DIVERGED; the other channels are solved as from a finite
+    guess."""
+    import torch
+    f, m = _problem(seed=51)
+    ref = oracle.solve_pcg(f.astype(np.float64), m)
+    guess = np.full_like(f, 100.0)
+    unknown = np.flatnonzero(m.ravel() == 0)
+    guess[1].ravel()[unknown[len(unknown) // 2]] = np.nan
+    fd, md = torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()
+    od = torch.from_numpy(guess.copy()).cuda()
+    with pytest.raises(binding.InpaintError) as e:
+        binding.inpaint_solve_ex(fd, md, TOL, out=od, opts=binding.make_opts(schedule=WARM))
+    torch.cuda.synchronize()
+    assert e.value.code == binding.E_DIVERGED
+    u = od.cpu().numpy()
+    good = np.full_like(f, 100.0)
+    u_ok, st, _ = _warm(f, m, good)
+    assert st == binding.OK
+    for ch in (0, 2):
+        assert np.array_equal(u[ch], u_ok[ch]), ch
+        assert np.abs(u[ch].astype(np.float64) - ref[ch]).max() <= 0.5
