@@ -24,7 +24,10 @@
  *   - Relative residual (Section 5.2, "Stopping Criterion"; the start of the
  *     decay is not named in the paper, this library uses the zero-filled start
  *     C f):  rel_res(u) = ||b - A u||_2 / ||b - A C f||_2, in float64 on the
- *     finest grid, per channel.
+ *     finest grid, per channel.  Where ||b - A C f|| = 0 (every known pixel
+ *     next to an unknown one is 0 in that channel), C f is the exact solution:
+ *     the channel stops at its first convergence test and C f is returned,
+ *     with a relative residual of 0.
  *   - Guarantees on success: out equals f bit for bit at known pixels, and each
  *     channel is solved on its own (its result does not depend on the others).
  *   - Return value: an inpaint_status.  Negative values are errors and leave

@@ -884,6 +884,7 @@ void build_output(Plan& P, const std::vector<Member*>& ms) {
     a.out = m->o_d;
     a.Pout = m->W;
     a.C = m->C;
+    a.den = m->ws->den;
     P.add(a, work_output(a));
   }
   P.end();
@@ -909,6 +910,7 @@ static void build_output_selected(Plan& P, const std::vector<Member*>& ms, const
     a.out = m->o_d;
     a.Pout = m->W;
     a.C = m->C;
+    a.den = m->ws->den;
     a.flags = (const int*)m->ws->relres;
     a.nplan = nplan;
     a.ncycle = c.ncycle;

@@ -259,6 +259,9 @@ struct OutputArgs {
   const int* flags;
   int nplan, ncycle;
   int cur[3];
+  // reference residual norms [C] (nullptr: not read): a channel whose
+  // ||b - A C f|| is 0 is solved exactly by C f, which is written
+  const double* den;
 };
 
 // Initial guess of a warm-started solve on the finest grid: u = known ? b :

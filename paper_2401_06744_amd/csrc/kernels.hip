@@ -237,6 +237,8 @@ __device__ __forceinline__ void output_body(const OutputArgs& a, unsigned lin) {
     up = cb == 0 ? a.u[0] : a.u[1];
   }
   const gptr<const float> u = glb(up);
+  // ||b - A C f|| = 0: C f solves the channel exactly (0 at unknown pixels)
+  const bool exact = a.den && a.den[ch] == 0.0;
   uint8_t k[kOutRows];
   float bv[kOutRows], uv[kOutRows];
 #pragma unroll
@@ -249,7 +251,8 @@ __device__ __forceinline__ void output_body(const OutputArgs& a, unsigned lin) {
 #pragma unroll
   for (int r = 0; r < kOutRows; ++r) {
     const int y = y0 + 4 * r;
-    if (y < lv.H) glb(a.out)[(size_t)ch * a.Pout * lv.H + (size_t)y * a.Pout + x] = k[r] ? bv[r] : uv[r];
+    if (y < lv.H)
+      glb(a.out)[(size_t)ch * a.Pout * lv.H + (size_t)y * a.Pout + x] = k[r] ? bv[r] : (exact ? 0.0f : uv[r]);
   }
 }
 
@@ -495,7 +498,9 @@ __device__ void reduce_norm(double acc, int ch, unsigned tile, unsigned ntiles, 
       __hip_atomic_store(cnt + gi * 32, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (no.check) {
       const double den = no.den[ch];
-      const double rel = den > 0.0 ? sqrt(tot / den) : (tot > 0.0 ? INFINITY : 0.0);
+      // den = 0: A C f = b, so C f is the exact solution; the output writes
+      // it, and the channel counts as converged at its first test
+      const double rel = den > 0.0 ? sqrt(tot / den) : 0.0;
       no.relres[ch] = rel;
       // converged, or diverged (a non-finite residual): the channel stops
       if (rel <= no.tol || !(rel < INFINITY)) no.active[ch] = 0;

@@ -385,3 +385,41 @@ def test_workspace_cache_is_bounded():
         assert 0 < left <= 64 << 20
     finally:
         binding.inpaint_cache_limit(16 << 30)
+
+
+def _zero_reference_residual_problem():
+    """Channel 0: every known pixel next to an unknown one is 0, so
+    ||b - A C f|| = 0 and C f is the exact solution, although known pixels
+    inside a solid known patch are not 0 (the coarse levels see them).
+    Channel 1: an ordinary image on the same mask."""
+    W, H = 150, 90
+    m = synth.bernoulli_mask(W, H, 0.04, seed=71)
+    m[30:50, 40:70] = 1
+    f = synth.frame_image(W, H, 2, seed=72)
+    f[0][m != 0] = 0.0
+    f[0][31:49, 41:69] = 200.0  # the patch's interior: every neighbour is known
+    return np.ascontiguousarray(f), m
+
+
+@pytest.mark.parametrize("sched", ["RFMG", "FMG", "MULTILEVEL", "SINGLE", "CG"])
+def test_zero_reference_residual_returns_c_f(sched):
+    """The relative residual's denominator is 0 for channel 0: the solve
+    returns C f there (the exact solution, rel-res 0) and channel 1 as
+    usual; from a warm guess too."""
+    f, m = _zero_reference_residual_problem()
+    k = m != 0
+    exact = np.where(k, f[0], 0.0).astype(np.float32)
+    ref1 = oracle.solve_pcg(f[1:2].astype(np.float64), m)
+    assert np.array_equal(oracle.solve_pcg(f[0:1].astype(np.float64), m)[0], exact)
+    runs = [binding.make_opts(schedule=getattr(binding, "SCHED_" + sched))]
+    if sched == "RFMG":
+        runs.append(binding.make_opts(schedule=binding.SCHED_WARM))
+        runs.append(binding.make_opts(precision=binding.PREC_FP16))
+    tol = 1e-5 if sched == "CG" else TOL  # float32 CG stalls near 1e-6
+    for opts in runs:
+        out = np.random.default_rng(5).uniform(0, 255, f.shape).astype(np.float32)
+        _, st, stats = binding.inpaint_solve_ex(f, m, tol, out=out, opts=opts)
+        assert st == binding.OK, (sched, st)
+        assert np.array_equal(out[0], exact), sched
+        assert stats["rel_res"] <= tol
+        _check(out[1:2], f[1:2], m, ref=ref1, rr_tol=tol)

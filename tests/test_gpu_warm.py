@@ -165,3 +165,21 @@ def test_non_finite_guess_diverges_alone():
     for ch in (0, 2):
         assert np.array_equal(u[ch], u_ok[ch]), ch
         assert np.abs(u[ch].astype(np.float64) - ref[ch]).max() <= 0.5
+
+
+@pytest.mark.parametrize("W,H,C,dens,seed", [
+    (1, 100, 1, 0.1, 61), (100, 1, 1, 0.1, 62), (2, 2, 1, 0.5, 63), (33, 33, 3, 0.04, 64),
+    (129, 257, 4, 0.02, 65), (1000, 3, 1, 0.05, 66), (511, 383, 3, 0.04, 67),
+])
+def test_warm_start_on_ragged_sizes(W, H, C, dens, seed):
+    """Strips one pixel wide, a 2x2 image, single-level and multi-level
+    problems, four channels: from a random guess every channel meets the gate."""
+    f = synth.frame_image(W, H, C, seed=seed)
+    m = synth.bernoulli_mask(W, H, dens, seed=seed + 100)
+    if not m.any():
+        m.ravel()[0] = 1
+    ref = oracle.solve_pcg(f.astype(np.float64), m)
+    guess = np.random.default_rng(seed).uniform(0, 255, f.shape).astype(np.float32)
+    u, st, _ = _warm(f, m, guess)
+    assert st == binding.OK
+    _check(u, f, m, ref)
