@@ -423,3 +423,22 @@ def test_zero_reference_residual_returns_c_f(sched):
         assert np.array_equal(out[0], exact), sched
         assert stats["rel_res"] <= tol
         _check(out[1:2], f[1:2], m, ref=ref1, rr_tol=tol)
+
+
+@pytest.mark.parametrize("prec", [binding.PREC_FP32, binding.PREC_FP16, binding.PREC_BF16])
+def test_single_known_pixel_gives_a_constant(prec):
+    """One known pixel: the solution is that value everywhere (the constant is
+    discrete-harmonic under reflecting boundaries), a purely global,
+    low-frequency error for the coarse levels to remove."""
+    W, H = 301, 203
+    vals = np.array([137.5, 3.25, 250.0], np.float32)
+    f = np.zeros((3, H, W), np.float32)
+    m = np.zeros((H, W), np.uint8)
+    m[150, 40] = 1
+    f[:, 150, 40] = vals
+    out, st, stats = _solve(f, m, precision=prec)
+    assert st == binding.OK
+    for ch in range(3):
+        assert np.abs(out[ch].astype(np.float64) - vals[ch]).max() <= 0.5, (ch, prec)
+    rr = oracle.rel_res(out.astype(np.float64), f.astype(np.float64), m)
+    assert np.all(rr <= TOL), rr
