@@ -135,3 +135,29 @@ def test_destroy_finishes_submitted_requests():
     for (f, m), o in zip(reqs, outs):
         solo, _, _ = binding.inpaint_solve_ex(f, m, TOL)
         assert np.array_equal(o, solo)
+
+
+def test_served_zero_reference_residual_request():
+    """A request whose first channel has ||b - A C f|| = 0 (every known pixel
+    next to an unknown one is 0) among ordinary ones: that channel comes back
+    as C f, the exact solution, and every request as its solo solve."""
+    W, H = 150, 90
+    m = synth.bernoulli_mask(W, H, 0.04, seed=71)
+    m[30:50, 40:70] = 1
+    f = synth.frame_image(W, H, 2, seed=72)
+    f[0][m != 0] = 0.0
+    f[0][31:49, 41:69] = 200.0
+    f = np.ascontiguousarray(f)
+    reqs = _reqs(4, seed=3) + [(f, m)] + _reqs(3, seed=4)
+    srv = binding.inpaint_server_create(max_batch=4)
+    try:
+        tickets = [binding.inpaint_server_submit(srv, g, k, tol=TOL) for g, k in reqs]
+        results = [binding.inpaint_server_wait(srv, t) for t in tickets]
+    finally:
+        binding.inpaint_server_destroy(srv)
+    for (g, k), (out, st, _) in zip(reqs, results):
+        assert st == binding.OK
+        solo, st1, _ = binding.inpaint_solve_ex(g, k, TOL)
+        assert st1 == binding.OK and np.array_equal(out, solo)
+    out = results[4][0]
+    assert np.array_equal(out[0], np.where(m != 0, f[0], 0.0).astype(np.float32))
