@@ -183,3 +183,28 @@ def test_warm_start_on_ragged_sizes(W, H, C, dens, seed):
     u, st, _ = _warm(f, m, guess)
     assert st == binding.OK
     _check(u, f, m, ref)
+
+
+def test_batched_warm_members_stopping_at_different_tests():
+    """A batch in which one member's guess is already converged (0 cycles)
+    and the others start from poor guesses: each result equals its solo warm
+    solve bit for bit."""
+    import torch
+    probs = [_problem(W=160, H=90, seed=81), _problem(W=200, H=150, seed=83), _problem(W=64, H=300, C=1, seed=85)]
+    conv, st, _ = binding.inpaint_solve_ex(probs[0][0], probs[0][1], TOL)
+    assert st == binding.OK
+    guesses = [conv, np.zeros_like(probs[1][0]), np.full_like(probs[2][0], 255.0)]
+    solo = []
+    for (f, m), g in zip(probs, guesses):
+        u, st, stats = _warm(f, m, g)
+        assert st == binding.OK
+        solo.append((u, stats["cycles"]))
+    assert solo[0][1] == 0 and solo[1][1] > 0
+    items = [(torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda(), torch.from_numpy(g.copy()).cuda())
+             for (f, m), g in zip(probs, guesses)]
+    _, st, stats = binding.inpaint_solve_batched(items, TOL, opts=binding.make_opts(schedule=WARM))
+    torch.cuda.synchronize()
+    assert st == binding.OK
+    for (_, _, o), (u, cyc), s in zip(items, solo, stats):
+        assert np.array_equal(o.cpu().numpy(), u)
+        assert s["cycles"] == cyc
