@@ -442,3 +442,19 @@ def test_single_known_pixel_gives_a_constant(prec):
         assert np.abs(out[ch].astype(np.float64) - vals[ch]).max() <= 0.5, (ch, prec)
     rr = oracle.rel_res(out.astype(np.float64), f.astype(np.float64), m)
     assert np.all(rr <= TOL), rr
+
+
+def test_any_nonzero_mask_byte_marks_a_known_pixel():
+    """The mask is read as known = (byte != 0): 1, 255 or any other nonzero
+    byte give the same result bit for bit, solo and batched."""
+    f = synth.frame_image(173, 111, 3, seed=91)
+    m = synth.bernoulli_mask(173, 111, 0.05, seed=92)
+    rng = np.random.default_rng(93)
+    m_any = np.where(m != 0, rng.integers(1, 256, m.shape), 0).astype(np.uint8)
+    base, st, _ = _solve(f, m)
+    assert st == binding.OK
+    for mm in (m * 255, m_any):
+        out, st, _ = _solve(f, np.ascontiguousarray(mm))
+        assert st == binding.OK and np.array_equal(out, base)
+    outs, st, _ = binding.inpaint_solve_batched([(f, m_any), (f, m)], TOL)
+    assert st == binding.OK and np.array_equal(outs[0], base) and np.array_equal(outs[1], base)
