@@ -458,3 +458,38 @@ def test_any_nonzero_mask_byte_marks_a_known_pixel():
         assert st == binding.OK and np.array_equal(out, base)
     outs, st, _ = binding.inpaint_solve_batched([(f, m_any), (f, m)], TOL)
     assert st == binding.OK and np.array_equal(outs[0], base) and np.array_equal(outs[1], base)
+
+
+def test_concurrent_calls_from_threads_match_sequential_ones():
+    """The entry points are thread-safe: four host threads solving at once
+    (two of them on problems of the same size, so that the cache hands out
+    separate workspaces) give the sequential results bit for bit."""
+    import threading
+    probs = [(synth.frame_image(W, H, C, seed=100 + k), synth.bernoulli_mask(W, H, 0.04, seed=110 + k))
+             for k, (W, H, C) in enumerate([(320, 180, 3), (320, 180, 3), (97, 61, 1), (640, 360, 2)])]
+    seq = []
+    for f, m in probs:
+        out, st, _ = _solve(f, m)
+        assert st == binding.OK
+        seq.append(out)
+    got = [[None] * 3 for _ in probs]
+    errors = []
+
+    def work(i):
+        try:
+            for r in range(3):
+                out, st, _ = _solve(*probs[i])
+                got[i][r] = out if st == binding.OK else None
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append((i, repr(e)))
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(len(probs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=90)
+    assert not any(t.is_alive() for t in threads), "a solving thread did not finish"
+    assert not errors, errors
+    for i, outs in enumerate(got):
+        for out in outs:
+            assert out is not None and np.array_equal(out, seq[i]), i
