@@ -493,3 +493,32 @@ def test_concurrent_calls_from_threads_match_sequential_ones():
     for i, outs in enumerate(got):
         for out in outs:
             assert out is not None and np.array_equal(out, seq[i]), i
+
+
+def test_solve_on_a_caller_stream():
+    """Work issued on the caller's stream (a torch stream at the default
+    priority), with the inputs written on that stream just before the call:
+    the results equal those on the null stream, solo, batched and without
+    allocation."""
+    import torch
+    f = synth.frame_image(256, 160, 3, seed=121)
+    m = synth.bernoulli_mask(256, 160, 0.05, seed=122)
+    base, st, _ = _solve(f, m)
+    assert st == binding.OK
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        fd = torch.from_numpy(f).cuda(non_blocking=False)
+        md = torch.from_numpy(m).cuda(non_blocking=False)
+        fd.mul_(1.0)  # pending work on s when the solve is issued
+        od = torch.empty_like(fd)
+    _, st, _ = binding.inpaint_solve_ex(fd, md, TOL, out=od, stream=s)
+    assert st == binding.OK and np.array_equal(od.cpu().numpy(), base)
+    with torch.cuda.stream(s):
+        od2 = torch.empty_like(fd)
+    outs, st, _ = binding.inpaint_solve_batched([(fd, md, od2)], TOL, stream=s)
+    assert st == binding.OK and np.array_equal(od2.cpu().numpy(), base)
+    with torch.cuda.stream(s):
+        od3 = torch.empty_like(fd)
+    _, st, _ = binding.inpaint_solve_noalloc(fd, md, TOL, out=od3, stream=s)
+    s.synchronize()
+    assert st == binding.OK and np.array_equal(od3.cpu().numpy(), base)
