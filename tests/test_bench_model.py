@@ -50,3 +50,11 @@ def test_algorithmic_bytes_cover_every_kernel_class():
     for cls in ("block_solve", "update", "prolong", "restrict", "residual", "stage", "pyramid", "output",
                 "coarse"):
         assert bench.algorithmic_bytes(cls, 3840, 2160, 3) > 3840 * 2160
+
+
+def test_more_than_one_gpu_is_refused_before_any_work():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
